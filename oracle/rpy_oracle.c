@@ -1,0 +1,922 @@
+/*
+ * rpy_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, obviously-correct FP64 CPU reference for the Rotne-Prager-
+ * Yamakawa (RPY) mobility matrix-vector product of Guan et al., "RPYFMM:
+ * Parallel adaptive fast multipole method for Rotne-Prager-Yamakawa tensor"
+ * (arXiv:1711.02976).  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code, header, table
+ * or helper with the HIP library in paper_1711_02976_amd/.
+ *
+ * Contents, each citing the passage it follows:
+ *   O1  orc_rpy_block / orc_rpy_direct   -- the RPY tensor (Sec. 1, the three
+ *       RPY block equations) summed directly, O(N^2).
+ *   O2  orc_far_four_laplace            -- the far-field RPY sum written as the
+ *       four Laplace potentials L1..L4 and L_C (Sec. 2, definitions of L1..L4,
+ *       L_C and eq. (2.8)), brute force over pairs with r >= 2a.
+ *   O3  orc_tree_*                      -- adaptive octree with refinement limit
+ *       (Sec. 4.2, "threshold") and the adaptive-FMM interaction lists
+ *       U, V, W, X (+ O for overlapping pairs outside U), by brute force over
+ *       boxes from their definitions.
+ *   O4  orc_fmm                          -- the four-Laplace adaptive FMM with
+ *       expansions in the paper's normalisation (Sec. 2, multipole/local
+ *       expansion forms and Y_n^m), derivatives at targets by Theorem 1 (M)
+ *       and Theorem 2 (L), and assembly by eq. (2.8).
+ *
+ * Readings of the paper taken here (each is pinned by a CPU test):
+ *   - overlap block (r < 2a): prefactor 1/(6 pi eta a), dyad (3/(32a)) d d^T / r
+ *     (the printed 1/(6 pi eta r_ij) prefactor is not dimensionally consistent);
+ *   - eq. (2.8): the L_C term enters with a minus sign, -C2 grad L_C;
+ *   - Theorem 2: s1 sums over n, and s6 carries a leading minus sign;
+ *   - P_n^m carries the Condon-Shortley phase (-1)^m;
+ *   - kB*T = 1 (mobility), one radius a and viscosity eta for all beads;
+ *   - the fourth charge is centred on the box that owns each expansion,
+ *     q4 = F.(r - c), an exact rewriting of L4 that avoids cancellation.
+ * M2M, M2L and L2L are not printed in the paper; they are derived here from
+ * the addition theorem in the paper's normalisation (parity pinned by
+ * exactness tests and convergence to O1, not by a printed value).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <complex.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORC_PI 3.14159265358979323846
+
+static void set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ O1 --- */
+
+/* The 3x3 RPY mobility block for separation d = r_i - r_j (Sec. 1, RPY block
+ * equations, with kB*T = 1).  d = 0 gives the self block I/(6 pi eta a), which
+ * is also the r -> 0+ limit of the overlap block (coincident distinct beads).
+ * M is even in d, so the paper's r_ij = r_j - r_i convention does not matter. */
+void orc_rpy_block(const double d[3], double a, double eta, double out[9]) {
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double r = sqrt(r2);
+  double A, B;
+  if (r == 0.0) {
+    A = 1.0 / (6.0 * ORC_PI * eta * a);
+    B = 0.0;
+  } else if (r >= 2.0 * a) {
+    double c = 1.0 / (8.0 * ORC_PI * eta * r);
+    A = c * (1.0 + 2.0 * a * a / (3.0 * r2));
+    B = c * (1.0 - 2.0 * a * a / r2) / r2;
+  } else {
+    double c = 1.0 / (6.0 * ORC_PI * eta * a);
+    A = c * (1.0 - 9.0 * r / (32.0 * a));
+    B = c * (3.0 / (32.0 * a)) / r;
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[3 * i + j] = (i == j ? A : 0.0) + B * d[i] * d[j];
+}
+
+/* Neumaier-compensated accumulation. */
+static inline void neu_add(double* s, double* c, double t) {
+  double u = *s + t;
+  if (fabs(*s) >= fabs(t)) *c += (*s - u) + t;
+  else *c += (t - u) + *s;
+  *s = u;
+}
+
+/* u_i = sum_j M(r_i - r_j) F_j over all beads j, self included (Sec. 1).
+ * pos [n][3]; F [nrhs][n][3]; tgt (nullable) lists the nt target indices;
+ * out [nrhs][nt][3].  Sums are Neumaier-compensated FP64. */
+void orc_rpy_direct(int64_t n, const double* pos, int nrhs, const double* F, double a,
+                    double eta, int64_t nt, const int64_t* tgt, double* out, int nthreads) {
+  set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t ti = 0; ti < nt; ++ti) {
+    int64_t i = tgt ? tgt[ti] : ti;
+    for (int r = 0; r < nrhs; ++r) {
+      double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+      const double* Fr = F + (size_t)r * n * 3;
+      for (int64_t j = 0; j < n; ++j) {
+        double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                       pos[3 * i + 2] - pos[3 * j + 2]};
+        double M[9];
+        orc_rpy_block(d, a, eta, M);
+        for (int k = 0; k < 3; ++k)
+          neu_add(&s[k], &c[k],
+                  M[3 * k] * Fr[3 * j] + M[3 * k + 1] * Fr[3 * j + 1] + M[3 * k + 2] * Fr[3 * j + 2]);
+      }
+      for (int k = 0; k < 3; ++k) out[((size_t)r * nt + ti) * 3 + k] = s[k] + c[k];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ O2 --- */
+
+/* Far-field RPY at each target written through the four Laplace potentials
+ * (Sec. 2: L1..L3 = sum F^k/|r_i-r_j|, L4 = sum F.r_j/|r_i-r_j|, L_C =
+ * d_x L1 + d_y L2 + d_z L3, assembled by eq. (2.8) with the -C2 reading).
+ * The sums run over all j != i with |r_i - r_j| >= 2a.  If centers is NULL
+ * the fourth charge uses the global origin exactly as printed; otherwise
+ * q4 = F_j.(r_j - c_i) and x_i - c_i replaces x_i, an exact rewriting.
+ * out [n][3] for the single right-hand side F [n][3]. */
+void orc_far_four_laplace(int64_t n, const double* pos, const double* F, double a, double eta,
+                          const double* centers, double* out, int nthreads) {
+  set_threads(nthreads);
+  const double C1 = 1.0 / (8.0 * ORC_PI * eta);
+  const double C2 = a * a / (12.0 * ORC_PI * eta);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t i = 0; i < n; ++i) {
+    double c[3] = {0, 0, 0};
+    if (centers) for (int k = 0; k < 3; ++k) c[k] = centers[3 * i + k];
+    double L[4] = {0}, G[4][3] = {{0}}, H[3][3][3] = {{{0}}};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3], r2 = 0;
+      for (int k = 0; k < 3; ++k) { d[k] = pos[3 * i + k] - pos[3 * j + k]; r2 += d[k] * d[k]; }
+      double r = sqrt(r2);
+      if (r < 2.0 * a) continue;
+      double q[4] = {F[3 * j], F[3 * j + 1], F[3 * j + 2], 0};
+      for (int k = 0; k < 3; ++k) q[3] += F[3 * j + k] * (pos[3 * j + k] - c[k]);
+      double ir = 1.0 / r, ir3 = ir * ir * ir, ir5 = ir3 * ir * ir;
+      for (int s = 0; s < 4; ++s) {
+        L[s] += q[s] * ir;
+        for (int k = 0; k < 3; ++k) G[s][k] += -q[s] * d[k] * ir3;
+      }
+      for (int s = 0; s < 3; ++s)
+        for (int u = 0; u < 3; ++u)
+          for (int v = 0; v < 3; ++v)
+            H[s][u][v] += q[s] * (3.0 * d[u] * d[v] - (u == v ? r2 : 0.0)) * ir5;
+    }
+    for (int k = 0; k < 3; ++k) {
+      double xs = 0, gLc = 0;
+      for (int s = 0; s < 3; ++s) {
+        xs += (pos[3 * i + s] - c[s]) * G[s][k];
+        gLc += H[s][k][s];
+      }
+      out[3 * i + k] = C1 * L[k] - C1 * xs + C1 * G[3][k] - C2 * gLc;
+    }
+  }
+}
+
+/* --------------------------------------------- spherical harmonics ------ */
+
+#define IDX(n, m) ((n) * ((n) + 1) / 2 + (m))
+
+/* Associated Legendre P_n^m(x), 0 <= m <= n <= P, with the Condon-Shortley
+ * phase, by the standard three-term recurrence in n. */
+void orc_legendre(int P, double x, double* out) {
+  double sx = sqrt(fmax(0.0, 1.0 - x * x));
+  double pmm = 1.0;
+  for (int m = 0; m <= P; ++m) {
+    if (m > 0) pmm *= -(2.0 * m - 1.0) * sx;
+    out[IDX(m, m)] = pmm;
+    if (m + 1 <= P) out[IDX(m + 1, m)] = x * (2.0 * m + 1.0) * pmm;
+    for (int n = m + 2; n <= P; ++n)
+      out[IDX(n, m)] = ((2.0 * n - 1.0) * x * out[IDX(n - 1, m)] - (n + m - 1.0) * out[IDX(n - 2, m)]) /
+                       (double)(n - m);
+  }
+}
+
+static double fact(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= (double)i;
+  return f;
+}
+
+/* Y_n^m(theta, phi) = sqrt((n-|m|)!/(n+|m|)!) P_n^|m|(cos theta) e^{i m phi}
+ * (Sec. 2, the paper's normalisation), stored for 0 <= m <= n <= P;
+ * Y_n^{-m} is the complex conjugate. */
+void orc_ynm(int P, double theta, double phi, double* re, double* im) {
+  double* Pl = malloc(sizeof(double) * (P + 1) * (P + 2) / 2);
+  orc_legendre(P, cos(theta), Pl);
+  for (int n = 0; n <= P; ++n)
+    for (int m = 0; m <= n; ++m) {
+      double c = sqrt(fact(n - m) / fact(n + m)) * Pl[IDX(n, m)];
+      re[IDX(n, m)] = c * cos(m * phi);
+      im[IDX(n, m)] = c * sin(m * phi);
+    }
+  free(Pl);
+}
+
+static void to_sph(const double v[3], double* r, double* th, double* ph) {
+  *r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  *th = (*r > 0) ? acos(fmax(-1.0, fmin(1.0, v[2] / *r))) : 0.0;
+  *ph = atan2(v[1], v[0]);
+}
+
+/* ------------------------------------------------------------------ O3 --- */
+
+#define ORC_KBITS 21
+
+typedef struct {
+  int64_t n;
+  int leaf_size, max_depth;
+  double a;
+  double lo[3], side;
+  uint64_t* key;     /* sorted keys */
+  int64_t* perm;     /* perm[k] = caller index of the k-th sorted bead */
+  int64_t nbox, cap;
+  int* level;
+  int64_t* anchor;   /* [nbox][3] */
+  int64_t *begin, *end, *parent, *child_begin;
+  int* nchild;
+  int64_t* off[5];   /* lists U, V, W, X, O in CSR, entries sorted by box id */
+  int64_t* ent[5];
+  int64_t nent[5];
+} orc_tree;
+
+static uint64_t spread3(uint64_t v) {
+  uint64_t k = 0;
+  for (int b = 0; b < ORC_KBITS; ++b) k |= ((v >> b) & 1ull) << (3 * b);
+  return k;
+}
+
+typedef struct { uint64_t key; int64_t idx; } kv_t;
+static int kv_cmp(const void* A, const void* B) {
+  const kv_t* x = A; const kv_t* y = B;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+static void push_box(orc_tree* t, int lev, const int64_t anc[3], int64_t b, int64_t e, int64_t par) {
+  if (t->nbox == t->cap) {
+    t->cap = t->cap ? 2 * t->cap : 64;
+    t->level = realloc(t->level, sizeof(int) * t->cap);
+    t->anchor = realloc(t->anchor, sizeof(int64_t) * 3 * t->cap);
+    t->begin = realloc(t->begin, sizeof(int64_t) * t->cap);
+    t->end = realloc(t->end, sizeof(int64_t) * t->cap);
+    t->parent = realloc(t->parent, sizeof(int64_t) * t->cap);
+    t->child_begin = realloc(t->child_begin, sizeof(int64_t) * t->cap);
+    t->nchild = realloc(t->nchild, sizeof(int) * t->cap);
+  }
+  int64_t i = t->nbox++;
+  t->level[i] = lev;
+  for (int k = 0; k < 3; ++k) t->anchor[3 * i + k] = anc[k];
+  t->begin[i] = b; t->end[i] = e; t->parent[i] = par;
+  t->child_begin[i] = -1; t->nchild[i] = 0;
+}
+
+/* Two boxes are adjacent iff their closed cubes intersect (touching or
+ * overlapping), tested in integer units of the finer level. */
+static int adjacent(const orc_tree* t, int64_t A, int64_t B) {
+  int L = t->level[A] > t->level[B] ? t->level[A] : t->level[B];
+  int sa = L - t->level[A], sb = L - t->level[B];
+  for (int k = 0; k < 3; ++k) {
+    int64_t alo = t->anchor[3 * A + k] << sa, ahi = (t->anchor[3 * A + k] + 1) << sa;
+    int64_t blo = t->anchor[3 * B + k] << sb, bhi = (t->anchor[3 * B + k] + 1) << sb;
+    if (alo > bhi || blo > ahi) return 0;
+  }
+  return 1;
+}
+
+/* Closest distance between two boxes is below 2a (exact integer gaps at the
+ * finer level, one FP64 threshold computed as (2a)/(side 2^-L)). */
+static int near_2a(const orc_tree* t, int64_t A, int64_t B) {
+  int L = t->level[A] > t->level[B] ? t->level[A] : t->level[B];
+  int sa = L - t->level[A], sb = L - t->level[B];
+  int64_t g2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    int64_t alo = t->anchor[3 * A + k] << sa, ahi = (t->anchor[3 * A + k] + 1) << sa;
+    int64_t blo = t->anchor[3 * B + k] << sb, bhi = (t->anchor[3 * B + k] + 1) << sb;
+    int64_t g = 0;
+    if (blo > ahi) g = blo - ahi;
+    if (alo > bhi) g = alo - bhi;
+    g2 += g * g;
+  }
+  double unit = ldexp(t->side, -L);
+  double thr = (2.0 * t->a) / unit;
+  return (double)g2 < thr * thr;
+}
+
+static int is_leaf(const orc_tree* t, int64_t b) { return t->nchild[b] == 0; }
+
+/* Build the adaptive octree (Sec. 4.2: a box is refined while it holds more
+ * than `threshold` beads) and all interaction lists.
+ *   bounding cube: lo = per-axis minimum, side = largest extent (1 if 0);
+ *   quantisation:  k = min(floor((x - lo) * (2^21 / side)), 2^21 - 1);
+ *   Morton key:    bit b of k_x, k_y, k_z at key bits 3b, 3b+1, 3b+2;
+ *   order:         stable by (key, caller index);
+ *   refinement:    split while count > leaf_size and level < max_depth,
+ *                  empty children are dropped, boxes numbered by (level, key). */
+orc_tree* orc_tree_build(int64_t n, const double* pos, int leaf_size, int max_depth, double a) {
+  orc_tree* t = calloc(1, sizeof(orc_tree));
+  t->n = n; t->leaf_size = leaf_size; t->max_depth = max_depth; t->a = a;
+  if (n <= 0) return t;
+  double hi[3];
+  for (int k = 0; k < 3; ++k) { t->lo[k] = pos[k]; hi[k] = pos[k]; }
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      if (pos[3 * i + k] < t->lo[k]) t->lo[k] = pos[3 * i + k];
+      if (pos[3 * i + k] > hi[k]) hi[k] = pos[3 * i + k];
+    }
+  t->side = 0;
+  for (int k = 0; k < 3; ++k) if (hi[k] - t->lo[k] > t->side) t->side = hi[k] - t->lo[k];
+  if (t->side == 0) t->side = 1.0;
+  double scale = 2097152.0 / t->side;
+  kv_t* kv = malloc(sizeof(kv_t) * n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t key = 0;
+    for (int k = 0; k < 3; ++k) {
+      volatile double dx = pos[3 * i + k] - t->lo[k];
+      volatile double s = dx * scale;
+      double f = floor(s);
+      int64_t q = (int64_t)f;
+      if (q > 2097151) q = 2097151;
+      if (q < 0) q = 0;
+      key |= spread3((uint64_t)q) << k;
+    }
+    kv[i].key = key; kv[i].idx = i;
+  }
+  qsort(kv, n, sizeof(kv_t), kv_cmp);
+  t->key = malloc(sizeof(uint64_t) * n);
+  t->perm = malloc(sizeof(int64_t) * n);
+  for (int64_t i = 0; i < n; ++i) { t->key[i] = kv[i].key; t->perm[i] = kv[i].idx; }
+  free(kv);
+
+  int64_t zero[3] = {0, 0, 0};
+  push_box(t, 0, zero, 0, n, -1);
+  for (int64_t b = 0; b < t->nbox; ++b) { /* breadth-first: (level, key) order */
+    int lev = t->level[b];
+    if (t->end[b] - t->begin[b] <= leaf_size || lev >= max_depth) continue;
+    int shift = 3 * (ORC_KBITS - lev - 1);
+    int64_t i = t->begin[b];
+    for (int o = 0; o < 8; ++o) {
+      int64_t j = i;
+      while (j < t->end[b] && (int)((t->key[j] >> shift) & 7u) == o) ++j;
+      if (j > i) {
+        int64_t anc[3];
+        for (int k = 0; k < 3; ++k) anc[k] = 2 * t->anchor[3 * b + k] + ((o >> k) & 1);
+        if (t->child_begin[b] < 0) t->child_begin[b] = t->nbox;
+        t->nchild[b]++;
+        push_box(t, lev + 1, anc, i, j, b);
+      }
+      i = j;
+    }
+  }
+
+  /* Lists from their definitions, by brute force over boxes. */
+  int64_t B = t->nbox;
+  for (int L = 0; L < 5; ++L) { t->off[L] = calloc(B + 1, sizeof(int64_t)); t->nent[L] = 0; }
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1)
+      for (int L = 0; L < 5; ++L) t->ent[L] = malloc(sizeof(int64_t) * (t->off[L][B] + 1));
+    for (int64_t b = 0; b < B; ++b) {
+      int64_t cnt[5] = {0};
+      int64_t* w[5];
+      for (int L = 0; L < 5; ++L) w[L] = pass ? t->ent[L] + t->off[L][b] : NULL;
+#define PUT(L) do { if (pass) w[L][cnt[L]] = c; cnt[L]++; } while (0)
+      for (int64_t c = 0; c < B; ++c) {
+        int adj = adjacent(t, b, c);
+        /* U(b): b a leaf, c any adjacent leaf (b itself included). */
+        if (is_leaf(t, b) && is_leaf(t, c) && adj) { PUT(0); }
+        /* V(b): same level, parents adjacent, c not adjacent to b. */
+        if (t->level[c] == t->level[b] && t->level[b] >= 1 &&
+            adjacent(t, t->parent[b], t->parent[c]) && !adj) { PUT(1); }
+        /* W(b): b a leaf; c finer than b, c's parent adjacent to b, c not. */
+        if (is_leaf(t, b) && t->level[c] > t->level[b] && !adj && adjacent(t, t->parent[c], b)) {
+          PUT(2);
+        }
+        /* X(b) = {c : b in W(c)}: c a leaf coarser than b, adjacent to b's
+           parent, not adjacent to b. */
+        if (is_leaf(t, c) && t->level[b] > t->level[c] && !adj && adjacent(t, t->parent[b], c)) {
+          PUT(3);
+        }
+        /* O(b): b a leaf; c a leaf outside U(b) closer than 2a. */
+        if (is_leaf(t, b) && is_leaf(t, c) && !adj && near_2a(t, b, c)) {
+          PUT(4);
+        }
+      }
+#undef PUT
+      if (!pass) for (int L = 0; L < 5; ++L) t->off[L][b + 1] = t->off[L][b] + cnt[L];
+    }
+  }
+  for (int L = 0; L < 5; ++L) t->nent[L] = t->off[L][B];
+  return t;
+}
+
+void orc_tree_free(orc_tree* t) {
+  if (!t) return;
+  free(t->key); free(t->perm); free(t->level); free(t->anchor); free(t->begin); free(t->end);
+  free(t->parent); free(t->child_begin); free(t->nchild);
+  for (int L = 0; L < 5; ++L) { free(t->off[L]); free(t->ent[L]); }
+  free(t);
+}
+
+/* sizes: [nbox, |U|, |V|, |W|, |X|, |O|]; geom: [lo0, lo1, lo2, side] */
+void orc_tree_sizes(const orc_tree* t, int64_t* sizes, double* geom) {
+  sizes[0] = t->nbox;
+  for (int L = 0; L < 5; ++L) sizes[1 + L] = t->nent[L];
+  for (int k = 0; k < 3; ++k) geom[k] = t->lo[k];
+  geom[3] = t->side;
+}
+
+/* Copy the tree out.  boxes [nbox][8] = level, ax, ay, az, begin, end,
+ * parent, child_begin (-1 for leaves); offsets [5][nbox+1]; entries are the
+ * five lists concatenated in the order U, V, W, X, O. */
+void orc_tree_export(const orc_tree* t, uint64_t* keys, int64_t* perm, int64_t* boxes,
+                     int64_t* offsets, int64_t* entries) {
+  if (keys) memcpy(keys, t->key, sizeof(uint64_t) * t->n);
+  if (perm) memcpy(perm, t->perm, sizeof(int64_t) * t->n);
+  for (int64_t b = 0; b < t->nbox; ++b) {
+    int64_t* o = boxes + 8 * b;
+    o[0] = t->level[b]; o[1] = t->anchor[3 * b]; o[2] = t->anchor[3 * b + 1];
+    o[3] = t->anchor[3 * b + 2]; o[4] = t->begin[b]; o[5] = t->end[b]; o[6] = t->parent[b];
+    o[7] = t->child_begin[b];
+  }
+  int64_t e = 0;
+  for (int L = 0; L < 5; ++L) {
+    memcpy(offsets + (size_t)L * (t->nbox + 1), t->off[L], sizeof(int64_t) * (t->nbox + 1));
+    memcpy(entries + e, t->ent[L], sizeof(int64_t) * t->nent[L]);
+    e += t->nent[L];
+  }
+}
+
+/* ------------------------------------------------------------------ O4 --- */
+
+/* Coefficient tables for 0 <= m <= n <= p live at IDX(n, m); negative orders
+ * follow from conjugate symmetry (Sec. 2: M_n^{-m} = conj(M_n^m)). */
+static inline cplx coef(const cplx* C, int n, int m) {
+  return m >= 0 ? C[IDX(n, m)] : conj(C[IDX(n, -m)]);
+}
+static inline double sgnfac(int m) { return (m >= 0 || (m & 1) == 0) ? 1.0 : -1.0; }
+
+typedef struct {
+  int p, P2;         /* order and 2p+2 (highest harmonic degree needed) */
+  double* s;         /* s[n][m] = sqrt((n-m)!(n+m)!) at IDX(n,m), n <= P2 */
+} orc_ops;
+
+static double sfac(const orc_ops* o, int n, int m) { return o->s[IDX(n, m < 0 ? -m : m)]; }
+
+/* Y_n^m(v) rho^pw for 0 <= m <= n <= P, the building block of every operator. */
+static void harmonics(int P, const double v[3], cplx* Y, double* rho) {
+  double r, th, ph;
+  to_sph(v, &r, &th, &ph);
+  double* re = malloc(sizeof(double) * (P + 1) * (P + 2) / 2);
+  double* im = malloc(sizeof(double) * (P + 1) * (P + 2) / 2);
+  orc_ynm(P, th, ph, re, im);
+  for (int i = 0; i < (P + 1) * (P + 2) / 2; ++i) Y[i] = re[i] + I * im[i];
+  free(re); free(im);
+  *rho = r;
+}
+static inline cplx Yget(const cplx* Y, int n, int m) {
+  return m >= 0 ? Y[IDX(n, m)] : conj(Y[IDX(n, -m)]);
+}
+
+/* S->M: M_n^m = sum_j q_j rho_j^n Y_n^{-m}(alpha_j, beta_j) about c (Sec. 2,
+ * multipole form; expansion of 1/|x-y| by the addition theorem). */
+static void p2m(const orc_ops* o, int64_t nb, const double* pos, const double* q, const double c[3],
+                cplx* M) {
+  int p = o->p;
+  cplx* Y = malloc(sizeof(cplx) * IDX(p + 1, 0));
+  memset(M, 0, sizeof(cplx) * IDX(p + 1, 0));
+  for (int64_t j = 0; j < nb; ++j) {
+    double v[3] = {pos[3 * j] - c[0], pos[3 * j + 1] - c[1], pos[3 * j + 2] - c[2]}, rho;
+    harmonics(p, v, Y, &rho);
+    for (int n = 0; n <= p; ++n)
+      for (int m = 0; m <= n; ++m) M[IDX(n, m)] += q[j] * pow(rho, n) * conj(Y[IDX(n, m)]);
+  }
+  free(Y);
+}
+
+/* S->L: L_n^m = sum_j q_j Y_n^{-m}(alpha_j, beta_j) / rho_j^{n+1} about c. */
+static void p2l(const orc_ops* o, int64_t nb, const double* pos, const double* q, const double c[3],
+                cplx* L) {
+  int p = o->p;
+  cplx* Y = malloc(sizeof(cplx) * IDX(p + 1, 0));
+  for (int64_t j = 0; j < nb; ++j) {
+    double v[3] = {pos[3 * j] - c[0], pos[3 * j + 1] - c[1], pos[3 * j + 2] - c[2]}, rho;
+    harmonics(p, v, Y, &rho);
+    for (int n = 0; n <= p; ++n)
+      for (int m = 0; m <= n; ++m) L[IDX(n, m)] += q[j] * conj(Y[IDX(n, m)]) / pow(rho, n + 1);
+  }
+  free(Y);
+}
+
+/* M->M: child expansion about cc moved to the parent centre cp:
+ * M'_n^m = sum_{k<=n,l} M_k^l e(m)e(l)e(m-l) s_n^m/(s_k^l s_{n-k}^{m-l})
+ *          rho^{n-k} Y_{n-k}^{l-m}(cc - cp),  e(mu) = (-1)^mu for mu < 0.
+ * Applied to nd expansions stored T apart; results are added to out. */
+static void m2m(const orc_ops* o, int nd, const cplx* M, const double cc[3], const double cp[3], cplx* out) {
+  int p = o->p, T = IDX(p + 1, 0);
+  double d[3] = {cc[0] - cp[0], cc[1] - cp[1], cc[2] - cp[2]}, rho;
+  cplx* Y = malloc(sizeof(cplx) * T);
+  double* rp = malloc(sizeof(double) * (p + 1));
+  harmonics(p, d, Y, &rho);
+  for (int j = 0; j <= p; ++j) rp[j] = pow(rho, j);
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m)
+      for (int k = 0; k <= n; ++k)
+        for (int l = -k; l <= k; ++l) {
+          int j = n - k, mu = m - l;
+          if (mu > j || mu < -j) continue;
+          double f = sgnfac(m) * sgnfac(l) * sgnfac(mu) * sfac(o, n, m) / (sfac(o, k, l) * sfac(o, j, mu));
+          cplx g = f * rp[j] * Yget(Y, j, -mu);
+          for (int s = 0; s < nd; ++s) out[s * T + IDX(n, m)] += coef(M + s * T, k, l) * g;
+        }
+  free(Y); free(rp);
+}
+
+/* M->L: multipole about cs to a local expansion about ct, t = cs - ct:
+ * L_k^l = sum_{n,m} M_n^m (-1)^{n+l} e(l)e(m)e(m-l) s_{n+k}^{m-l}/(s_k^l s_n^m)
+ *         Y_{n+k}^{m-l}(t) / rho^{n+k+1}. */
+static void m2l(const orc_ops* o, int nd, const cplx* M, const double cs[3], const double ct[3], cplx* out) {
+  int p = o->p, T = IDX(p + 1, 0);
+  double t[3] = {cs[0] - ct[0], cs[1] - ct[1], cs[2] - ct[2]}, rho;
+  cplx* Y = malloc(sizeof(cplx) * IDX(2 * p + 1, 0));
+  double* ip = malloc(sizeof(double) * (2 * p + 2));
+  harmonics(2 * p, t, Y, &rho);
+  for (int j = 0; j <= 2 * p + 1; ++j) ip[j] = 1.0 / pow(rho, j);
+  for (int k = 0; k <= p; ++k)
+    for (int l = 0; l <= k; ++l)
+      for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+          double f = (((n + l) & 1) ? -1.0 : 1.0) * sgnfac(l) * sgnfac(m) * sgnfac(m - l) *
+                     sfac(o, n + k, m - l) / (sfac(o, k, l) * sfac(o, n, m));
+          cplx g = f * Yget(Y, n + k, m - l) * ip[n + k + 1];
+          for (int s = 0; s < nd; ++s) out[s * T + IDX(k, l)] += coef(M + s * T, n, m) * g;
+        }
+  free(Y); free(ip);
+}
+
+/* L->L: parent expansion about cp shifted to the child centre cc:
+ * L'_k^l = sum_{n>=k,m} L_n^m e(l)e(m)e(m-l) s_n^m/(s_k^l s_{n-k}^{m-l})
+ *          rho^{n-k} Y_{n-k}^{m-l}(cc - cp). */
+static void l2l(const orc_ops* o, int nd, const cplx* L, const double cp[3], const double cc[3], cplx* out) {
+  int p = o->p, T = IDX(p + 1, 0);
+  double d[3] = {cc[0] - cp[0], cc[1] - cp[1], cc[2] - cp[2]}, rho;
+  cplx* Y = malloc(sizeof(cplx) * T);
+  double* rp = malloc(sizeof(double) * (p + 1));
+  harmonics(p, d, Y, &rho);
+  for (int j = 0; j <= p; ++j) rp[j] = pow(rho, j);
+  for (int k = 0; k <= p; ++k)
+    for (int l = 0; l <= k; ++l)
+      for (int n = k; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+          int j = n - k, mu = m - l;
+          if (mu > j || mu < -j) continue;
+          double f = sgnfac(l) * sgnfac(m) * sgnfac(mu) * sfac(o, n, m) / (sfac(o, k, l) * sfac(o, j, mu));
+          cplx g = f * rp[j] * Yget(Y, j, mu);
+          for (int s = 0; s < nd; ++s) out[s * T + IDX(k, l)] += coef(L + s * T, n, m) * g;
+        }
+  free(Y); free(rp);
+}
+
+/* The fourth charge of an expansion formed about c0, re-expressed for the
+ * centre c1: F.(r - c1) = F.(r - c0) + F.(c0 - c1), so by linearity
+ * E4' = E4 + sum_k (c0 - c1)_k E_k.  E holds the four densities T apart. */
+static void recentre(int T, cplx* E, const double c0[3], const double c1[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double w = c0[k] - c1[k];
+    for (int i = 0; i < T; ++i) E[3 * T + i] += w * E[k * T + i];
+  }
+}
+
+/* Value, gradient and Hessian of a real potential from the complex
+ * derivatives (Sec. 2, extraction of d_x ... d_zz from nabla_0, nabla_+). */
+typedef struct { double v, g[3], h[3][3]; } vgh_t;
+static void extract(double val, double d0, cplx dp, cplx dpd0, cplx dpdp, double d0d0, vgh_t* out) {
+  out->v += val;
+  out->g[0] += creal(dp); out->g[1] += cimag(dp); out->g[2] += d0;
+  double hxx = creal(dpdp - d0d0) / 2, hyy = creal(-dpdp - d0d0) / 2, hzz = d0d0;
+  double hxy = cimag(dpdp) / 2, hxz = creal(dpd0), hyz = cimag(dpd0);
+  out->h[0][0] += hxx; out->h[1][1] += hyy; out->h[2][2] += hzz;
+  out->h[0][1] += hxy; out->h[1][0] += hxy;
+  out->h[0][2] += hxz; out->h[2][0] += hxz;
+  out->h[1][2] += hyz; out->h[2][1] += hyz;
+}
+
+/* M->T with Theorem 1: value, nabla_0, nabla_+, nabla_+ nabla_0,
+ * nabla_+ nabla_+, nabla_0 nabla_0 of a multipole expansion at v = x - c. */
+static void m2t(const orc_ops* o, const cplx* M, const double v[3], vgh_t* out) {
+  int p = o->p;
+  double r, th, ph;
+  to_sph(v, &r, &th, &ph);
+  double* Pl = malloc(sizeof(double) * IDX(p + 3, 0));
+  orc_legendre(p + 2, cos(th), Pl);
+#define PL(n, m) (((m) < 0 || (m) > (n)) ? 0.0 : Pl[IDX(n, m)])
+#define E(m) (cos((m) * ph) + I * sin((m) * ph))
+  double val = 0;
+  for (int n = 0; n <= p; ++n) {
+    double rn = pow(r, n + 1);
+    val += creal(M[IDX(n, 0)]) * PL(n, 0) / rn;
+    for (int m = 1; m <= n; ++m) val += 2 * creal(M[IDX(n, m)] * sqrt(fact(n - m) / fact(n + m)) * PL(n, m) * E(m)) / rn;
+  }
+  cplx s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0, s8 = 0, s9 = 0, s10 = 0;
+  for (int n = 0; n <= p; ++n) {
+    double r2 = pow(r, n + 2), r3 = pow(r, n + 3);
+    s1 -= M[IDX(n, 0)] * (n + 1.0) * PL(n + 1, 0) / r2;
+    s9 += M[IDX(n, 0)] * PL(n + 2, 0) * (n + 1.0) * (n + 2.0) / r3;
+    for (int m = 0; m <= n; ++m) {
+      cplx Mn = M[IDX(n, m)];
+      double fnm = fact(n - m), fpm = fact(n + m);
+      s3 += Mn * PL(n + 1, m + 1) * E(m + 1) / r2 * sqrt(fnm / fpm);
+      s5 -= Mn * PL(n + 2, m + 1) * E(m + 1) / r3 * sqrt(fact(n - m + 1) * fact(n - m + 1) / (fnm * fpm));
+      s7 += Mn * PL(n + 2, m + 2) * E(m + 2) / r3 * sqrt(fnm / fpm);
+      if (m >= 1) {
+        s2 -= Mn * PL(n + 1, m) * E(m) / r2 * sqrt(fact(n - m + 1) * fact(n - m + 1) / (fnm * fpm));
+        s4 -= Mn * PL(n + 1, m - 1) * E(m - 1) / r2 * sqrt(fact(n - m + 2) * fact(n - m + 2) / (fnm * fpm));
+        s6 += Mn * PL(n + 2, m - 1) * E(m - 1) / r3 * sqrt(fact(n - m + 3) * fact(n - m + 3) / (fnm * fpm));
+        s10 += Mn * PL(n + 2, m) * E(m) / r3 * sqrt(fact(n - m + 2) * fact(n - m + 2) / (fnm * fpm));
+      }
+      if (m >= 2) s8 += Mn * PL(n + 2, m - 2) * E(m - 2) / r3 * sqrt(fact(n - m + 4) * fact(n - m + 4) / (fnm * fpm));
+    }
+    if (n >= 1) s8 -= M[IDX(n, 1)] * PL(n + 2, 1) * E(-1) / r3 * sqrt(fact(n + 1) / fact(n - 1));
+  }
+  extract(val, creal(s1) + 2 * creal(s2), s3 + conj(s4), s5 + conj(s6), s7 + conj(s8),
+          creal(s9) + 2 * creal(s10), out);
+  free(Pl);
+}
+
+/* L->T with Theorem 2 (readings: s1 sums over n, s6 = -sum ...). */
+static void l2t(const orc_ops* o, const cplx* L, const double v[3], vgh_t* out) {
+  int p = o->p;
+  double r, th, ph;
+  to_sph(v, &r, &th, &ph);
+  double* Pl = malloc(sizeof(double) * IDX(p + 1, 0));
+  orc_legendre(p, cos(th), Pl);
+  double val = 0;
+  for (int n = 0; n <= p; ++n) {
+    double rn = pow(r, n);
+    val += creal(L[IDX(n, 0)]) * PL(n, 0) * rn;
+    for (int m = 1; m <= n; ++m) val += 2 * creal(L[IDX(n, m)] * sqrt(fact(n - m) / fact(n + m)) * PL(n, m) * E(m)) * rn;
+  }
+  cplx s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0, s8 = 0, s9 = 0, s10 = 0;
+  for (int n = 1; n <= p; ++n) {
+    double r1 = pow(r, n - 1), r2 = n >= 2 ? pow(r, n - 2) : 0.0;
+    s1 += L[IDX(n, 0)] * (double)n * r1 * PL(n - 1, 0);
+    if (n >= 2) s9 += L[IDX(n, 0)] * (double)n * (n - 1.0) * PL(n - 2, 0) * r2;
+    if (n >= 3) s8 -= L[IDX(n, 1)] * PL(n - 2, 1) * E(-1) * r2 * sqrt(fact(n + 1) / fact(n - 1));
+    for (int m = 0; m <= n; ++m) {
+      cplx Ln = L[IDX(n, m)];
+      double fnm = fact(n - m), fpm = fact(n + m);
+      if (m >= 1 && m <= n - 1) s2 += Ln * r1 * PL(n - 1, m) * E(m) * sqrt(fpm * fnm / (fact(n + m - 1) * fact(n + m - 1)));
+      if (n >= 2 && m <= n - 2) s3 += Ln * r1 * PL(n - 1, m + 1) * E(m + 1) * sqrt(fnm / fpm);
+      if (m >= 1) s4 -= Ln * r1 * PL(n - 1, m - 1) * E(m - 1) * sqrt(fpm * fnm / (fact(n + m - 2) * fact(n + m - 2)));
+      if (n >= 3 && m <= n - 3) s5 += Ln * PL(n - 2, m + 1) * E(m + 1) * r2 * sqrt(fnm * fpm / (fact(n + m - 1) * fact(n + m - 1)));
+      if (n >= 2 && m >= 1 && m <= n - 1) s6 -= Ln * PL(n - 2, m - 1) * E(m - 1) * r2 * sqrt(fnm * fpm / (fact(n + m - 3) * fact(n + m - 3)));
+      if (n >= 4 && m <= n - 4) s7 += Ln * PL(n - 2, m + 2) * E(m + 2) * r2 * sqrt(fnm / fpm);
+      if (n >= 2 && m >= 2) s8 += Ln * PL(n - 2, m - 2) * E(m - 2) * r2 * sqrt(fpm * fnm / (fact(n + m - 4) * fact(n + m - 4)));
+      if (n >= 2 && m >= 1 && m <= n - 2) s10 += Ln * r2 * PL(n - 2, m) * E(m) * sqrt(fpm * fnm / (fact(n + m - 2) * fact(n + m - 2)));
+    }
+  }
+#undef PL
+#undef E
+  extract(val, creal(s1) + 2 * creal(s2), s3 + conj(s4), s5 + conj(s6), s7 + conj(s8),
+          creal(s9) + 2 * creal(s10), out);
+  free(Pl);
+}
+
+/* Exported single-expansion helpers for the pins (paper normalisation). */
+void orc_p2m(int p, int64_t nb, const double* pos, const double* q, const double* c, double* Mri) {
+  orc_ops o = {p, 2 * p + 2, NULL};
+  o.s = malloc(sizeof(double) * IDX(o.P2 + 1, 0));
+  for (int n = 0; n <= o.P2; ++n) for (int m = 0; m <= n; ++m) o.s[IDX(n, m)] = sqrt(fact(n - m) * fact(n + m));
+  cplx* M = malloc(sizeof(cplx) * IDX(p + 1, 0));
+  p2m(&o, nb, pos, q, c, M);
+  for (int i = 0; i < IDX(p + 1, 0); ++i) { Mri[2 * i] = creal(M[i]); Mri[2 * i + 1] = cimag(M[i]); }
+  free(M); free(o.s);
+}
+
+/* Derivatives of a multipole (kind 0, Theorem 1) or local (kind 1,
+ * Theorem 2) expansion at v: out = [value, gx, gy, gz, hxx..hzz (9)]. */
+void orc_eval_expansion(int p, int kind, const double* Cri, const double* v, double* out) {
+  orc_ops o = {p, 2 * p + 2, NULL};
+  cplx* C = malloc(sizeof(cplx) * IDX(p + 1, 0));
+  for (int i = 0; i < IDX(p + 1, 0); ++i) C[i] = Cri[2 * i] + I * Cri[2 * i + 1];
+  vgh_t r;
+  memset(&r, 0, sizeof r);
+  if (kind == 0) m2t(&o, C, v, &r); else l2t(&o, C, v, &r);
+  out[0] = r.v;
+  for (int k = 0; k < 3; ++k) out[1 + k] = r.g[k];
+  for (int k = 0; k < 9; ++k) out[4 + k] = r.h[k / 3][k % 3];
+  free(C);
+}
+
+/* Translation helpers exported for the pins: op 0 = M2M, 1 = M2L, 2 = L2L,
+ * 3 = P2L (src/q given), from centre c0 to c1. */
+void orc_translate(int p, int op, const double* Cri, const double* c0, const double* c1, double* outri) {
+  orc_ops o = {p, 2 * p + 2, NULL};
+  o.s = malloc(sizeof(double) * IDX(o.P2 + 1, 0));
+  for (int n = 0; n <= o.P2; ++n) for (int m = 0; m <= n; ++m) o.s[IDX(n, m)] = sqrt(fact(n - m) * fact(n + m));
+  int T = IDX(p + 1, 0);
+  cplx* C = malloc(sizeof(cplx) * T);
+  cplx* out = calloc(T, sizeof(cplx));
+  for (int i = 0; i < T; ++i) C[i] = Cri[2 * i] + I * Cri[2 * i + 1];
+  if (op == 0) m2m(&o, 1, C, c0, c1, out);
+  else if (op == 1) m2l(&o, 1, C, c0, c1, out);
+  else l2l(&o, 1, C, c0, c1, out);
+  for (int i = 0; i < T; ++i) { outri[2 * i] = creal(out[i]); outri[2 * i + 1] = cimag(out[i]); }
+  free(C); free(out); free(o.s);
+}
+
+void orc_p2l(int p, int64_t nb, const double* pos, const double* q, const double* c, double* Lri) {
+  orc_ops o = {p, 2 * p + 2, NULL};
+  int T = IDX(p + 1, 0);
+  cplx* L = calloc(T, sizeof(cplx));
+  p2l(&o, nb, pos, q, c, L);
+  for (int i = 0; i < T; ++i) { Lri[2 * i] = creal(L[i]); Lri[2 * i + 1] = cimag(L[i]); }
+  free(L);
+}
+
+static void box_center(const orc_tree* t, int64_t b, double c[3]) {
+  double h = ldexp(t->side, -t->level[b]);
+  for (int k = 0; k < 3; ++k) c[k] = t->lo[k] + ((double)t->anchor[3 * b + k] + 0.5) * h;
+}
+
+/* The four-Laplace adaptive FMM (O4).  Expansions in the paper's
+ * normalisation; four densities per right-hand side: F^1, F^2, F^3 and the
+ * box-centred fourth charge F.(r - c).  The far field at a target sums
+ * the local expansion of its leaf (V and X lists of the leaf and its
+ * ancestors, carried down by L2L) and the multipoles of its W list, then
+ * assembles eq. (2.8); U-list beads are summed directly with the exact RPY
+ * block, and O-list pairs with r < 2a receive (M_overlap - M_far) F.
+ * pos [n][3], F [nrhs][n][3], out [nrhs][n][3], all in caller order.
+ * Returns 0, or -1 for invalid arguments. */
+int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, double eta, int p,
+            int leaf_size, int max_depth, double* out, int nthreads) {
+  if (n < 0 || p < 0 || p > 40 || nrhs < 1 || a <= 0 || eta <= 0 || leaf_size < 1) return -1;
+  if (n == 0) return 0;
+  set_threads(nthreads);
+  orc_tree* t = orc_tree_build(n, pos, leaf_size, max_depth, a);
+  orc_ops o = {p, 2 * p + 2, NULL};
+  o.s = malloc(sizeof(double) * IDX(o.P2 + 1, 0));
+  for (int nn = 0; nn <= o.P2; ++nn)
+    for (int m = 0; m <= nn; ++m) o.s[IDX(nn, m)] = sqrt(fact(nn - m) * fact(nn + m));
+  const int T = IDX(p + 1, 0);
+  const int64_t B = t->nbox;
+  const double C1 = 1.0 / (8.0 * ORC_PI * eta), C2 = a * a / (12.0 * ORC_PI * eta);
+  int maxlev = 0;
+  for (int64_t b = 0; b < B; ++b) if (t->level[b] > maxlev) maxlev = t->level[b];
+
+  double* spos = malloc(sizeof(double) * 3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) spos[3 * i + k] = pos[3 * t->perm[i] + k];
+  double* ctr = malloc(sizeof(double) * 3 * B);
+  for (int64_t b = 0; b < B; ++b) box_center(t, b, ctr + 3 * b);
+  cplx* M = malloc(sizeof(cplx) * (size_t)B * 4 * T);
+  cplx* L = malloc(sizeof(cplx) * (size_t)B * 4 * T);
+  double* sF = malloc(sizeof(double) * 3 * n);
+
+  for (int r = 0; r < nrhs; ++r) {
+    const double* Fr = F + (size_t)r * n * 3;
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) sF[3 * i + k] = Fr[3 * t->perm[i] + k];
+    memset(M, 0, sizeof(cplx) * (size_t)B * 4 * T);
+    memset(L, 0, sizeof(cplx) * (size_t)B * 4 * T);
+
+    /* S->M at leaves. */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < B; ++b) {
+      if (t->nchild[b]) continue;
+      int64_t nb = t->end[b] - t->begin[b];
+      double* q = malloc(sizeof(double) * nb);
+      const double* bp = spos + 3 * t->begin[b];
+      const double* bf = sF + 3 * t->begin[b];
+      for (int s = 0; s < 4; ++s) {
+        for (int64_t j = 0; j < nb; ++j) {
+          if (s < 3) q[j] = bf[3 * j + s];
+          else {
+            q[j] = 0;
+            for (int k = 0; k < 3; ++k) q[j] += bf[3 * j + k] * (bp[3 * j + k] - ctr[3 * b + k]);
+          }
+        }
+        p2m(&o, nb, bp, q, ctr + 3 * b, M + ((size_t)b * 4 + s) * T);
+      }
+      free(q);
+    }
+    /* M->M, finest level first; the child's fourth charge is re-centred on
+       the parent before the shift. */
+    for (int lev = maxlev - 1; lev >= 0; --lev) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int64_t b = 0; b < B; ++b) {
+        if (t->level[b] != lev || !t->nchild[b]) continue;
+        cplx* tmp = malloc(sizeof(cplx) * 4 * T);
+        for (int64_t c = t->child_begin[b]; c < t->child_begin[b] + t->nchild[b]; ++c) {
+          memcpy(tmp, M + (size_t)c * 4 * T, sizeof(cplx) * 4 * T);
+          recentre(T, tmp, ctr + 3 * c, ctr + 3 * b);
+          m2m(&o, 4, tmp, ctr + 3 * c, ctr + 3 * b, M + (size_t)b * 4 * T);
+        }
+        free(tmp);
+      }
+    }
+    /* Downward: L->L from the parent, M->L over V, S->L over X; every
+       incoming fourth charge is re-centred on this machine first. */
+    for (int lev = 0; lev <= maxlev; ++lev) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int64_t b = 0; b < B; ++b) {
+        if (t->level[b] != lev) continue;
+        cplx* Lb = L + (size_t)b * 4 * T;
+        cplx* tmp = malloc(sizeof(cplx) * 4 * T);
+        int64_t par = t->parent[b];
+        if (par >= 0) {
+          memcpy(tmp, L + (size_t)par * 4 * T, sizeof(cplx) * 4 * T);
+          recentre(T, tmp, ctr + 3 * par, ctr + 3 * b);
+          l2l(&o, 4, tmp, ctr + 3 * par, ctr + 3 * b, Lb);
+        }
+        for (int64_t e = t->off[1][b]; e < t->off[1][b + 1]; ++e) {
+          int64_t S = t->ent[1][e];
+          memcpy(tmp, M + (size_t)S * 4 * T, sizeof(cplx) * 4 * T);
+          recentre(T, tmp, ctr + 3 * S, ctr + 3 * b);
+          m2l(&o, 4, tmp, ctr + 3 * S, ctr + 3 * b, Lb);
+        }
+        for (int64_t e = t->off[3][b]; e < t->off[3][b + 1]; ++e) {
+          int64_t C = t->ent[3][e];
+          int64_t nb = t->end[C] - t->begin[C];
+          double* q = malloc(sizeof(double) * nb);
+          const double* cp = spos + 3 * t->begin[C];
+          const double* cf = sF + 3 * t->begin[C];
+          for (int s = 0; s < 4; ++s) {
+            for (int64_t j = 0; j < nb; ++j) {
+              if (s < 3) q[j] = cf[3 * j + s];
+              else {
+                q[j] = 0;
+                for (int k = 0; k < 3; ++k) q[j] += cf[3 * j + k] * (cp[3 * j + k] - ctr[3 * b + k]);
+              }
+            }
+            p2l(&o, nb, cp, q, ctr + 3 * b, Lb + s * T);
+          }
+          free(q);
+        }
+        free(tmp);
+      }
+    }
+    /* Targets: L->T and M->T (W list) then eq. (2.8); U list directly; O list
+       correction. */
+    double* ro = out + (size_t)r * n * 3;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < B; ++b) {
+      if (t->nchild[b]) continue;
+      const double* cb = ctr + 3 * b;
+      cplx* Mw = malloc(sizeof(cplx) * T * 4);
+      for (int64_t i = t->begin[b]; i < t->end[b]; ++i) {
+        const double* x = spos + 3 * i;
+        double v[3] = {x[0] - cb[0], x[1] - cb[1], x[2] - cb[2]};
+        vgh_t f[4];
+        memset(f, 0, sizeof f);
+        for (int s = 0; s < 4; ++s) l2t(&o, L + ((size_t)b * 4 + s) * T, v, &f[s]);
+        for (int64_t e = t->off[2][b]; e < t->off[2][b + 1]; ++e) {
+          int64_t C = t->ent[2][e];
+          const double* cc = ctr + 3 * C;
+          memcpy(Mw, M + (size_t)C * 4 * T, sizeof(cplx) * 4 * T);
+          recentre(T, Mw, cc, cb);
+          double vc[3] = {x[0] - cc[0], x[1] - cc[1], x[2] - cc[2]};
+          for (int s = 0; s < 4; ++s) m2t(&o, Mw + s * T, vc, &f[s]);
+        }
+        double u[3];
+        for (int k = 0; k < 3; ++k) {
+          double xs = 0, gLc = 0;
+          for (int s = 0; s < 3; ++s) { xs += v[s] * f[s].g[k]; gLc += f[s].h[k][s]; }
+          u[k] = C1 * f[k].v - C1 * xs + C1 * f[3].g[k] - C2 * gLc;
+        }
+        for (int64_t e = t->off[0][b]; e < t->off[0][b + 1]; ++e) {
+          int64_t C = t->ent[0][e];
+          for (int64_t j = t->begin[C]; j < t->end[C]; ++j) {
+            double d[3] = {x[0] - spos[3 * j], x[1] - spos[3 * j + 1], x[2] - spos[3 * j + 2]}, Mb[9];
+            orc_rpy_block(d, a, eta, Mb);
+            for (int k = 0; k < 3; ++k)
+              u[k] += Mb[3 * k] * sF[3 * j] + Mb[3 * k + 1] * sF[3 * j + 1] + Mb[3 * k + 2] * sF[3 * j + 2];
+          }
+        }
+        for (int64_t e = t->off[4][b]; e < t->off[4][b + 1]; ++e) {
+          int64_t C = t->ent[4][e];
+          for (int64_t j = t->begin[C]; j < t->end[C]; ++j) {
+            double d[3] = {x[0] - spos[3 * j], x[1] - spos[3 * j + 1], x[2] - spos[3 * j + 2]};
+            double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (rr >= 2.0 * a) continue;
+            /* M_far at this separation, then the exact block. */
+            double r2 = rr * rr, Mf[9], Mo[9];
+            double cf = 1.0 / (8.0 * ORC_PI * eta * rr);
+            double Af = cf * (1.0 + 2.0 * a * a / (3.0 * r2)), Bf = cf * (1.0 - 2.0 * a * a / r2) / r2;
+            for (int i2 = 0; i2 < 3; ++i2)
+              for (int j2 = 0; j2 < 3; ++j2) Mf[3 * i2 + j2] = (i2 == j2 ? Af : 0.0) + Bf * d[i2] * d[j2];
+            if (rr == 0.0) memset(Mf, 0, sizeof Mf); /* coincident: no far term was formed */
+            orc_rpy_block(d, a, eta, Mo);
+            for (int k = 0; k < 3; ++k)
+              for (int l = 0; l < 3; ++l) u[k] += (Mo[3 * k + l] - Mf[3 * k + l]) * sF[3 * j + l];
+          }
+        }
+        int64_t ci = t->perm[i];
+        for (int k = 0; k < 3; ++k) ro[3 * ci + k] = u[k];
+      }
+      free(Mw);
+    }
+  }
+  free(spos); free(ctr); free(M); free(L); free(sF); free(o.s);
+  orc_tree_free(t);
+  return 0;
+}
