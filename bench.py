@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the RPY mobility matvec on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube-1M]
+
+A step is one full matvec (tree reused): permute, near field (P2P + overlap
+correction), S->M, M->M, M->L, S->L, L->L, target evaluation (eq. 2.8) and
+un-permute, over device-resident forces.  Prints one JSON line with the
+metric, the live roofline of the dominant kernel (HIP events around each
+phase inside the timed region) and the FP64 CPU oracle timed on a bounded
+sample of the same workload (which also gates the accuracy).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "beads·matvecs/s at 1e-6 rel-L2 vs FP64 direct; mixed/batched vs FP64 FMM"
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (and FP64 matrix) peak
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {"cube-2k": 1, "cube-1M": 2, "blobs-4M": 3, "batched-64": 4, "cube-15M": 5}
+
+
+def algorithmic_counts(P, p, nrc):
+    """Algorithmic flops per launch of the P2P and M2L kernels, from the
+    plan's lists (host arithmetic on exported integers only)."""
+    ex = P.export()
+    boxes = ex["boxes"]
+    cnt = boxes[:, 5] - boxes[:, 4]
+    uo, ue = ex["lists"]["U"]
+    leaves = np.where(boxes[:, 7] < 0)[0]
+    src = np.add.reduceat(cnt[ue], uo[:-1]) if len(ue) else np.zeros(len(cnt))
+    # reduceat on empty segments returns the element at the offset; mask them
+    seg = uo[1:] - uo[:-1]
+    src = np.where(seg > 0, src, 0)
+    pairs = int(np.sum(cnt[leaves] * src[leaves]))
+    vo, _ = ex["lists"]["V"]
+    npair_v = int(vo[-1])
+    T = (p + 1) * (p + 2) // 2
+    # P2P: 8 flops of geometry + 12 for the RPY coefficients per pair, and 18
+    # per right-hand side (d.F, the scaled dyad and the accumulate).
+    p2p_flops = pairs * (20 + 18 * nrc)
+    # M2L (dense): per V pair and density, T x (p+1)^2 complex multiply-adds.
+    m2l_flops = npair_v * 4 * nrc * T * (p + 1) ** 2 * 8
+    return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "m2l_flops": m2l_flops}
+
+
+def traffic_for(kernel_file, launches_key):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current source of the kernel; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(launches_key)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_1711_02976_amd", "csrc", kernel_file)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha") != sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run(args):
+    import torch
+
+    import paper_1711_02976_amd as R
+    import workloads as W
+
+    w = W.config(WORKLOADS[args.workload], nsample=args.cpu_targets)
+    dev = torch.device("cuda:0")
+    pos = torch.as_tensor(w.pos, device=dev)
+    F = torch.as_tensor(w.forces, device=dev)
+    U = torch.empty_like(F)
+    counts = w.counts if len(w.counts) > 1 else None
+
+    results = {}
+    for prec in args.precisions:
+        torch.cuda.synchronize()
+        P = R.Plan(pos, w.a, w.eta, w.eps, precision=prec, leaf_size=args.leaf_size, order=args.order,
+                   max_depth=w.max_depth, counts=counts)
+        st = P.stats()
+        for _ in range(args.warmup):
+            P.matvec(F, out=U)
+        torch.cuda.synchronize()
+        P.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            P.matvec(F, out=U)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tm = P.timings()
+        ms = (t1 - t0) * 1e3 / args.steps
+        nrc = 4 if w.nrhs >= 4 else (2 if w.nrhs >= 2 else 1)
+        alg = algorithmic_counts(P, st["order"], nrc)
+        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "alg": alg,
+                         "u": U[:, w.sample].cpu().numpy()}
+
+    # CPU baseline: the FP64 oracle's direct sum on the sampled targets.
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        k = len(w.sample)
+        t0 = time.perf_counter()
+        ref = oracle.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
+        tc = time.perf_counter() - t0
+        cpu = {"value": k * w.nrhs / tc, "unit": "beads*matvecs/s", "cores": oracle.max_threads(),
+               "kind": "oracle",
+               "sample": f"direct O(N^2) FP64 sum for {k} sampled targets of {w.n} (all sources, "
+                         f"nrhs={w.nrhs}), {tc:.2f} s; value = targets*rhs/s"}
+        for prec, r in results.items():
+            errs[prec] = oracle.rel_l2(r["u"], ref)
+
+    # Headline: the fastest form that meets the accuracy gate.
+    ok = [p for p in results if (not errs) or errs[p] <= w.eps]
+    best = min(ok or list(results), key=lambda p: results[p]["ms"])
+    r = results[best]
+    value = w.n * w.nrhs / (r["ms"] * 1e-3)
+    tm = r["timings"]
+    phase_ms = {k: v / max(args.steps, 1) for k, v in tm["ms"].items()}
+    dom = max(("p2p", "m2l"), key=lambda k: tm["ms"][k])
+    launches = max(tm["launches"][dom], 1)
+    avg_ms = tm["ms"][dom] / launches
+    mixed = best == "mixed"
+    if dom == "p2p":
+        flops = r["alg"]["p2p_flops"]
+        peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+        kfile = "nearfield.hip"
+    else:
+        flops = r["alg"]["m2l_flops"]
+        peak = PEAK_FP64_TFLOPS
+        kfile = "fmm.hip"
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic_for(kfile, f"{dom}:{args.workload}:{best}"),
+            "avg_launch_ms": round(avg_ms, 4), "algorithmic_flops_per_launch": flops}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "beads*matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_beads": w.n, "nrhs": w.nrhs, "a": w.a, "eta": w.eta, "eps": w.eps,
+                   "precision": best, "order": r["stats"]["order"], "leaf_size": r["stats"]["leaf_size"],
+                   "boxes": r["stats"]["nbox"], "depth": r["stats"]["depth"],
+                   "plan_ms": round(r["stats"]["plan_ms"], 2)},
+        "rel_l2_vs_direct": errs.get(best),
+        "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+        "forms": {p: {"ms_per_step": round(q["ms"], 4), "value": w.n * w.nrhs / (q["ms"] * 1e-3),
+                      "rel_l2_vs_direct": errs.get(p)} for p, q in results.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    for q in results.values():
+        q["plan"].free()
+    print(json.dumps(line), flush=True)
+    if errs and errs[best] > w.eps:
+        print(f"accuracy gate failed: rel-L2 {errs[best]:.3e} > {w.eps:.0e}", file=sys.stderr)
+        return 3
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube-1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--precisions", default="fp64", help="comma list of forms to time: fp64,mixed")
+    ap.add_argument("--leaf-size", type=int, default=0)
+    ap.add_argument("--order", type=int, default=0)
+    ap.add_argument("--cpu-targets", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    args = ap.parse_args()
+    args.precisions = [p.strip() for p in args.precisions.split(",") if p.strip()]
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        return 2
+    return run(args)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

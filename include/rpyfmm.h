@@ -1,0 +1,168 @@
+/*
+ * rpyfmm.h -- C ABI of the MI355X (gfx950) RPY-FMM library.
+ *
+ * The library evaluates the Rotne-Prager-Yamakawa (RPY) mobility
+ * matrix-vector product over N beads of one radius a in a fluid of viscosity
+ * eta (Guan et al., arXiv:1711.02976, Sec. 1, the three RPY block equations;
+ * kB*T = 1, so the self block is I/(6 pi eta a)):
+ *
+ *     u_i = sum_j M(r_i - r_j; a, eta) F_j ,   j = i included (self term),
+ *
+ * by splitting the far field into four Laplace potentials (Sec. 2, L1..L4,
+ * L_C and eq. (2.8)) evaluated with an adaptive fast multipole method, plus
+ * the exact near field and an overlap correction for pairs closer than 2a
+ * that the far field treats with the r >= 2a formula.
+ *
+ * Conventions common to every entry point
+ *   - Pointers marked "device" must be HIP device (or managed) memory on the
+ *     current device.  Pointers marked "host" are ordinary host memory.
+ *   - Arrays are dense, row-major, FP64.  positions [n][3] = (x, y, z) per
+ *     bead; forces and velocities [nrhs][n][3], in the caller's bead order.
+ *   - Every entry point returns an rpy_status; negative values are errors.
+ *     No exception crosses the ABI.  rpy_last_error() gives a thread-local
+ *     human-readable detail of the last failure on the calling thread.
+ *   - A plan is used by one host thread at a time; distinct plans are
+ *     independent.  Work is issued on the plan's stream (options.stream, or
+ *     the null stream) and rpy_matvec returns before the GPU finishes.
+ */
+#ifndef RPYFMM_H
+#define RPYFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPY_OK = 0,
+  RPY_EINVAL = -1,       /* invalid argument (sizes, radius, viscosity, eps, NULL) */
+  RPY_ENONFINITE = -2,   /* a position is NaN or infinite */
+  RPY_ENOMEM = -3,       /* device allocation failed */
+  RPY_EDEVICE = -4,      /* a HIP call failed; sticky on the plan */
+  RPY_EUNSUPPORTED = -5  /* option combination not built */
+} rpy_status;
+
+typedef enum {
+  RPY_PREC_FP64 = 0,   /* every kernel in FP64 */
+  RPY_PREC_MIXED = 1   /* near field and M2L in FP32 (pair differences and
+                          expansion storage/sums in FP64) */
+} rpy_precision;
+
+typedef struct {
+  uint32_t struct_size;  /* sizeof(rpy_options); lets the struct grow */
+  int32_t precision;     /* rpy_precision */
+  int32_t leaf_size;     /* refinement limit: max beads per leaf (Sec. 4.2
+                            "threshold"); 0 = chosen by the library */
+  int32_t order;         /* expansion order p; 0 = chosen from eps */
+  int32_t max_depth;     /* deepest tree level, 1..21; 0 = 14 */
+  int32_t reserved0;
+  void* stream;          /* hipStream_t for all work; NULL = null stream */
+} rpy_options;
+
+typedef struct rpy_plan_s rpy_plan_t;
+
+typedef struct {
+  int64_t n;             /* beads (all systems) */
+  int32_t nsys;          /* independent systems in the plan */
+  int32_t order;         /* expansion order p in use */
+  int32_t leaf_size;     /* refinement limit in use */
+  int32_t depth;         /* deepest level present */
+  int32_t precision;     /* rpy_precision in use */
+  int32_t reserved0;
+  int64_t nbox;          /* boxes (all systems) */
+  int64_t nleaf;
+  int64_t list_len[5];   /* entries of the U, V, W, X, O lists */
+  int64_t device_bytes;  /* device memory held by the plan */
+  double plan_ms;        /* wall time of rpy_plan / rpy_plan_batched */
+} rpy_plan_stats_t;
+
+/* Fills *opt with the defaults (FP64, automatic leaf size and order,
+ * max_depth 14, null stream). */
+void rpy_default_options(rpy_options* opt);
+
+/* Build a plan for one system of n beads.
+ *   positions  device [n][3] FP64; copied, may be freed after return.
+ *   a, eta     bead radius and solvent viscosity, both > 0.
+ *   eps        requested relative L2 accuracy of the far field, in
+ *              [1e-12, 1e-1]; selects the expansion order when
+ *              opt->order == 0 (Sec. 4.3 uses 3, 6 and 9 digits).
+ *   opt        nullable; NULL means rpy_default_options.
+ * Builds, on the GPU: the bounding cube and 63-bit Morton keys, a stable
+ * radix sort, the adaptive octree (refine while more than leaf_size beads,
+ * Sec. 4.2) and the U, V, W, X and O interaction lists.  n == 0 is valid
+ * (every matvec is then a no-op).  On failure *out is set to NULL. */
+rpy_status rpy_plan(rpy_plan_t** out, int64_t n, const double* positions, double a, double eta,
+                    double eps, const rpy_options* opt);
+
+/* Build one plan for nsys independent systems whose beads are concatenated
+ * in positions (device [sum counts][3]); counts is host [nsys].  Systems do
+ * not interact; each gets its own bounding cube and tree, and one launch of
+ * each kernel serves all of them. */
+rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* counts,
+                            const double* positions, double a, double eta, double eps,
+                            const rpy_options* opt);
+
+/* velocities = M forces for nrhs right-hand sides.
+ *   forces      device [nrhs][n][3] FP64, caller bead order; read only.
+ *   velocities  device [nrhs][n][3] FP64; overwritten (not accumulated).
+ * Asynchronous on the plan's stream; the buffers must stay valid until the
+ * stream reaches this call's end. */
+rpy_status rpy_matvec(rpy_plan_t* plan, int32_t nrhs, const double* forces, double* velocities);
+
+/* Sizes and settings of a plan (host struct). */
+rpy_status rpy_plan_stats(const rpy_plan_t* plan, rpy_plan_stats_t* out);
+
+/* Copy the tree out for inspection and tests (all host arrays, caller
+ * allocated; any pointer may be NULL to skip it):
+ *   perm     [n]          caller index of the k-th bead in tree order
+ *   keys     [n]          63-bit Morton keys in tree order
+ *   boxes    [nbox][8]    level, anchor x, y, z, begin, end, parent,
+ *                         first child (-1 for a leaf); begin/end index the
+ *                         tree order; per-system boxes are concatenated
+ *   offsets  [5][nbox+1]  CSR offsets of the U, V, W, X, O lists
+ *   entries  [sum list_len] the five lists' entries, concatenated in the
+ *                         order U, V, W, X, O; each list sorted by box id
+ * Box ids and list entries are global across systems. */
+rpy_status rpy_plan_export(const rpy_plan_t* plan, int64_t* perm, uint64_t* keys, int64_t* boxes,
+                           int64_t* offsets, int64_t* entries);
+
+/* Phases of one matvec pass, in launch order. */
+typedef enum {
+  RPY_PH_PERMUTE = 0,  /* forces to tree order */
+  RPY_PH_P2P,          /* near field over the U lists, self term included */
+  RPY_PH_OVERLAP,      /* r < 2a correction over the O lists */
+  RPY_PH_P2M,          /* S->M at leaves */
+  RPY_PH_M2M,          /* M->M, one launch per level */
+  RPY_PH_M2L,          /* M->L over the V lists */
+  RPY_PH_P2L,          /* S->L over the X lists */
+  RPY_PH_L2L,          /* L->L, one launch per level */
+  RPY_PH_EVAL,         /* L->T, M->T (W lists) and eq. (2.8) */
+  RPY_PH_UNPERMUTE,    /* velocities to caller order */
+  RPY_NPHASE
+} rpy_phase;
+
+typedef struct {
+  double ms[RPY_NPHASE];         /* accumulated GPU time per phase (HIP events) */
+  int64_t launches[RPY_NPHASE];  /* kernel launches per phase */
+  int64_t passes;                /* matvec passes (right-hand-side chunks) timed */
+} rpy_timings_t;
+
+/* Enable (1) or disable (0) per-phase timing with HIP events on the plan's
+ * stream; enabling resets the accumulators.  Timing adds two events per
+ * phase and pass and no synchronisation. */
+rpy_status rpy_plan_set_timing(rpy_plan_t* plan, int32_t enable);
+
+/* Waits for the plan's stream, folds all recorded events into *out. */
+rpy_status rpy_plan_timings(rpy_plan_t* plan, rpy_timings_t* out);
+
+/* Release a plan and its device memory; NULL is a no-op. */
+void rpy_plan_free(rpy_plan_t* plan);
+
+const char* rpy_status_string(rpy_status s);
+const char* rpy_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPYFMM_H */

@@ -1,0 +1,115 @@
+// Internal declarations shared by the HIP sources of librpyfmm (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace rpy {
+
+constexpr int KBITS = 21;            // quantisation bits per axis (63-bit Morton key)
+constexpr int NSLOT = 27;            // colleague slots: offsets in {-1,0,1}^3
+constexpr int MAX_ORDER = 21;        // (p+1)(p+2)/2 <= 253 coefficients per expansion
+constexpr int STACK = 192;           // private DFS stack of the list kernels
+
+__host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
+
+// Device view of the octree.  Boxes are numbered by (level, system, Morton
+// key); begin/end index the sorted bead order.
+struct Tree {
+  int nbox;
+  int* level;
+  int* sys;
+  int* ax;
+  int* ay;
+  int* az;
+  int* begin;
+  int* end;
+  int* parent;
+  int* child;    // first child, -1 for a leaf
+  int* nchild;
+  double* cx;    // centre
+  double* cy;
+  double* cz;
+  double* h;     // side
+};
+
+// CSR list: entries of box b are ent[off[b] .. off[b+1]).
+struct List {
+  int* off;
+  int* ent;
+  int64_t len;
+};
+
+enum { LU = 0, LV = 1, LW = 2, LX = 3, LO = 4 };
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// ---- scan (exclusive prefix sum of int32) -------------------------------
+// Scans n ints from `in` to `out` (may alias) on stream; returns 0 or a HIP
+// error code.  Uses `tmp` scratch of scan_tmp_ints(n) ints.
+size_t scan_tmp_ints(int64_t n);
+hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
+
+// ---- tree build (tree.hip) ---------------------------------------------
+struct BuildArgs {
+  int64_t n;
+  int nsys;
+  const int64_t* sys_begin_h;   // host [nsys+1]
+  const double* pos;            // device [n][3], caller order
+  int leaf_size;
+  int max_depth;
+  double a;
+  hipStream_t stream;
+};
+
+// Everything rpy_plan builds on the device.  Owned buffers are released by
+// free_built().
+struct Built {
+  // beads in tree order
+  int64_t n = 0;
+  uint64_t* keys = nullptr;
+  int* perm = nullptr;        // tree order -> caller index
+  double* sx = nullptr;       // sorted positions, SoA
+  double* sy = nullptr;
+  double* sz = nullptr;
+  // systems
+  int nsys = 0;
+  std::vector<double> lo;      // [nsys][3]
+  std::vector<double> side;    // [nsys]
+  double* d_lo = nullptr;      // device copies
+  double* d_side = nullptr;
+  int* d_sys_begin = nullptr;  // [nsys+1]
+  // tree
+  Tree tree{};
+  int cap = 0;
+  std::vector<int> level_start;  // boxes of level l are [level_start[l], level_start[l+1])
+  int depth = 0;
+  int* colleague = nullptr;     // [nbox][27]
+  int nleaf = 0;
+  int* leaf_ids = nullptr;      // [nleaf]
+  List lists[5]{};
+  int64_t bytes = 0;
+};
+
+int build_tree(const BuildArgs& a, Built* out, Error* err);
+void free_built(Built* b);
+
+}  // namespace rpy
+
+#define RPY_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      if (err) {                                                                   \
+        err->code = -4;                                                            \
+        err->msg = std::string(#expr) + ": " + hipGetErrorString(e_);              \
+      }                                                                            \
+      return -4;                                                                   \
+    }                                                                              \
+  } while (0)

@@ -1,0 +1,61 @@
+// Declarations of the matvec kernels' launchers (fmm.hip, nearfield.hip).
+#pragma once
+#include "common.h"
+
+namespace rpy {
+
+// Expansion storage: for every box, ND = 4*nrc densities (F_x, F_y, F_z and
+// the box-centred fourth charge F.(r - c), per right-hand side), each with
+// ncoef(p) complex coefficients for 0 <= m <= n <= p.  Internally the
+// coefficients use solid harmonics normalised so that translations are
+// plain convolutions, R_n^m = r^n P_n^m(cos t) e^{im phi}/(n+m)! and
+// I_n^m = (n-m)! P_n^m(cos t) e^{im phi}/r^{n+1}, and they are scaled by the
+// box side h: a box's multipole is M_n^m/h^n and its local expansion
+// L_n^m h^{n+1}, so every translation operator depends only on offsets in
+// box units.  The paper's coefficients (Sec. 2) are these times (or divided
+// by) sqrt((n-m)!(n+m)!) and the matching power of h.
+struct Exp {
+  double2* M;
+  double2* L;
+};
+
+struct Tables {
+  int p;
+  double2* oct;    // [8][(p+1)^2] R_j^mu(d/h_parent), d = child - parent centre
+  double2* itab;   // [343][(2p+1)^2] I_j^mu(t), t integer offset in box units
+  int64_t bytes;
+};
+
+int make_tables(int p, Tables* tb, hipStream_t s, Error* err);
+void free_tables(Tables* tb);
+
+struct Launch {
+  const Built* B;
+  const Tables* tb;
+  int p;
+  double a, eta;
+  hipStream_t s;
+};
+
+// Forces (caller order, [nrhs][n][3]) -> sorted SoA [nrc][3][n] for rhs r0..r0+nrc-1.
+hipError_t permute_forces(const Launch& l, const double* F, int nrhs_total, int r0, int nrc, double* sF);
+// Sorted SoA velocities -> caller order output.
+hipError_t unpermute_velocities(const Launch& l, const double* u, int r0, int nrc, double* out);
+
+hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e);
+hipError_t run_m2m(const Launch& l, int nrc, Exp e);
+hipError_t run_m2l(const Launch& l, int nrc, Exp e);
+hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e);
+hipError_t run_l2l(const Launch& l, int nrc, Exp e);
+hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u);
+
+// Near field.  `tiles` lists (leaf, first bead, count) work items.
+struct Tiles {
+  int n;
+  int4* t;
+};
+int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err);
+hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);
+
+}  // namespace rpy

@@ -1,0 +1,736 @@
+// Far-field kernels of the four-Laplace FMM (arXiv:1711.02976, Sec. 2):
+// S->M, M->M, M->L, S->L, L->L and the target evaluation that assembles
+// eq. (2.8) from the local expansion (L->T) and the W-list multipoles (M->T).
+//
+// Densities per right-hand side: F_x, F_y, F_z (the charges of L1..L3) and the
+// fourth charge F.(r - c) centred on the box that owns the expansion
+// (an exact rewriting of L4 = sum F.r_j/|r_i - r_j| that keeps every term
+// O(box size)); whenever an expansion moves to a new centre its fourth
+// density is re-centred by E4 += (c_old - c_new).(E1, E2, E3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "fmm.h"
+
+namespace rpy {
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+__host__ __device__ inline int fidx(int n, int m) { return n * n + n + m; }  // full layout, |m| <= n
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cmulc(double2 a, double2 b) {  // a * conj(b)
+  return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+__device__ inline void cfmac(double2& acc, double2 a, double2 b) {  // acc += a * conj(b)
+  acc.x = fma(a.x, b.x, fma(a.y, b.y, acc.x));
+  acc.y = fma(a.y, b.x, fma(-a.x, b.y, acc.y));
+}
+
+// Coefficient C_n^m of a real-symmetric set stored for m >= 0 (C^{-m} =
+// (-1)^m conj(C^m)); zero outside 0 <= n <= nmax, |m| <= n.
+__device__ inline double2 getc(const double2* C, int n, int m, int nmax) {
+  if (n < 0 || n > nmax || m > n || m < -n) return make_double2(0.0, 0.0);
+  if (m >= 0) return C[tri(n) + m];
+  double2 v = C[tri(n) - m];
+  return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
+}
+
+// Column m of the regular harmonics R_n^m(v), n = m..nmax, into H[tri(n)+m].
+__device__ inline void regular_column(double x, double y, double z, int m, int nmax, double2* H) {
+  double r2 = x * x + y * y + z * z;
+  double2 rmm = make_double2(1.0, 0.0);
+  for (int k = 1; k <= m; ++k) {
+    double f = -0.5 / k;
+    rmm = make_double2(f * (x * rmm.x - y * rmm.y), f * (x * rmm.y + y * rmm.x));
+  }
+  if (m > nmax) return;
+  H[tri(m) + m] = rmm;
+  if (m + 1 > nmax) return;
+  double2 r1 = make_double2(z * rmm.x, z * rmm.y);
+  H[tri(m + 1) + m] = r1;
+  double2 r0 = rmm;
+  for (int n = m + 2; n <= nmax; ++n) {
+    double inv = 1.0 / ((double)(n + m) * (n - m));
+    double a = (2 * n - 1) * z * inv, b = r2 * inv;
+    double2 rn = make_double2(a * r1.x - b * r0.x, a * r1.y - b * r0.y);
+    H[tri(n) + m] = rn;
+    r0 = r1;
+    r1 = rn;
+  }
+}
+
+// Column m of the irregular harmonics I_n^m(v), n = m..nmax.
+__device__ inline void irregular_column(double x, double y, double z, int m, int nmax, double2* H) {
+  double r2 = x * x + y * y + z * z;
+  double ir2 = 1.0 / r2;
+  double2 imm = make_double2(sqrt(ir2), 0.0);
+  for (int k = 1; k <= m; ++k) {
+    double f = -(2 * k - 1) * ir2;
+    imm = make_double2(f * (x * imm.x - y * imm.y), f * (x * imm.y + y * imm.x));
+  }
+  if (m > nmax) return;
+  H[tri(m) + m] = imm;
+  if (m + 1 > nmax) return;
+  double f1 = (2 * m + 1) * z * ir2;
+  double2 i1 = make_double2(f1 * imm.x, f1 * imm.y);
+  H[tri(m + 1) + m] = i1;
+  double2 i0 = imm;
+  for (int n = m + 2; n <= nmax; ++n) {
+    double a = (2 * n - 1) * z * ir2, b = (double)(n + m - 1) * (n - m - 1) * ir2;
+    double2 in = make_double2(a * i1.x - b * i0.x, a * i1.y - b * i0.y);
+    H[tri(n) + m] = in;
+    i0 = i1;
+    i1 = in;
+  }
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// ------------------------------------------------------------ host tables --
+void host_regular(double x, double y, double z, int p, std::vector<double2>& out) {
+  // full layout, all |mu| <= j
+  out.assign((p + 1) * (p + 1), make_double2(0, 0));
+  double r2 = x * x + y * y + z * z;
+  std::vector<double2> col(ncoef(p));
+  for (int m = 0; m <= p; ++m) {
+    double2 rmm = make_double2(1, 0);
+    for (int k = 1; k <= m; ++k) {
+      double f = -0.5 / k;
+      rmm = make_double2(f * (x * rmm.x - y * rmm.y), f * (x * rmm.y + y * rmm.x));
+    }
+    col[tri(m) + m] = rmm;
+    if (m + 1 <= p) col[tri(m + 1) + m] = make_double2(z * rmm.x, z * rmm.y);
+    for (int n = m + 2; n <= p; ++n) {
+      double inv = 1.0 / ((double)(n + m) * (n - m));
+      double2 a = col[tri(n - 1) + m], b = col[tri(n - 2) + m];
+      col[tri(n) + m] = make_double2(((2 * n - 1) * z * a.x - r2 * b.x) * inv, ((2 * n - 1) * z * a.y - r2 * b.y) * inv);
+    }
+  }
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      double2 v = col[tri(n) + m];
+      out[fidx(n, m)] = v;
+      out[fidx(n, -m)] = (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
+    }
+}
+
+void host_irregular(double x, double y, double z, int p, std::vector<double2>& out) {
+  out.assign((p + 1) * (p + 1), make_double2(0, 0));
+  double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+  std::vector<double2> col(ncoef(p));
+  for (int m = 0; m <= p; ++m) {
+    double2 imm = make_double2(std::sqrt(ir2), 0);
+    for (int k = 1; k <= m; ++k) {
+      double f = -(2 * k - 1) * ir2;
+      imm = make_double2(f * (x * imm.x - y * imm.y), f * (x * imm.y + y * imm.x));
+    }
+    col[tri(m) + m] = imm;
+    if (m + 1 <= p) {
+      double f1 = (2 * m + 1) * z * ir2;
+      col[tri(m + 1) + m] = make_double2(f1 * imm.x, f1 * imm.y);
+    }
+    for (int n = m + 2; n <= p; ++n) {
+      double a = (2 * n - 1) * z * ir2, b = (double)(n + m - 1) * (n - m - 1) * ir2;
+      double2 u = col[tri(n - 1) + m], v = col[tri(n - 2) + m];
+      col[tri(n) + m] = make_double2(a * u.x - b * v.x, a * u.y - b * v.y);
+    }
+  }
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      double2 v = col[tri(n) + m];
+      out[fidx(n, m)] = v;
+      out[fidx(n, -m)] = (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
+    }
+}
+
+}  // namespace
+
+int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
+  tb->p = p;
+  tb->bytes = 0;
+  const int F1 = (p + 1) * (p + 1), F2 = (2 * p + 1) * (2 * p + 1);
+  std::vector<double2> oct(8 * F1), itab((size_t)343 * F2, make_double2(0, 0)), tmp;
+  for (int o = 0; o < 8; ++o) {
+    double dx = (o & 1) ? 0.25 : -0.25, dy = ((o >> 1) & 1) ? 0.25 : -0.25, dz = ((o >> 2) & 1) ? 0.25 : -0.25;
+    host_regular(dx, dy, dz, p, tmp);
+    std::copy(tmp.begin(), tmp.end(), oct.begin() + (size_t)o * F1);
+  }
+  for (int tx = -3; tx <= 3; ++tx)
+    for (int ty = -3; ty <= 3; ++ty)
+      for (int tz = -3; tz <= 3; ++tz) {
+        if (std::abs(tx) <= 1 && std::abs(ty) <= 1 && std::abs(tz) <= 1) continue;
+        int o = (tx + 3) * 49 + (ty + 3) * 7 + (tz + 3);
+        host_irregular(tx, ty, tz, 2 * p, tmp);
+        std::copy(tmp.begin(), tmp.end(), itab.begin() + (size_t)o * F2);
+      }
+  RPY_HIP(hipMalloc(&tb->oct, sizeof(double2) * oct.size()));
+  RPY_HIP(hipMalloc(&tb->itab, sizeof(double2) * itab.size()));
+  tb->bytes = sizeof(double2) * (oct.size() + itab.size());
+  RPY_HIP(hipMemcpyAsync(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice, s));
+  RPY_HIP(hipMemcpyAsync(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice, s));
+  RPY_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+void free_tables(Tables* tb) {
+  if (tb->oct) (void)hipFree(tb->oct);
+  if (tb->itab) (void)hipFree(tb->itab);
+  tb->oct = tb->itab = nullptr;
+}
+
+// ------------------------------------------------------------- permutes ----
+__global__ void k_permute_forces(const double* F, const int* perm, int64_t n, int r0, int nrc, double* sF) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = perm[i];
+  for (int r = 0; r < nrc; ++r) {
+    const double* f = F + ((int64_t)(r0 + r) * n + j) * 3;
+    for (int k = 0; k < 3; ++k) sF[((int64_t)r * 3 + k) * n + i] = f[k];
+  }
+}
+
+__global__ void k_unpermute(const double* u, const int* perm, int64_t n, int r0, int nrc, double* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = perm[i];
+  for (int r = 0; r < nrc; ++r) {
+    double* o = out + ((int64_t)(r0 + r) * n + j) * 3;
+    for (int k = 0; k < 3; ++k) o[k] = u[((int64_t)r * 3 + k) * n + i];
+  }
+}
+
+hipError_t permute_forces(const Launch& l, const double* F, int nrhs_total, int r0, int nrc, double* sF) {
+  (void)nrhs_total;
+  int64_t n = l.B->n;
+  if (n == 0) return hipSuccess;
+  k_permute_forces<<<nblk(n, 256), 256, 0, l.s>>>(F, l.B->perm, n, r0, nrc, sF);
+  return hipGetLastError();
+}
+
+hipError_t unpermute_velocities(const Launch& l, const double* u, int r0, int nrc, double* out) {
+  int64_t n = l.B->n;
+  if (n == 0) return hipSuccess;
+  k_unpermute<<<nblk(n, 256), 256, 0, l.s>>>(u, l.B->perm, n, r0, nrc, out);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------------------- S->M, S->L ---
+// One block per box.  Beads are taken CH at a time: their harmonics go to
+// LDS column by column, then thread t accumulates coefficient t of every
+// density.  LOCAL = false: multipole of the box's own beads (S->M, written);
+// LOCAL = true: local expansion from the beads of the box's X list (S->L,
+// added).
+constexpr int P2E_T = 256;
+constexpr int P2E_CH = 16;
+
+template <int ND, bool LOCAL>
+__global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, List X, const double* sx,
+                                               const double* sy, const double* sz, const double* sF, int64_t n,
+                                               double2* E) {
+  constexpr int NRC = ND / 4;
+  const int T = ncoef(p);
+  const int b = ids ? ids[blockIdx.x] : blockIdx.x;
+  int s0 = 0, s1 = 1;
+  if (LOCAL) {
+    s0 = X.off[b];
+    s1 = X.off[b + 1];
+    if (s0 == s1) return;
+  }
+  __shared__ double2 H[P2E_CH * ncoef(MAX_ORDER)];
+  __shared__ double q[P2E_CH][ND];
+  __shared__ double xi[P2E_CH][3];
+  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
+  double2 acc[ND];
+  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  for (int si = s0; si < s1; ++si) {
+    const int C = LOCAL ? X.ent[si] : b;
+    const int j0 = t.begin[C], j1 = t.end[C];
+    for (int jc = j0; jc < j1; jc += P2E_CH) {
+      const int nb = min(P2E_CH, j1 - jc);
+      __syncthreads();
+      if (threadIdx.x < nb) {
+        int j = jc + threadIdx.x;
+        double dx = sx[j] - cx, dy = sy[j] - cy, dz = sz[j] - cz;
+        xi[threadIdx.x][0] = dx * ih; xi[threadIdx.x][1] = dy * ih; xi[threadIdx.x][2] = dz * ih;
+        for (int r = 0; r < NRC; ++r) {
+          double fx = sF[((int64_t)r * 3 + 0) * n + j], fy = sF[((int64_t)r * 3 + 1) * n + j],
+                 fz = sF[((int64_t)r * 3 + 2) * n + j];
+          q[threadIdx.x][4 * r] = fx; q[threadIdx.x][4 * r + 1] = fy; q[threadIdx.x][4 * r + 2] = fz;
+          q[threadIdx.x][4 * r + 3] = fx * dx + fy * dy + fz * dz;
+        }
+      }
+      __syncthreads();
+      for (int w = threadIdx.x; w < nb * (p + 1); w += P2E_T) {
+        int bj = w / (p + 1), m = w % (p + 1);
+        if (LOCAL) irregular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, H + bj * T);
+        else regular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, H + bj * T);
+      }
+      __syncthreads();
+      if (threadIdx.x < T) {
+        for (int bj = 0; bj < nb; ++bj) {
+          double2 hv = H[bj * T + threadIdx.x];
+          hv.y = -hv.y;  // conjugate
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            acc[d].x = fma(q[bj][d], hv.x, acc[d].x);
+            acc[d].y = fma(q[bj][d], hv.y, acc[d].y);
+          }
+        }
+      }
+    }
+  }
+  if (threadIdx.x < T) {
+    double2* out = E + (int64_t)b * ND * T + threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      if (LOCAL) {
+        double2 v = out[d * T];
+        out[d * T] = make_double2(v.x + acc[d].x, v.y + acc[d].y);
+      } else {
+        out[d * T] = acc[d];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ M->M --
+// One block per parent box of one level; thread t = output coefficient (n,m):
+// M_n^m(P) = sum_{k<=n,l} 2^-k M_k^l(C) conj(R_{n-k}^{m-l}(d/h_P)).
+constexpr int TR_T = 256;
+
+template <int ND>
+__global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const double2* oct, double2* M) {
+  const int b = ls + blockIdx.x;
+  const int nc = t.nchild[b];
+  if (nc == 0) return;
+  const int T = ncoef(p), F1 = (p + 1) * (p + 1);
+  extern __shared__ double2 sm[];
+  double2* Rt = sm;        // F1
+  double2* Mc = sm + F1;   // ND * F1
+  double2 acc[ND];
+  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  int n = 0, m = 0;
+  if (threadIdx.x < T) {
+    n = (int)floor((sqrt(8.0 * threadIdx.x + 1.0) - 1.0) * 0.5);
+    while (tri(n + 1) <= (int)threadIdx.x) ++n;
+    while (tri(n) > (int)threadIdx.x) --n;
+    m = threadIdx.x - tri(n);
+  }
+  for (int C = t.child[b]; C < t.child[b] + nc; ++C) {
+    const int o = (t.ax[C] & 1) | ((t.ay[C] & 1) << 1) | ((t.az[C] & 1) << 2);
+    const double w[3] = {t.cx[C] - t.cx[b], t.cy[C] - t.cy[b], t.cz[C] - t.cz[b]};
+    __syncthreads();
+    for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
+    const double2* src = M + (int64_t)C * ND * T;
+    for (int i = threadIdx.x; i < ND * F1; i += TR_T) {
+      int d = i / F1, f = i % F1;
+      int k = (int)sqrt((double)f);
+      while (k * k > f) --k;
+      while ((k + 1) * (k + 1) <= f) ++k;
+      int l = f - k * k - k;
+      int dd = d & 3, base = d - dd;
+      double2 v = getc(src + d * T, k, l, p);
+      if (dd == 3)
+        for (int c = 0; c < 3; ++c) {
+          double2 u = getc(src + (base + c) * T, k, l, p);
+          v.x += w[c] * u.x;
+          v.y += w[c] * u.y;
+        }
+      double sc = ldexp(1.0, -k);
+      Mc[d * F1 + f] = make_double2(v.x * sc, v.y * sc);
+    }
+    __syncthreads();
+    if (threadIdx.x < T) {
+      for (int k = 0; k <= n; ++k) {
+        int j = n - k;
+        int lmin = max(-k, m - j), lmax = min(k, m + j);
+        for (int l = lmin; l <= lmax; ++l) {
+          double2 r = Rt[fidx(j, m - l)];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) cfmac(acc[d], Mc[d * F1 + fidx(k, l)], r);
+        }
+      }
+    }
+  }
+  if (threadIdx.x < T)
+    for (int d = 0; d < ND; ++d) M[(int64_t)b * ND * T + d * T + threadIdx.x] = acc[d];
+}
+
+// ------------------------------------------------------------------ L->L --
+// One block per child box of one level; thread t = output (k,l):
+// L_k^l(C) += 2^-(k+1) sum_{n>=k,m} L_n^m(P) R_{n-k}^{m-l}(d/h_P).
+template <int ND>
+__global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const double2* oct, double2* L) {
+  const int b = ls + blockIdx.x;
+  const int P = t.parent[b];
+  if (P < 0) return;
+  const int T = ncoef(p), F1 = (p + 1) * (p + 1);
+  extern __shared__ double2 sm[];
+  double2* Rt = sm;        // F1
+  double2* Lp = sm + F1;   // ND * F1
+  const int o = (t.ax[b] & 1) | ((t.ay[b] & 1) << 1) | ((t.az[b] & 1) << 2);
+  const double w[3] = {t.cx[P] - t.cx[b], t.cy[P] - t.cy[b], t.cz[P] - t.cz[b]};
+  for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
+  const double2* src = L + (int64_t)P * ND * T;
+  for (int i = threadIdx.x; i < ND * F1; i += TR_T) {
+    int d = i / F1, f = i % F1;
+    int k = (int)sqrt((double)f);
+    while (k * k > f) --k;
+    while ((k + 1) * (k + 1) <= f) ++k;
+    int l = f - k * k - k;
+    int dd = d & 3, base = d - dd;
+    double2 v = getc(src + d * T, k, l, p);
+    if (dd == 3)
+      for (int c = 0; c < 3; ++c) {
+        double2 u = getc(src + (base + c) * T, k, l, p);
+        v.x += w[c] * u.x;
+        v.y += w[c] * u.y;
+      }
+    Lp[d * F1 + f] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x >= T) return;
+  int k = 0;
+  while (tri(k + 1) <= (int)threadIdx.x) ++k;
+  const int l = threadIdx.x - tri(k);
+  double2 acc[ND];
+  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  for (int n = k; n <= p; ++n) {
+    int j = n - k;
+    int mmin = max(-n, l - j), mmax = min(n, l + j);
+    for (int m = mmin; m <= mmax; ++m) {
+      double2 r = Rt[fidx(j, m - l)];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) cfma(acc[d], Lp[d * F1 + fidx(n, m)], r);
+    }
+  }
+  const double sc = ldexp(1.0, -(k + 1));
+  double2* out = L + (int64_t)b * ND * T + threadIdx.x;
+  for (int d = 0; d < ND; ++d) {
+    double2 v = out[d * T];
+    out[d * T] = make_double2(v.x + sc * acc[d].x, v.y + sc * acc[d].y);
+  }
+}
+
+// ----------------------------------------------------------- M->L (V) -----
+// One block per target box; for every V-list source the offset table
+// I_j^mu(t) and the (re-centred) source multipole are staged in LDS and
+// thread (k,l) accumulates (-1)^l sum_{n,m} (-1)^n M_n^m I_{n+k}^{m-l}(t).
+constexpr int M2L_T = 256;
+
+template <int ND>
+__global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, const double2* itab,
+                                                     const double2* M, double2* L) {
+  const int b = blockIdx.x;
+  const int T = ncoef(p), F1 = (p + 1) * (p + 1), F2 = (2 * p + 1) * (2 * p + 1);
+  extern __shared__ double2 sm[];
+  double2* It = sm;            // F2
+  double2* Ms = sm + F2;       // ND * F1
+  int k = 0, l = 0;
+  if (threadIdx.x < T) {
+    while (tri(k + 1) <= (int)threadIdx.x) ++k;
+    l = threadIdx.x - tri(k);
+  }
+  double2 acc[ND];
+  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  const int e0 = V.off[b], e1 = V.off[b + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int S = V.ent[e];
+    const int tx = t.ax[S] - t.ax[b], ty = t.ay[S] - t.ay[b], tz = t.az[S] - t.az[b];
+    const int o = (tx + 3) * 49 + (ty + 3) * 7 + (tz + 3);
+    const double w[3] = {t.cx[S] - t.cx[b], t.cy[S] - t.cy[b], t.cz[S] - t.cz[b]};
+    __syncthreads();
+    for (int i = threadIdx.x; i < F2; i += M2L_T) It[i] = itab[(int64_t)o * F2 + i];
+    const double2* src = M + (int64_t)S * ND * T;
+    for (int i = threadIdx.x; i < ND * F1; i += M2L_T) {
+      int d = i / F1, f = i % F1;
+      int n = (int)sqrt((double)f);
+      while (n * n > f) --n;
+      while ((n + 1) * (n + 1) <= f) ++n;
+      int m = f - n * n - n;
+      int dd = d & 3, base = d - dd;
+      double2 v = getc(src + d * T, n, m, p);
+      if (dd == 3)
+        for (int c = 0; c < 3; ++c) {
+          double2 u = getc(src + (base + c) * T, n, m, p);
+          v.x += w[c] * u.x;
+          v.y += w[c] * u.y;
+        }
+      if (n & 1) { v.x = -v.x; v.y = -v.y; }
+      Ms[d * F1 + f] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < T) {
+      for (int n = 0; n <= p; ++n) {
+        const int base_i = (n + k) * (n + k) + (n + k) - l;
+        const int base_m = n * n + n;
+        for (int m = -n; m <= n; ++m) {
+          double2 iv = It[base_i + m];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) cfma(acc[d], Ms[d * F1 + base_m + m], iv);
+        }
+      }
+    }
+  }
+  if (threadIdx.x < T) {
+    const double sg = (l & 1) ? -1.0 : 1.0;
+    double2* out = L + (int64_t)b * ND * T + threadIdx.x;
+    for (int d = 0; d < ND; ++d) out[d * T] = make_double2(sg * acc[d].x, sg * acc[d].y);
+  }
+}
+
+// --------------------------------------------------------- evaluation -----
+// One block per leaf.  For every right-hand side the box's local expansion
+// (and then each W-list multipole, re-centred on this machine) is turned into
+// twelve real-symmetric derived coefficient sets in LDS:
+//   E_i  = C1 L_i + C1 d_i L4 - C2 d_i (d_x L1 + d_y L2 + d_z L3)
+//   G_ik = d_i L_k                                   (i, k in x, y, z)
+// so that eq. (2.8) at a target x reads u_i = E_i(x) - C1 sum_k (x-c)_k G_ik(x);
+// each target then sums the twelve sets against its own harmonics.
+constexpr int EV_T = 128;
+
+// Derivative of a real-symmetric set in coefficient space.  Local (regular)
+// sets: d_z C -> C_{n+1}^m, d_x -> (C_{n+1}^{m-1} - C_{n+1}^{m+1})/2,
+// d_y -> -i (C_{n+1}^{m-1} + C_{n+1}^{m+1})/2.  Multipole (irregular) sets use
+// n-1 in place of n+1 and d_z -> -C_{n-1}^m.
+__device__ inline double2 dcoef(const double2* C, int nmax, int n, int m, int axis, bool mult) {
+  int nn = mult ? n - 1 : n + 1;
+  if (axis == 2) {
+    double2 v = getc(C, nn, m, nmax);
+    return mult ? make_double2(-v.x, -v.y) : v;
+  }
+  double2 a = getc(C, nn, m - 1, nmax), b = getc(C, nn, m + 1, nmax);
+  if (axis == 0) return make_double2(0.5 * (a.x - b.x), 0.5 * (a.y - b.y));
+  return make_double2(0.5 * (a.y + b.y), -0.5 * (a.x + b.x));
+}
+
+// Build the 12 derived sets (E_x,E_y,E_z,G_xx,G_xy,G_xz,G_yx,...) of degree
+// <= nout from the four sets in src (degree <= nin).  scale = 1/h.
+__device__ void derived_sets(const double2* src, int nin, int nout, bool mult, double ih, double C1, double C2,
+                             double2* D, double2* LC, double2* G1) {
+  const int To = ncoef(nout);
+  // G1[k][i] = d_i L_k for k = 0..3 (sets of degree <= nout), and the L_C set.
+  for (int w = threadIdx.x; w < 12 * To; w += EV_T) {
+    int k = w / (3 * To), rem = w % (3 * To), i = rem / To, c = rem % To;
+    int n = 0;
+    while (tri(n + 1) <= c) ++n;
+    int m = c - tri(n);
+    G1[w] = dcoef(src + k * ncoef(nin), nin, n, m, i, mult);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < To; c += EV_T) {
+    double2 a = G1[0 * 3 * To + 0 * To + c], b = G1[1 * 3 * To + 1 * To + c], d = G1[2 * 3 * To + 2 * To + c];
+    LC[c] = make_double2(a.x + b.x + d.x, a.y + b.y + d.y);
+  }
+  __syncthreads();
+  const double ih2 = ih * ih, ih3 = ih2 * ih;
+  for (int w = threadIdx.x; w < 3 * To; w += EV_T) {
+    int i = w / To, c = w % To;
+    int n = 0;
+    while (tri(n + 1) <= c) ++n;
+    int m = c - tri(n);
+    double2 l = getc(src + i * ncoef(nin), n, m, nin);
+    double2 g4 = G1[3 * 3 * To + i * To + c];
+    double2 dc = dcoef(LC, nout, n, m, i, mult);
+    D[i * To + c] = make_double2(C1 * ih * l.x + C1 * ih2 * g4.x - C2 * ih3 * dc.x,
+                                 C1 * ih * l.y + C1 * ih2 * g4.y - C2 * ih3 * dc.y);
+  }
+  for (int w = threadIdx.x; w < 9 * To; w += EV_T) {
+    int i = w / (3 * To), rem = w % (3 * To), k = rem / To, c = rem % To;
+    double2 g = G1[k * 3 * To + i * To + c];
+    D[(3 + 3 * i + k) * To + c] = make_double2(ih2 * g.x, ih2 * g.y);
+  }
+  __syncthreads();
+}
+
+// Sum the 12 sets against the target's harmonics (regular or irregular) of
+// xi, n <= nmax, generating columns on the fly.
+template <bool MULT>
+__device__ inline void apply_sets(const double2* D, int nmax, double x, double y, double z, const double v[3],
+                                  double C1, double u[3]) {
+  const int To = ncoef(nmax);
+  double s[12];
+  for (int e = 0; e < 12; ++e) s[e] = 0.0;
+  double r2 = x * x + y * y + z * z;
+  double ir2 = MULT ? 1.0 / r2 : 0.0;
+  double2 hmm = make_double2(MULT ? sqrt(ir2) : 1.0, 0.0);
+  for (int m = 0; m <= nmax; ++m) {
+    if (m > 0) {
+      double f = MULT ? -(2 * m - 1) * ir2 : -0.5 / m;
+      hmm = make_double2(f * (x * hmm.x - y * hmm.y), f * (x * hmm.y + y * hmm.x));
+    }
+    const double wm = m ? 2.0 : 1.0;
+    double2 hm2 = make_double2(0, 0), hm1 = make_double2(0, 0);
+    for (int n = m; n <= nmax; ++n) {
+      double2 h;
+      if (n == m) {
+        h = hmm;
+      } else if (n == m + 1) {
+        double f = MULT ? (2 * m + 1) * z * ir2 : z;
+        h = make_double2(f * hmm.x, f * hmm.y);
+      } else if (MULT) {
+        double a = (2 * n - 1) * z * ir2, bb = (double)(n + m - 1) * (n - m - 1) * ir2;
+        h = make_double2(a * hm1.x - bb * hm2.x, a * hm1.y - bb * hm2.y);
+      } else {
+        double inv = 1.0 / ((double)(n + m) * (n - m));
+        double a = (2 * n - 1) * z * inv, bb = r2 * inv;
+        h = make_double2(a * hm1.x - bb * hm2.x, a * hm1.y - bb * hm2.y);
+      }
+      hm2 = hm1;
+      hm1 = h;
+      const int c = tri(n) + m;
+      const double hx = wm * h.x, hy = wm * h.y;
+#pragma unroll
+      for (int e = 0; e < 12; ++e) {
+        double2 q = D[e * To + c];
+        s[e] = fma(q.x, hx, fma(-q.y, hy, s[e]));
+      }
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    double t = s[i];
+    for (int k = 0; k < 3; ++k) t -= C1 * v[k] * s[3 + 3 * i + k];
+    u[i] += t;
+  }
+}
+
+template <int NRC>
+__global__ void __launch_bounds__(EV_T) k_eval(int p, const int* leaves, Tree t, List W, const double* sx,
+                                               const double* sy, const double* sz, int64_t n, const double2* M,
+                                               const double2* L, double C1, double C2, double* u) {
+  constexpr int ND = 4 * NRC;
+  const int b = leaves[blockIdx.x];
+  const int T = ncoef(p), Tw = ncoef(p + 2);
+  extern __shared__ double2 sm[];
+  double2* D = sm;                 // 12 * Tw
+  double2* G1 = D + 12 * Tw;       // 12 * Tw
+  double2* LC = G1 + 12 * Tw;      // Tw
+  double2* src = LC + Tw;          // 4 * T
+  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], h = t.h[b];
+  const int j0 = t.begin[b], j1 = t.end[b];
+  for (int r = 0; r < NRC; ++r) {
+    // local expansion of this box
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * T; i += EV_T) src[i] = L[(int64_t)b * ND * T + (4 * r) * T + i];
+    __syncthreads();
+    derived_sets(src, p, p, false, 1.0 / h, C1, C2, D, LC, G1);
+    for (int j = j0 + threadIdx.x; j < j1; j += EV_T) {
+      double v[3] = {sx[j] - cx, sy[j] - cy, sz[j] - cz};
+      double uu[3] = {0, 0, 0};
+      apply_sets<false>(D, p, v[0] / h, v[1] / h, v[2] / h, v, C1, uu);
+      for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[k];
+    }
+    // W list: multipoles evaluated directly at this leaf's targets.
+    for (int e = W.off[b]; e < W.off[b + 1]; ++e) {
+      const int C = W.ent[e];
+      const double hc = t.h[C];
+      const double w[3] = {t.cx[C] - cx, t.cy[C] - cy, t.cz[C] - cz};
+      __syncthreads();
+      for (int i = threadIdx.x; i < 4 * T; i += EV_T) {
+        int d = i / T, c = i % T;
+        double2 v = M[(int64_t)C * ND * T + (4 * r + d) * T + c];
+        if (d == 3)
+          for (int k = 0; k < 3; ++k) {
+            double2 q = M[(int64_t)C * ND * T + (4 * r + k) * T + c];
+            v.x += w[k] * q.x;
+            v.y += w[k] * q.y;
+          }
+        src[i] = v;
+      }
+      __syncthreads();
+      derived_sets(src, p, p + 2, true, 1.0 / hc, C1, C2, D, LC, G1);
+      for (int j = j0 + threadIdx.x; j < j1; j += EV_T) {
+        double v[3] = {sx[j] - cx, sy[j] - cy, sz[j] - cz};
+        double xc = (sx[j] - t.cx[C]) / hc, yc = (sy[j] - t.cy[C]) / hc, zc = (sz[j] - t.cz[C]) / hc;
+        double uu[3] = {0, 0, 0};
+        apply_sets<true>(D, p + 2, xc, yc, zc, v, C1, uu);
+        for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[k];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ launchers ---
+#define DISPATCH_ND(nrc, KERNEL_CALL)               \
+  switch (nrc) {                                    \
+    case 1: { constexpr int ND = 4; KERNEL_CALL; break; }  \
+    case 2: { constexpr int ND = 8; KERNEL_CALL; break; }  \
+    case 4: { constexpr int ND = 16; KERNEL_CALL; break; } \
+    default: return hipErrorInvalidValue;           \
+  }
+
+hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e) {
+  const Built* B = l.B;
+  if (B->nleaf == 0) return hipSuccess;
+  DISPATCH_ND(nrc, (k_p2e<ND, false><<<B->nleaf, P2E_T, 0, l.s>>>(l.p, B->leaf_ids, B->tree, B->lists[LX], B->sx,
+                                                                   B->sy, B->sz, sF, B->n, e.M)));
+  return hipGetLastError();
+}
+
+hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
+  const Built* B = l.B;
+  if (B->lists[LX].len == 0) return hipSuccess;
+  DISPATCH_ND(nrc, (k_p2e<ND, true><<<B->tree.nbox, P2E_T, 0, l.s>>>(l.p, nullptr, B->tree, B->lists[LX], B->sx,
+                                                                      B->sy, B->sz, sF, B->n, e.L)));
+  return hipGetLastError();
+}
+
+hipError_t run_m2m(const Launch& l, int nrc, Exp e) {
+  const Built* B = l.B;
+  for (int lev = B->depth - 1; lev >= 0; --lev) {
+    int ls = B->level_start[lev], le = B->level_start[lev + 1];
+    size_t shm = sizeof(double2) * (1 + 4 * nrc) * (l.p + 1) * (l.p + 1);
+    DISPATCH_ND(nrc, (k_m2m<ND><<<le - ls, TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_m2l(const Launch& l, int nrc, Exp e) {
+  const Built* B = l.B;
+  const int p = l.p;
+  size_t shm = sizeof(double2) * ((2 * p + 1) * (2 * p + 1) + 4 * nrc * (p + 1) * (p + 1));
+  DISPATCH_ND(nrc, (k_m2l_dense<ND><<<B->tree.nbox, M2L_T, shm, l.s>>>(p, B->tree, B->lists[LV], l.tb->itab, e.M,
+                                                                       e.L)));
+  return hipGetLastError();
+}
+
+hipError_t run_l2l(const Launch& l, int nrc, Exp e) {
+  const Built* B = l.B;
+  for (int lev = 2; lev <= B->depth; ++lev) {
+    int ls = B->level_start[lev], le = B->level_start[lev + 1];
+    size_t shm = sizeof(double2) * (1 + 4 * nrc) * (l.p + 1) * (l.p + 1);
+    DISPATCH_ND(nrc, (k_l2l<ND><<<le - ls, TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u) {
+  const Built* B = l.B;
+  if (B->nleaf == 0) return hipSuccess;
+  const int p = l.p;
+  const double C1 = 1.0 / (8.0 * PI * l.eta), C2 = l.a * l.a / (12.0 * PI * l.eta);
+  size_t shm = sizeof(double2) * (25 * ncoef(p + 2) + 4 * ncoef(p));
+  switch (nrc) {
+    case 1: k_eval<1><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
+    case 2: k_eval<2><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
+    case 4: k_eval<4><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rpy

@@ -1,0 +1,195 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+  * tree, permutation and U/V/W/X/O lists: bit-exact (integers);
+  * a single-leaf plan is the direct sum:           rel-L2 <= 1e-12 vs O1;
+  * FP64 FMM vs the oracle FMM of the same order:  rel-L2 <= 1e-12 vs O4;
+  * FP64 FMM at eps vs the direct sum:             rel-L2 <= eps   vs O1;
+  * several right-hand sides equal separate calls, and the edge cases.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import gpu_matvec, log, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _tree_cases():
+    return [
+        ("uniform", W.uniform_cube(2500, 1.0, 0.01, seed=21).pos, 30, 14, 0.01),
+        ("clustered", W.clustered(3000, 12, 10.0, 0.7, 0.05, 1, seed=22).pos, 20, 14, 0.05),
+        ("deep-overlap", W.clustered(2000, 4, 50.0, 0.3, 0.5, 1, seed=23).pos, 8, 14, 0.5),
+        ("depth-capped", W.uniform_cube(1500, 1.0, 0.01, seed=24).pos, 3, 2, 0.01),
+        ("ragged-20k", W.clustered(20_011, 40, 30.0, 1.0, 0.05, 1, seed=25).pos, 33, 14, 0.05),
+    ]
+
+
+@pytest.mark.parametrize("case", _tree_cases(), ids=lambda c: c[0])
+def test_tree_and_lists_bit_exact(orc, case):
+    import paper_1711_02976_amd as R
+    name, pos, s, md, a = case
+    log(f"tree case {name} n={len(pos)} s={s} max_depth={md}")
+    ref = orc.Tree(pos, s, md, a)
+    P = R.Plan(to_dev(pos), a, 1.0, 1e-3, leaf_size=s, max_depth=md)
+    try:
+        got = P.export()
+        st = P.stats()
+    finally:
+        P.free()
+    assert st["nbox"] == ref.nbox
+    assert np.array_equal(got["keys"], ref.keys)
+    assert np.array_equal(got["perm"], ref.perm)
+    assert np.array_equal(got["boxes"], ref.boxes)
+    for L in "UVWXO":
+        assert np.array_equal(got["lists"][L][0], ref.lists[L][0]), L
+        assert np.array_equal(got["lists"][L][1], ref.lists[L][1]), L
+
+
+def test_batched_tree_matches_per_system(orc):
+    import paper_1711_02976_amd as R
+    w = W.multi_system(5, 200, 3000, 0.1, 0.5, 1, seed=41)
+    log(f"batched tree counts={w.counts}")
+    P = R.Plan(to_dev(w.pos), 0.5, 1.0, 1e-3, leaf_size=40, counts=w.counts)
+    try:
+        got = P.export()
+    finally:
+        P.free()
+    boxes = got["boxes"]
+    off = np.concatenate([[0], np.cumsum(w.counts)])
+    # per-system renumbering: GPU machines are ordered by (level, system, key)
+    for s in range(len(w.counts)):
+        ref = orc.Tree(w.pos[off[s]:off[s + 1]], 40, 14, 0.5)
+        mine = np.where((boxes[:, 4] >= off[s]) & (boxes[:, 5] <= off[s + 1]) & (boxes[:, 5] > boxes[:, 4]))[0]
+        # roots of other systems can be empty only if count is 0 (not the case here)
+        assert len(mine) == ref.nbox
+        gid2loc = {int(g): i for i, g in enumerate(mine)}
+        b = boxes[mine].copy()
+        b[:, 4:6] -= off[s]
+        b[:, 6] = [gid2loc.get(int(x), -1) for x in b[:, 6]]
+        b[:, 7] = [gid2loc.get(int(x), -1) for x in b[:, 7]]
+        assert np.array_equal(b, ref.boxes)
+        assert np.array_equal(got["perm"][off[s]:off[s + 1]] - off[s], ref.perm)
+        for L in "UVWXO":
+            goff, gent = got["lists"][L]
+            roff, rent = ref.lists[L]
+            for i, g in enumerate(mine):
+                e = [gid2loc[int(x)] for x in gent[goff[g]:goff[g + 1]]]
+                assert e == list(rent[roff[i]:roff[i + 1]]), (s, L, i)
+
+
+def test_single_leaf_is_direct(orc):
+    w = W.uniform_cube(3000, 1.0, 0.02, nrhs=2, seed=51)
+    log("single leaf n=3000")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, leaf_size=10_000)
+    assert st["nleaf"] == 1
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta)
+    assert orc.rel_l2(u, ref) <= 1e-12
+
+
+def _fmm_cases():
+    return [
+        ("uniform-p8", W.uniform_cube(6000, 1.0, 0.005, nrhs=1, seed=61), 8, 30),
+        ("uniform-p16-ragged", W.uniform_cube(4999, 1.0, 0.005, nrhs=1, seed=62), 16, 40),
+        ("clustered-p10-WX", W.clustered(5000, 15, 15.0, 1.0, 0.05, 1, seed=63), 10, 25),
+        ("overlap-p6-O", W.uniform_cube(3000, 1.0, 0.07, nrhs=2, seed=64), 6, 12),
+        ("far-origin-nrhs3", W.uniform_cube(3000, 1.0, 0.01, nrhs=3, seed=65), 9, 30),
+        ("nrhs5-chunks", W.clustered(2500, 8, 8.0, 0.8, 0.05, 5, seed=66), 7, 20),
+    ]
+
+
+@pytest.mark.parametrize("case", _fmm_cases(), ids=lambda c: c[0])
+def test_fmm_fp64_matches_oracle_fmm(orc, case):
+    name, w, p, s = case
+    pos = w.pos + (500.0 if name.startswith("far") else 0.0)
+    log(f"fmm parity {name} n={w.n} nrhs={w.nrhs} p={p} s={s}")
+    u, st = gpu_matvec(pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s)
+    ref = orc.fmm(pos, w.forces, w.a, w.eta, p, s)
+    err = orc.rel_l2(u, ref)
+    log(f"  rel-L2 vs oracle FMM = {err:.3e}; lists {st['list_len']}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_fmm_fp64_accuracy_vs_direct(orc, eps):
+    w = W.uniform_cube(20_000, 2.0, 0.01, nrhs=1, seed=71)
+    log(f"accuracy n=20000 eps={eps}")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, eps, leaf_size=60)
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta)
+    err = orc.rel_l2(u, ref)
+    log(f"  p={st['order']} rel-L2 vs direct = {err:.3e}")
+    assert err <= eps
+
+
+def test_clustered_accuracy_vs_direct(orc):
+    w = W.clustered(20_000, 30, 30.0, 1.0, 0.5, 1, seed=72)
+    log("clustered accuracy n=20000 eps=1e-6 (O list active)")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, leaf_size=40)
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta)
+    err = orc.rel_l2(u, ref)
+    log(f"  p={st['order']} lists={st['list_len']} rel-L2 = {err:.3e}")
+    assert st["list_len"]["O"] > 0
+    assert err <= 1e-6
+
+
+def test_multi_rhs_equals_separate_calls(orc):
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    w = W.uniform_cube(4000, 1.0, 0.01, nrhs=7, seed=81)
+    log("nrhs=7 vs 7 single calls")
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6, leaf_size=40)
+    try:
+        F = to_dev(w.forces)
+        U = P.matvec(F).cpu().numpy()
+        for r in range(7):
+            ur = P.matvec(F[r]).cpu().numpy()
+            assert orc.rel_l2(ur, U[r]) <= 1e-14
+        torch.cuda.synchronize()
+    finally:
+        P.free()
+
+
+def test_edge_cases(orc):
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    log("edge cases")
+    # n = 0: valid, no-op
+    P = R.Plan(torch.zeros((0, 3), dtype=torch.float64, device="cuda"), 0.5)
+    P.matvec(torch.zeros((1, 0, 3), dtype=torch.float64, device="cuda"))
+    P.free()
+    # n = 1: F / (6 pi eta a)
+    u, _ = gpu_matvec(np.array([[0.3, -2.0, 5.0]]), np.array([[[1.0, 2.0, -3.0]]]), 0.25, 2.0)
+    assert np.allclose(u[0, 0], np.array([1.0, 2.0, -3.0]) / (6 * np.pi * 2.0 * 0.25), rtol=1e-14)
+    # coincident beads and a max-depth leaf holding many of them
+    pos = np.repeat(np.array([[0.5, 0.5, 0.5], [0.1, 0.9, 0.3], [0.7, 0.2, 0.8]]), [300, 7, 1], axis=0)
+    F = np.random.default_rng(3).normal(size=(1, len(pos), 3))
+    u, st = gpu_matvec(pos, F, 0.05, 1.0, 1e-6, leaf_size=4)
+    ref = orc.rpy_direct(pos, F, 0.05, 1.0)
+    assert orc.rel_l2(u, ref) <= 1e-6
+    # non-finite position
+    bad = np.zeros((5, 3))
+    bad[2, 1] = np.nan
+    with pytest.raises(R.RpyError) as ei:
+        R.Plan(to_dev(bad), 0.5)
+    assert ei.value.status == R.RPY_ENONFINITE
+    with pytest.raises(R.RpyError):
+        R.Plan(to_dev(np.zeros((5, 3))), -0.5)
+
+
+def test_fullsize_cube_1M_sampled(orc):
+    """1,000,000 beads, cube side 100, a = 0.5: FP64 FMM at eps = 1e-6 against
+    the direct sum on 2,000 sampled targets."""
+    torch = torch_cuda()
+    w = W.config(2, nsample=2000)
+    log(f"full size {w.name} n={w.n} eps=1e-6")
+    import paper_1711_02976_amd as R
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6)
+    try:
+        u = P.matvec(to_dev(w.forces)).cpu().numpy()
+        st = P.stats()
+    finally:
+        P.free()
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
+    err = orc.rel_l2(u[:, w.sample], ref)
+    log(f"  p={st['order']} s={st['leaf_size']} nbox={st['nbox']} rel-L2 (2000 targets) = {err:.3e}")
+    assert err <= 1e-6
