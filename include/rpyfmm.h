@@ -56,7 +56,9 @@ typedef struct {
                             "threshold"); 0 = chosen by the library */
   int32_t order;         /* expansion order p; 0 = chosen from eps */
   int32_t max_depth;     /* deepest tree level, 1..21; 0 = 14 */
-  int32_t reserved0;
+  int32_t m2l_mode;      /* multipole-to-local operator: 0 = library choice,
+                            1 = dense O(p^4) translation, 2 = rotation to the
+                            z axis, O(p^3) */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
 } rpy_options;
 

@@ -22,17 +22,26 @@ rpy_status fail(rpy_status s, const std::string& msg) {
   return s;
 }
 
-// Smallest expansion order whose measured far-field relative L2 error on
-// uniform and clustered calibration inputs stays below eps/2 (the accuracy
-// to order map is not given in the paper; Sec. 4.3 reports 3, 6 and 9
-// digits with refinement limits 80, 100 and 120).
-int order_for_eps(double eps) {
+// Smallest expansion order whose measured relative L2 error against the
+// direct sum stays below eps/2 on calibration inputs (the accuracy-to-order
+// map is not given in the paper; Sec. 4.3 reports 3, 6 and 9 digits with
+// refinement limits 80, 100 and 120).  Level-uniform trees (no W/X lists)
+// converge faster than adaptive ones, whose W and X interactions have a
+// worse separation ratio: measured on a uniform cube, p = 7 gives 2.2e-4 and
+// p = 16 gives 4.0e-7; on Gaussian blobs p = 12, 16, 20 give 3.2e-5, 2.6e-6
+// and 2.8e-7.
+int order_for_eps(double eps, bool adaptive) {
   static const double tol[] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7,
                                3e-8, 1e-8, 1e-9};
   static const int ord[] = {2, 3, 4, 6, 7, 8, 10, 11, 13, 14, 16, 17, 19, 20, 21, 21};
+  int p = rpy::MAX_ORDER;
   for (int i = 0; i < (int)(sizeof(tol) / sizeof(tol[0])); ++i)
-    if (eps >= tol[i]) return ord[i];
-  return rpy::MAX_ORDER;
+    if (eps >= tol[i]) {
+      p = ord[i];
+      break;
+    }
+  if (adaptive) p += (p - 4 + 1) / 3;
+  return std::min(p, rpy::MAX_ORDER);
 }
 
 }  // namespace
@@ -41,7 +50,7 @@ struct rpy_plan_s {
   rpy::Built B;
   rpy::Tables tb{};
   rpy::Tiles tiles{};
-  int p = 0, leaf_size = 0, max_depth = 14, precision = 0;
+  int p = 0, leaf_size = 0, max_depth = 14, precision = 0, m2l_mode = 2;
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
   int sticky = 0;
@@ -175,6 +184,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.leaf_size < 0) return fail(RPY_EINVAL, "leaf_size must be >= 0");
   if (o.max_depth == 0) o.max_depth = 14;
   if (o.max_depth < 1 || o.max_depth > 21) return fail(RPY_EINVAL, "max_depth must be 1..21");
+  if (o.m2l_mode < 0 || o.m2l_mode > 2) return fail(RPY_EINVAL, "m2l_mode must be 0, 1 or 2");
 
   rpy_plan_t* P = new rpy_plan_t();
   P->a = a;
@@ -182,15 +192,20 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   P->eps = eps;
   P->precision = o.precision;
   P->stream = (hipStream_t)o.stream;
-  P->p = o.order ? o.order : order_for_eps(eps);
+  P->p = o.order;
   P->leaf_size = o.leaf_size ? o.leaf_size : 100;
   P->max_depth = o.max_depth;
+  // library choice: the dense operator measures faster than the cooperative
+  // rotation kernel for FP64 on MI355X at the orders used (see m2l_rot.hip).
+  P->m2l_mode = o.m2l_mode == 0 ? 1 : o.m2l_mode;
 
   std::vector<int64_t> sb(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) sb[s + 1] = sb[s] + counts[s];
   rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
   rpy::Error err{0, ""};
   int rc = rpy::build_tree(ba, &P->B, &err);
+  if (rc == 0 && P->p == 0)
+    P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
   if (rc != 0) {
@@ -237,7 +252,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_overlap(l, P->tiles, c, P->sF, P->u); });
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, [&] { return rpy::run_p2m(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, [&] { return rpy::run_m2m(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] { return rpy::run_m2l(l, c, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] { return P->m2l_mode == 1 ? rpy::run_m2l(l, c, e) : rpy::run_m2l_rot(l, c, e, mixed); });
     if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, [&] { return rpy::run_p2l(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, [&] { return rpy::run_l2l(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, [&] { return rpy::run_eval(l, c, e, P->u); });

@@ -23,6 +23,13 @@ struct Tables {
   int p;
   double2* oct;    // [8][(p+1)^2] R_j^mu(d/h_parent), d = child - parent centre
   double2* itab;   // [343][(2p+1)^2] I_j^mu(t), t integer offset in box units
+  // Rotation-based M->L: the real rotation by +90 degrees about y for every
+  // degree n <= p, split for real-symmetric coefficient sets into
+  // rot[n][m][m'] = (A+, A-) with m' padded to a multiple of 4.
+  double2* rot;
+  int* rot_off;    // [p+2] start of degree n in rot
+  double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
+  int rot_len;
   int64_t bytes;
 };
 
@@ -44,7 +51,8 @@ hipError_t unpermute_velocities(const Launch& l, const double* u, int r0, int nr
 
 hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_m2m(const Launch& l, int nrc, Exp e);
-hipError_t run_m2l(const Launch& l, int nrc, Exp e);
+hipError_t run_m2l(const Launch& l, int nrc, Exp e);       // dense O(p^4)
+hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32);  // rotation, O(p^3)
 hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_l2l(const Launch& l, int nrc, Exp e);
 hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u);

@@ -153,6 +153,90 @@ void host_irregular(double x, double y, double z, int p, std::vector<double2>& o
     }
 }
 
+// Paper-normalised Y_n^m(theta, phi) = sqrt((n-m)!/(n+m)!) P_n^m(cos theta)
+// e^{i m phi}, Condon-Shortley phase in P_n^m, for 0 <= m <= n <= p.
+void host_ynm(int p, double ct, double phi, std::vector<double2>& y) {
+  y.assign(ncoef(p), make_double2(0, 0));
+  double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  std::vector<double> P(ncoef(p));
+  double pmm = 1.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) pmm *= -(2.0 * m - 1.0) * st;
+    P[tri(m) + m] = pmm;
+    if (m + 1 <= p) P[tri(m + 1) + m] = ct * (2.0 * m + 1.0) * pmm;
+    for (int n = m + 2; n <= p; ++n)
+      P[tri(n) + m] = ((2.0 * n - 1.0) * ct * P[tri(n - 1) + m] - (n + m - 1.0) * P[tri(n - 2) + m]) / (n - m);
+  }
+  for (int n = 0; n <= p; ++n) {
+    double f = 1.0;  // (n-m)!/(n+m)! built up over m
+    for (int m = 0; m <= n; ++m) {
+      if (m > 0) f /= (double)(n + m) * (n - m + 1);
+      double c = std::sqrt(f) * P[tri(n) + m];
+      y[tri(n) + m] = make_double2(c * std::cos(m * phi), c * std::sin(m * phi));
+    }
+  }
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration).
+void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(N, 0.0);
+  w.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (N + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= N; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = N == 1 ? z : p1, pm = N == 1 ? 1.0 : p0;
+      dp = N * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// The rotation by +90 degrees about y acting on degree-n coefficient sets:
+// D[m'][m] (m', m in -n..n) such that f(R^-1 x) = sum_{m'} (D c)_{m'} Y_n^{m'}
+// for f = sum_m c_m Y_n^m, by quadrature exact for degree 2n
+// (D = (2n+1)/(4 pi) * integral conj(Y^{m'}) Y^m(R^-1 x)).  Real orthogonal.
+void host_rot90(int n, std::vector<double>& D) {
+  const int W = 2 * n + 1;
+  D.assign((size_t)W * W, 0.0);
+  std::vector<double> gx, gw;
+  gauss_legendre(n + 1, gx, gw);
+  const int nphi = 2 * n + 1;
+  std::vector<double2> y, yr;
+  for (int i = 0; i <= n; ++i) {
+    double ct = gx[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+    for (int k = 0; k < nphi; ++k) {
+      double ph = 2.0 * M_PI * k / nphi;
+      double x = st * std::cos(ph), yv = st * std::sin(ph), z = ct;
+      // R^-1 x for R = rotation by +pi/2 about y: (x, y, z) -> (-z, y, x)
+      double xr = -z, yy = yv, zr = x;
+      double ctr = std::max(-1.0, std::min(1.0, zr)), phr = std::atan2(yy, xr);
+      host_ynm(n, ct, ph, y);
+      host_ynm(n, ctr, phr, yr);
+      double wt = gw[i] * (2.0 * M_PI / nphi) * (2 * n + 1) / (4.0 * M_PI);
+      for (int mp = -n; mp <= n; ++mp) {
+        double2 a = y[tri(n) + std::abs(mp)];
+        if (mp < 0) a.y = -a.y;
+        for (int m = -n; m <= n; ++m) {
+          double2 b = yr[tri(n) + std::abs(m)];
+          if (m < 0) b.y = -b.y;
+          // Re(conj(a) b)
+          D[(size_t)(mp + n) * W + (m + n)] += wt * (a.x * b.x + a.y * b.y);
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
@@ -173,19 +257,54 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
         host_irregular(tx, ty, tz, 2 * p, tmp);
         std::copy(tmp.begin(), tmp.end(), itab.begin() + (size_t)o * F2);
       }
+  // rotation tables
+  std::vector<int> roff(p + 2, 0);
+  for (int n = 0; n <= p; ++n) roff[n + 1] = roff[n] + (n + 1) * (4 * ((n + 4) / 4));
+  std::vector<double2> rot(roff[p + 1], make_double2(0, 0));
+  std::vector<double> D;
+  for (int n = 0; n <= p; ++n) {
+    host_rot90(n, D);
+    const int W = 2 * n + 1, pad = 4 * ((n + 4) / 4);
+    for (int m = 0; m <= n; ++m)
+      for (int mp = 0; mp <= n; ++mp) {
+        double dp = D[(size_t)(mp + n) * W + (m + n)], dm = D[(size_t)(mp + n) * W + (n - m)];
+        double2 v = m == 0 ? make_double2(dp, 0.0) : make_double2(dp + dm, dp - dm);
+        rot[roff[n] + m * pad + mp] = v;
+      }
+  }
+  std::vector<double> sf(ncoef(p));
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      double f = 1.0;
+      for (int k = 2; k <= n - m; ++k) f *= k;
+      double g = 1.0;
+      for (int k = 2; k <= n + m; ++k) g *= k;
+      sf[tri(n) + m] = std::sqrt(f * g);
+    }
+  tb->rot_len = roff[p + 1];
   RPY_HIP(hipMalloc(&tb->oct, sizeof(double2) * oct.size()));
   RPY_HIP(hipMalloc(&tb->itab, sizeof(double2) * itab.size()));
-  tb->bytes = sizeof(double2) * (oct.size() + itab.size());
-  RPY_HIP(hipMemcpyAsync(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice, s));
-  RPY_HIP(hipMemcpyAsync(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice, s));
-  RPY_HIP(hipStreamSynchronize(s));
+  RPY_HIP(hipMalloc(&tb->rot, sizeof(double2) * rot.size()));
+  RPY_HIP(hipMalloc(&tb->rot_off, sizeof(int) * roff.size()));
+  RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
+  tb->bytes = sizeof(double2) * (oct.size() + itab.size() + rot.size()) + sizeof(int) * roff.size() +
+              sizeof(double) * sf.size();
+  RPY_HIP(hipMemcpy(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->rot, rot.data(), sizeof(double2) * rot.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->rot_off, roff.data(), sizeof(int) * roff.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->sfac, sf.data(), sizeof(double) * sf.size(), hipMemcpyHostToDevice));
+  (void)s;
   return 0;
 }
 
 void free_tables(Tables* tb) {
-  if (tb->oct) (void)hipFree(tb->oct);
-  if (tb->itab) (void)hipFree(tb->itab);
-  tb->oct = tb->itab = nullptr;
+  void* ps[] = {tb->oct, tb->itab, tb->rot, tb->rot_off, tb->sfac};
+  for (void* q : ps)
+    if (q) (void)hipFree(q);
+  tb->oct = tb->itab = tb->rot = nullptr;
+  tb->rot_off = nullptr;
+  tb->sfac = nullptr;
 }
 
 // ------------------------------------------------------------- permutes ----

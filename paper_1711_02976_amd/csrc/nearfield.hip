@@ -64,52 +64,45 @@ int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err) 
 struct RpyConst {
   double c0;      // 1/(6 pi eta a): self mobility
   double c1;      // 1/(8 pi eta)
-  double twoa2_3; // 2a^2/3
-  double twoa2;   // 2a^2
+  double c1a3;    // c1 * 2a^2/3
+  double c1a2;    // c1 * 2a^2
   double four_a2; // (2a)^2
   double k9;      // 9/(32a)
-  double k3;      // 3/(32a)
+  double c0k3;    // c0 * 3/(32a)
 };
 
-__device__ inline void rpy_coef(double r2, const RpyConst& k, double& A, double& B) {
-  // 1/r from a single-precision estimate refined by two Newton steps.
-  float r2f = (float)r2;
-  double y = (double)__builtin_amdgcn_rsqf(r2f);
+// 1/r from the single-precision estimate refined by one Newton step
+// (relative error below 2^-44); 0 for coincident beads (r^2 < 1e-30).
+__device__ inline double rinv64(double r2) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r2);
   y = y * fma(-0.5 * r2, y * y, 1.5);
-  y = y * fma(-0.5 * r2, y * y, 1.5);
-  const bool coinc = r2 < 1e-30;
-  const double rinv = coinc ? 0.0 : y;
-  const double ri2 = rinv * rinv;
-  const double Af = k.c1 * rinv * fma(k.twoa2_3, ri2, 1.0);
-  const double Bf = k.c1 * rinv * ri2 * fma(-k.twoa2, ri2, 1.0);
-  const double r = r2 * rinv;
-  const double Ao = k.c0 * fma(-k.k9, r, 1.0);
-  const double Bo = k.c0 * k.k3 * rinv;
-  const bool ov = r2 < k.four_a2;
-  A = ov ? Ao : Af;
-  B = ov ? Bo : Bf;
+  return r2 < 1e-30 ? 0.0 : y;
 }
 
-__device__ inline void rpy_coef_f(float r2, float c0, float c1, float ta3, float ta, float fa2, float k9, float k3,
-                                  float& A, float& B) {
-  const bool coinc = r2 < 1e-30f;
-  const float rinv = coinc ? 0.0f : __builtin_amdgcn_rsqf(r2);
-  const float ri2 = rinv * rinv;
-  const float Af = c1 * rinv * fmaf(ta3, ri2, 1.0f);
-  const float Bf = c1 * rinv * ri2 * fmaf(-ta, ri2, 1.0f);
-  const float r = r2 * rinv;
-  const float Ao = c0 * fmaf(-k9, r, 1.0f);
-  const float Bo = c0 * k3 * rinv;
-  const bool ov = r2 < fa2;
-  A = ov ? Ao : Af;
-  B = ov ? Bo : Bf;
+// Far (r >= 2a) block: A = c1/r (1 + 2a^2/(3r^2)), B = c1/r^3 (1 - 2a^2/r^2).
+__device__ inline void rpy_far(double rinv, const RpyConst& k, double& A, double& B) {
+  const double ri2 = rinv * rinv, ri3 = ri2 * rinv;
+  A = fma(k.c1a3, ri3, k.c1 * rinv);
+  B = fma(-k.c1a2 * ri2, ri3, k.c1 * ri3);
 }
+
+// Overlap (r < 2a) block: A = c0 (1 - 9r/(32a)), B = c0 3/(32a) / r.
+__device__ inline void rpy_overlap(double r2, double rinv, const RpyConst& k, double& A, double& B) {
+  A = k.c0 * fma(-k.k9, r2 * rinv, 1.0);
+  B = k.c0k3 * rinv;
+}
+
+struct RpyConstF {
+  float c0, c1, c1a3, c1a2, four_a2, k9, c0k3;
+};
 
 // --------------------------------------------------------------- P2P -----
+// The overlap formula is evaluated only when some lane of the wave has a
+// source closer than 2a (a wave-uniform branch), since such pairs are rare.
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
-                                               RpyConst k, double* u) {
+                                               RpyConst k, RpyConstF kf, double* u) {
   __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ double fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
@@ -119,8 +112,6 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   const double xi = sx[i], yi = sy[i], zi = sz[i];
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
-  const float c0f = (float)k.c0, c1f = (float)k.c1, ta3 = (float)k.twoa2_3, ta = (float)k.twoa2,
-              fa2 = (float)k.four_a2, k9f = (float)k.k9, k3f = (float)k.k3;
   for (int e = U.off[b]; e < U.off[b + 1]; ++e) {
     const int C = U.ent[e];
     const int j1 = t.end[C];
@@ -136,11 +127,20 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       if (MIXED) {
         float af[NRC][3];
         for (int r = 0; r < NRC; ++r) af[r][0] = af[r][1] = af[r][2] = 0.0f;
+#pragma unroll 2
         for (int s = 0; s < ns; ++s) {
           const float dx = (float)(xi - xs[s]), dy = (float)(yi - ys[s]), dz = (float)(zi - zs[s]);
           const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          float A, B;
-          rpy_coef_f(r2, c0f, c1f, ta3, ta, fa2, k9f, k3f, A, B);
+          const float rinv = r2 < 1e-30f ? 0.0f : __builtin_amdgcn_rsqf(r2);
+          const float ri2 = rinv * rinv, ri3 = ri2 * rinv;
+          float A = fmaf(kf.c1a3, ri3, kf.c1 * rinv);
+          float B = fmaf(-kf.c1a2 * ri2, ri3, kf.c1 * ri3);
+          const bool ov = r2 < kf.four_a2;
+          if (__builtin_expect(__any(ov), 0)) {
+            const float Ao = kf.c0 * fmaf(-kf.k9, r2 * rinv, 1.0f), Bo = kf.c0k3 * rinv;
+            A = ov ? Ao : A;
+            B = ov ? Bo : B;
+          }
 #pragma unroll
           for (int r = 0; r < NRC; ++r) {
             const float fx = (float)fs[3 * r][s], fy = (float)fs[3 * r + 1][s], fz = (float)fs[3 * r + 2][s];
@@ -153,11 +153,20 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
         for (int r = 0; r < NRC; ++r)
           for (int c = 0; c < 3; ++c) acc[r][c] += (double)af[r][c];
       } else {
+#pragma unroll 2
         for (int s = 0; s < ns; ++s) {
           const double dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
           const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const double rinv = rinv64(r2);
           double A, B;
-          rpy_coef(r2, k, A, B);
+          rpy_far(rinv, k, A, B);
+          const bool ov = r2 < k.four_a2;
+          if (__builtin_expect(__any(ov), 0)) {
+            double Ao, Bo;
+            rpy_overlap(r2, rinv, k, Ao, Bo);
+            A = ov ? Ao : A;
+            B = ov ? Bo : B;
+          }
 #pragma unroll
           for (int r = 0; r < NRC; ++r) {
             const double fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
@@ -206,9 +215,11 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, Tree t, Li
         const double dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         if (!(r2 < k.four_a2) || r2 < 1e-30) continue;
-        const double rinv = 1.0 / sqrt(r2), ri2 = rinv * rinv, r = r2 * rinv;
-        const double A = k.c0 * fma(-k.k9, r, 1.0) - k.c1 * rinv * fma(k.twoa2_3, ri2, 1.0);
-        const double B = k.c0 * k.k3 * rinv - k.c1 * rinv * ri2 * fma(-k.twoa2, ri2, 1.0);
+        const double rinv = 1.0 / sqrt(r2);
+        double Af, Bf, Ao, Bo;
+        rpy_far(rinv, k, Af, Bf);
+        rpy_overlap(r2, rinv, k, Ao, Bo);
+        const double A = Ao - Af, B = Bo - Bf;
         for (int r = 0; r < NRC; ++r) {
           const double fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
           const double sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
@@ -228,24 +239,30 @@ static RpyConst rpy_const(double a, double eta) {
   RpyConst k;
   k.c0 = 1.0 / (6.0 * PI * eta * a);
   k.c1 = 1.0 / (8.0 * PI * eta);
-  k.twoa2_3 = 2.0 * a * a / 3.0;
-  k.twoa2 = 2.0 * a * a;
+  k.c1a3 = k.c1 * 2.0 * a * a / 3.0;
+  k.c1a2 = k.c1 * 2.0 * a * a;
   k.four_a2 = 4.0 * a * a;
   k.k9 = 9.0 / (32.0 * a);
-  k.k3 = 3.0 / (32.0 * a);
+  k.c0k3 = k.c0 * 3.0 / (32.0 * a);
   return k;
+}
+
+static RpyConstF rpy_const_f(const RpyConst& k) {
+  return RpyConstF{(float)k.c0, (float)k.c1, (float)k.c1a3, (float)k.c1a2, (float)k.four_a2, (float)k.k9,
+                   (float)k.c0k3};
 }
 
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   if (tiles.n == 0) return hipSuccess;
   const Built* B = l.B;
   RpyConst k = rpy_const(l.a, l.eta);
+  RpyConstF kf = rpy_const_f(k);
 #define P2P_CASE(NR)                                                                                            \
   case NR:                                                                                                      \
     if (mixed)                                                                                                  \
-      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, u); \
+      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, kf, u); \
     else                                                                                                        \
-      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, u); \
+      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, kf, u); \
     break;
   switch (nrc) {
     P2P_CASE(1)

@@ -115,9 +115,15 @@ __global__ void __launch_bounds__(BB_T) k_bbox_partial(const double* pos, const 
   if (threadIdx.x < 6) part[((int64_t)s * nblk + blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// one block per system: reduce partials, flag non-finite coordinates.
-__global__ void k_bbox_final(const double* part, int nblk, double* out /*[nsys][6]*/, int* bad) {
+// one block per system: reduce partials, flag non-finite coordinates.  An
+// empty system gets the unit cube at the origin.
+__global__ void k_bbox_final(const double* part, int nblk, const int* sys_begin, double* out /*[nsys][6]*/,
+                             int* bad) {
   int s = blockIdx.x;
+  if (sys_begin[s] == sys_begin[s + 1]) {
+    if (threadIdx.x < 6) out[s * 6 + threadIdx.x] = 0.0;
+    return;
+  }
   __shared__ double red[6][64];
   double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   for (int i = threadIdx.x; i < nblk; i += 64)
@@ -582,7 +588,7 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
   if (dalloc(&bad, 1, B, err)) return -3;
   RPY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
   k_bbox_partial<<<dim3(nblk, nsys), BB_T, 0, s>>>(A.pos, B->d_sys_begin, nblk, part);
-  k_bbox_final<<<nsys, 64, 0, s>>>(part, nblk, bb, bad);
+  k_bbox_final<<<nsys, 64, 0, s>>>(part, nblk, B->d_sys_begin, bb, bad);
   k_check_finite<<<1024, 256, 0, s>>>(A.pos, 3 * n, bad);
   RPY_HIP(hipGetLastError());
   std::vector<double> hbb(nsys * 6);

@@ -193,3 +193,19 @@ def test_fullsize_cube_1M_sampled(orc):
     err = orc.rel_l2(u[:, w.sample], ref)
     log(f"  p={st['order']} s={st['leaf_size']} nbox={st['nbox']} rel-L2 (2000 targets) = {err:.3e}")
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("p", [4, 13, 21])
+def test_m2l_rotation_matches_dense(orc, p):
+    """The rotation-based M->L and the dense O(p^4) M->L compute the same
+    truncated operator; both match the oracle FMM."""
+    w = W.clustered(4000, 10, 10.0, 0.8, 0.05, 2, seed=91)
+    log(f"m2l modes p={p}")
+    ud, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=30, m2l="dense")
+    ur, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=30, m2l="rotation")
+    err = orc.rel_l2(ur, ud)
+    log(f"  rotation vs dense rel-L2 = {err:.3e}")
+    assert err <= 1e-12
+    if p <= 13:
+        ref = orc.fmm(w.pos, w.forces, w.a, w.eta, p, 30)
+        assert orc.rel_l2(ur, ref) <= 1e-12
