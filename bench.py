@@ -53,7 +53,14 @@ def algorithmic_counts(P, p, nrc):
     p2p_flops = pairs * (20 + 18 * nrc)
     # M2L (dense): per V pair and density, T x (p+1)^2 complex multiply-adds.
     m2l_flops = npair_v * 4 * nrc * T * (p + 1) ** 2 * 8
-    return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "m2l_flops": m2l_flops}
+    # M2L (rotation): per V pair and density, two real rotations of
+    # sum_n (2n+1)^2 multiply-adds and the z translation, sum_l (p-l+1)^2
+    # multiply-adds on the real and (l > 0) imaginary parts.
+    rot = (p + 1) * (2 * p + 1) * (2 * p + 3) // 3
+    zt = (p + 1) * (p + 2) * (2 * p + 3) // 6
+    m2l_rot_flops = npair_v * 4 * nrc * 2 * (2 * rot + 2 * zt - (p + 1))
+    return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "m2l_flops": m2l_flops,
+            "m2l_rot_flops": m2l_rot_flops}
 
 
 def traffic_for(kernel_file, launches_key):
@@ -141,9 +148,10 @@ def run(args):
         peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
         kfile = "nearfield.hip"
     else:
-        flops = r["alg"]["m2l_flops"]
-        peak = PEAK_FP64_TFLOPS
-        kfile = "fmm.hip"
+        dense = r["stats"].get("m2l_mode", 1) == 1
+        flops = r["alg"]["m2l_flops"] if dense else r["alg"]["m2l_rot_flops"]
+        peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+        kfile = "fmm.hip" if dense else "m2l_rot.hip"
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic_for(kfile, f"{dom}:{args.workload}:{best}"),
@@ -187,7 +195,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cube-1M", choices=sorted(WORKLOADS))
-    ap.add_argument("--precisions", default="fp64", help="comma list of forms to time: fp64,mixed")
+    ap.add_argument("--precisions", default="fp64,mixed", help="comma list of forms to time: fp64,mixed")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=2000)

@@ -71,7 +71,7 @@ typedef struct {
   int32_t leaf_size;     /* refinement limit in use */
   int32_t depth;         /* deepest level present */
   int32_t precision;     /* rpy_precision in use */
-  int32_t reserved0;
+  int32_t m2l_mode;      /* multipole-to-local operator in use: 1 dense, 2 rotation */
   int64_t nbox;          /* boxes (all systems) */
   int64_t nleaf;
   int64_t list_len[5];   /* entries of the U, V, W, X, O lists */

@@ -32,7 +32,7 @@ class rpy_options(C.Structure):
 
 class rpy_plan_stats_t(C.Structure):
     _fields_ = [("n", C.c_int64), ("nsys", C.c_int32), ("order", C.c_int32), ("leaf_size", C.c_int32),
-                ("depth", C.c_int32), ("precision", C.c_int32), ("reserved0", C.c_int32),
+                ("depth", C.c_int32), ("precision", C.c_int32), ("m2l_mode", C.c_int32),
                 ("nbox", C.c_int64), ("nleaf", C.c_int64), ("list_len", C.c_int64 * 5),
                 ("device_bytes", C.c_int64), ("plan_ms", C.c_double)]
 
@@ -136,7 +136,7 @@ def rpy_plan_stats(plan):
     s = rpy_plan_stats_t()
     _check(lib().rpy_plan_stats(plan, C.byref(s)))
     return {"n": s.n, "nsys": s.nsys, "order": s.order, "leaf_size": s.leaf_size, "depth": s.depth,
-            "precision": s.precision, "nbox": s.nbox, "nleaf": s.nleaf,
+            "precision": s.precision, "m2l_mode": s.m2l_mode, "nbox": s.nbox, "nleaf": s.nleaf,
             "list_len": dict(zip(LIST_NAMES, list(s.list_len))), "device_bytes": s.device_bytes,
             "plan_ms": s.plan_ms}
 

@@ -21,12 +21,28 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 arithmetic stays disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # hardware FP64 atomic add on (coarse-grained) device memory
+    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
 
-def _compile(src: str) -> str:
+HEADERS = [os.path.join(CSRC, h) for h in ("common.h", "fmm.h")]
+ABI_HEADER = os.path.join(os.path.dirname(HERE), "include", "rpyfmm.h")
+
+
+def _stale(src_path: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src_path, *HEADERS] + ([ABI_HEADER] if src_path.endswith("api.hip") else [])
+    return any(os.path.getmtime(f) > t for f in deps if os.path.exists(f))
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    if not force and not _stale(os.path.join(CSRC, src), obj):
+        return obj
     cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -36,10 +52,11 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only stale objects, then link."""
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda f: _compile(f, force), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
@@ -50,4 +67,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--incremental" not in sys.argv)

@@ -195,9 +195,10 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   P->p = o.order;
   P->leaf_size = o.leaf_size ? o.leaf_size : 100;
   P->max_depth = o.max_depth;
-  // library choice: the dense operator measures faster than the cooperative
-  // rotation kernel for FP64 on MI355X at the orders used (see m2l_rot.hip).
-  P->m2l_mode = o.m2l_mode == 0 ? 1 : o.m2l_mode;
+  // library choice: FP64 uses the dense operator (it measures faster than the
+  // cooperative rotation kernel at the orders used); the mixed form uses the
+  // rotation operator in FP32.
+  P->m2l_mode = o.m2l_mode != 0 ? o.m2l_mode : (o.precision == RPY_PREC_MIXED ? 2 : 1);
 
   std::vector<int64_t> sb(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) sb[s + 1] = sb[s] + counts[s];
@@ -208,6 +209,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
+
   if (rc != 0) {
     rpy_status st = rc == -2 ? RPY_ENONFINITE : rc == -3 ? RPY_ENOMEM : RPY_EDEVICE;
     g_last_error = err.msg;
@@ -252,7 +254,10 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_overlap(l, P->tiles, c, P->sF, P->u); });
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, [&] { return rpy::run_p2m(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, [&] { return rpy::run_m2m(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] { return P->m2l_mode == 1 ? rpy::run_m2l(l, c, e) : rpy::run_m2l_rot(l, c, e, mixed); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] {
+      if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
+      return rpy::run_m2l_rot(l, c, e, mixed);
+    });
     if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, [&] { return rpy::run_p2l(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, [&] { return rpy::run_l2l(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, [&] { return rpy::run_eval(l, c, e, P->u); });
@@ -276,6 +281,7 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   out->leaf_size = P->leaf_size;
   out->depth = P->B.depth;
   out->precision = P->precision;
+  out->m2l_mode = P->m2l_mode;
   out->nbox = P->B.tree.nbox;
   out->nleaf = P->B.nleaf;
   for (int L = 0; L < 5; ++L) out->list_len[L] = P->B.lists[L].len;

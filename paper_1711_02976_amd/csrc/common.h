@@ -56,6 +56,13 @@ struct Error {
 size_t scan_tmp_ints(int64_t n);
 hipError_t scan_exclusive(const int* in, int* out, int64_t n, int* tmp, hipStream_t s);
 
+// Stable LSD radix sort of (key, value) pairs by 8-bit digits: key_passes
+// digits of the key (least significant first), then sys_passes digits of
+// the system index of each value (for concatenated systems).  The result is
+// left in (*keys, *vals); kalt/valt are scratch of the same size.
+hipError_t radix_sort(uint64_t** keys, int** vals, uint64_t* kalt, int* valt, int64_t n, int key_passes,
+                      int sys_passes, const int* sys_begin, int nsys, hipStream_t s);
+
 // ---- tree build (tree.hip) ---------------------------------------------
 struct BuildArgs {
   int64_t n;

@@ -29,11 +29,20 @@ struct Tables {
   double2* rot;
   int* rot_off;    // [p+2] start of degree n in rot
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
+  // per integer offset t (343 slots): e^{-i m (pi/2 - phi_t)}, e^{i m theta_t}
+  // (m = 0..p, complex) and j!/|t|^{j+1} (j = 0..2p)
+  double* offtab;
   int rot_len;
   int64_t bytes;
 };
 
 int make_tables(int p, Tables* tb, hipStream_t s, Error* err);
+
+// Host helpers (fmm.hip): paper-normalised Y_n^m for 0 <= m <= n <= p at
+// (cos theta, phi); the rotation by +90 degrees about y on degree-n sets,
+// D[(m'+n)(2n+1) + (m+n)].
+void host_ynm(int p, double ct, double phi, std::vector<double2>& y);
+void host_rot90(int n, std::vector<double>& D);
 void free_tables(Tables* tb);
 
 struct Launch {

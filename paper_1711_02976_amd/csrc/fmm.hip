@@ -153,6 +153,8 @@ void host_irregular(double x, double y, double z, int p, std::vector<double2>& o
     }
 }
 
+}  // namespace
+
 // Paper-normalised Y_n^m(theta, phi) = sqrt((n-m)!/(n+m)!) P_n^m(cos theta)
 // e^{i m phi}, Condon-Shortley phase in P_n^m, for 0 <= m <= n <= p.
 void host_ynm(int p, double ct, double phi, std::vector<double2>& y) {
@@ -237,8 +239,6 @@ void host_rot90(int n, std::vector<double>& D) {
   }
 }
 
-}  // namespace
-
 int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   tb->p = p;
   tb->bytes = 0;
@@ -281,14 +281,39 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
       for (int k = 2; k <= n + m; ++k) g *= k;
       sf[tri(n) + m] = std::sqrt(f * g);
     }
+  // per-offset phases and z-translation factors of the rotation M->L
+  const int OT = 4 * (p + 1) + 2 * p + 1;
+  std::vector<double> offt((size_t)343 * OT, 0.0);
+  for (int tx = -3; tx <= 3; ++tx)
+    for (int ty = -3; ty <= 3; ++ty)
+      for (int tz = -3; tz <= 3; ++tz) {
+        if (std::abs(tx) <= 1 && std::abs(ty) <= 1 && std::abs(tz) <= 1) continue;
+        double* q = offt.data() + (size_t)((tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)) * OT;
+        const double rho = std::sqrt((double)(tx * tx + ty * ty + tz * tz));
+        const double th = std::acos(tz / rho), ph = std::atan2((double)ty, (double)tx);
+        for (int m = 0; m <= p; ++m) {
+          q[2 * m] = std::cos(m * (0.5 * M_PI - ph));
+          q[2 * m + 1] = -std::sin(m * (0.5 * M_PI - ph));
+          q[2 * (p + 1) + 2 * m] = std::cos(m * th);
+          q[2 * (p + 1) + 2 * m + 1] = std::sin(m * th);
+        }
+        double f = 1.0, rp = 1.0 / rho;
+        for (int j = 0; j <= 2 * p; ++j) {
+          if (j > 0) f *= j;
+          q[4 * (p + 1) + j] = f * rp;
+          rp /= rho;
+        }
+      }
   tb->rot_len = roff[p + 1];
   RPY_HIP(hipMalloc(&tb->oct, sizeof(double2) * oct.size()));
   RPY_HIP(hipMalloc(&tb->itab, sizeof(double2) * itab.size()));
   RPY_HIP(hipMalloc(&tb->rot, sizeof(double2) * rot.size()));
   RPY_HIP(hipMalloc(&tb->rot_off, sizeof(int) * roff.size()));
   RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
+  RPY_HIP(hipMalloc(&tb->offtab, sizeof(double) * offt.size()));
+  RPY_HIP(hipMemcpy(tb->offtab, offt.data(), sizeof(double) * offt.size(), hipMemcpyHostToDevice));
   tb->bytes = sizeof(double2) * (oct.size() + itab.size() + rot.size()) + sizeof(int) * roff.size() +
-              sizeof(double) * sf.size();
+              sizeof(double) * (sf.size() + offt.size());
   RPY_HIP(hipMemcpy(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->rot, rot.data(), sizeof(double2) * rot.size(), hipMemcpyHostToDevice));
@@ -299,12 +324,13 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
 }
 
 void free_tables(Tables* tb) {
-  void* ps[] = {tb->oct, tb->itab, tb->rot, tb->rot_off, tb->sfac};
+  void* ps[] = {tb->oct, tb->itab, tb->rot, tb->rot_off, tb->sfac, tb->offtab};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   tb->oct = tb->itab = tb->rot = nullptr;
   tb->rot_off = nullptr;
   tb->sfac = nullptr;
+  tb->offtab = nullptr;
 }
 
 // ------------------------------------------------------------- permutes ----

@@ -44,7 +44,6 @@ struct RotSmem {
   R* G;           // RC * (2p+1)
   C* E1;          // RC * (p+1)
   C* E2;          // RC * (p+1)
-  double2* Lacc;  // ND * T (FP64 sum over the V list)
   int* colS;      // RC
   int* colD;      // RC
   int* roff;      // p+2
@@ -159,16 +158,14 @@ __device__ void ztrans_step(const RotSmem<R>& sm, int p, int RC, const typename 
 template <int ND, class R>
 __global__ void __launch_bounds__(ROT_T) k_m2l_rot(int p, int RC, Tree t, List V, const double2* rot,
                                                    const int* roff, int rot_len, const double* sfac,
-                                                   const double2* M, double2* L) {
+                                                   const double* offtab, const double2* M, double2* L) {
   using C = typename V2<R>::T;
   extern __shared__ double2 smem[];
   const int b = blockIdx.x;
-  const int T = ncoef(p);
+  const int T = ncoef(p), OT = 4 * (p + 1) + 2 * p + 1;
   RotSmem<R> sm;
   {
-    double2* q = smem;
-    sm.Lacc = q; q += ND * T;
-    double* d = reinterpret_cast<double*>(q);
+    double* d = reinterpret_cast<double*>(smem);
     sm.sf = d; d += T;
     C* cq = reinterpret_cast<C*>(d);
     sm.rot = cq; cq += rot_len;
@@ -191,50 +188,37 @@ __global__ void __launch_bounds__(ROT_T) k_m2l_rot(int p, int RC, Tree t, List V
   }
   for (int i = threadIdx.x; i < T; i += ROT_T) sm.sf[i] = sfac[i];
   for (int i = threadIdx.x; i < p + 2; i += ROT_T) sm.roff[i] = roff[i];
-  for (int i = threadIdx.x; i < ND * T; i += ROT_T) sm.Lacc[i] = make_double2(0, 0);
+  double2* Lb = L + (int64_t)b * ND * T;
+  for (int i = threadIdx.x; i < ND * T; i += ROT_T) Lb[i] = make_double2(0, 0);
   const int e0 = V.off[b], e1 = V.off[b + 1];
   const int ncols = (e1 - e0) * ND;
   for (int c0 = 0; c0 < ncols; c0 += RC) {
     __syncthreads();
-    // column geometry: offset in box units, phases and the z-translation factors
     if ((int)threadIdx.x < RC) {
       const int c = threadIdx.x, gc = c0 + c;
-      int S = -1, d = 0;
-      if (gc < ncols) {
-        S = V.ent[e0 + gc / ND];
-        d = gc % ND;
-      }
-      sm.colS[c] = S;
-      sm.colD[c] = d;
-      double tx = 1, ty = 0, tz = 0;
-      if (S >= 0) {
-        tx = t.ax[S] - t.ax[b];
-        ty = t.ay[S] - t.ay[b];
-        tz = t.az[S] - t.az[b];
-      }
-      double rho = sqrt(tx * tx + ty * ty + tz * tz);
-      double th = acos(tz / rho), ph = atan2(ty, tx);
-      double fac = 1.0, ir = 1.0 / rho, rp = ir;
-      R* G = sm.G + c * (2 * p + 1);
-      for (int j = 0; j <= 2 * p; ++j) {
-        if (j > 0) fac *= j;
-        G[j] = (R)(fac * rp);
-        rp *= ir;
-      }
-      const double a1 = 0.5 * M_PI - ph;
-      for (int m = 0; m <= p; ++m) {
-        double s1, c1, s2, c2;
-        sincos(m * a1, &s1, &c1);
-        sincos(m * th, &s2, &c2);
-        C e1, e2;
-        e1.x = (R)c1; e1.y = (R)-s1;  // e^{-i m (pi/2 - phi)}
-        e2.x = (R)c2; e2.y = (R)s2;   // e^{+i m theta}
-        sm.E1[c * (p + 1) + m] = e1;
-        sm.E2[c * (p + 1) + m] = e2;
+      sm.colS[c] = gc < ncols ? V.ent[e0 + gc / ND] : -1;
+      sm.colD[c] = gc % ND;
+    }
+    __syncthreads();
+    // per-column phases and translation factors from the offset tables
+    const int per = 2 * (p + 1) + 2 * (p + 1) + 2 * p + 1;
+    for (int i = threadIdx.x; i < RC * per; i += ROT_T) {
+      const int c = i / per, k = i % per;
+      const int S = sm.colS[c] >= 0 ? sm.colS[c] : V.ent[e0];
+      const int o = (t.ax[S] - t.ax[b] + 3) * 49 + (t.ay[S] - t.ay[b] + 3) * 7 + (t.az[S] - t.az[b] + 3);
+      const double* q = offtab + (int64_t)o * OT;
+      if (k < 2 * (p + 1)) {
+        R* e = reinterpret_cast<R*>(sm.E1 + c * (p + 1));
+        e[k] = (R)q[k];
+      } else if (k < 4 * (p + 1)) {
+        R* e = reinterpret_cast<R*>(sm.E2 + c * (p + 1));
+        e[k - 2 * (p + 1)] = (R)q[k];
+      } else {
+        sm.G[c * (2 * p + 1) + (k - 4 * (p + 1))] = (R)q[k];
       }
     }
     __syncthreads();
-    // load: multipole (stored as R-normalised, box-scaled) -> paper
+    // load: multipole (stored R-normalised, box-scaled) -> paper
     // normalisation, fourth density re-centred on this machine, times E1.
     for (int i = threadIdx.x; i < RC * T; i += ROT_T) {
       const int c = i / T, f = i % T;
@@ -278,46 +262,46 @@ __global__ void __launch_bounds__(ROT_T) k_m2l_rot(int p, int RC, Tree t, List V
     __syncthreads();
     dense_step(sm, p, RC, sm.X, sm.Y, true, 2, sm.E1);
     __syncthreads();
+    // sum the columns of each density into this box's local expansion
+    // (paper normalisation -> R-normalised storage, times s_k^l)
     for (int i = threadIdx.x; i < ND * T; i += ROT_T) {
       const int d = i / T, f = i % T;
-      double2 a = sm.Lacc[i];
+      double ax = 0.0, ay = 0.0;
+      bool any = false;
       for (int c = 0; c < RC; ++c)
         if (sm.colS[c] >= 0 && sm.colD[c] == d) {
-          a.x += (double)sm.Y[c * T + f].x;
-          a.y += (double)sm.Y[c * T + f].y;
+          ax += (double)sm.Y[c * T + f].x;
+          ay += (double)sm.Y[c * T + f].y;
+          any = true;
         }
-      sm.Lacc[i] = a;
+      if (any) {
+        const double s = sm.sf[f];
+        double2 v = Lb[i];
+        Lb[i] = make_double2(v.x + ax * s, v.y + ay * s);
+      }
     }
-  }
-  __syncthreads();
-  // paper normalisation -> R-normalised storage (times s_k^l), overwrite L.
-  for (int i = threadIdx.x; i < ND * T; i += ROT_T) {
-    const int f = i % T;
-    const double s = sm.sf[f];
-    double2 a = sm.Lacc[i];
-    L[(int64_t)b * ND * T + i] = make_double2(a.x * s, a.y * s);
   }
 }
 
-static size_t rot_smem_bytes(int p, int RC, int ND, int rot_len, size_t real) {
+static size_t rot_smem_bytes(int p, int RC, int rot_len, size_t real) {
   const int T = ncoef(p);
-  return sizeof(double2) * ND * T + sizeof(double) * T +
-         2 * real * (rot_len + 2 * RC * T + 2 * RC * (p + 1)) + real * RC * (2 * p + 1) +
+  return sizeof(double) * T + 2 * real * (rot_len + 2 * RC * T + 2 * RC * (p + 1)) + real * RC * (2 * p + 1) +
          sizeof(int) * (2 * RC + p + 2) + 16;
 }
 
 template <class R>
 static hipError_t launch_rot(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
-  const int p = l.p, ND = 4 * nrc;
-  int RC = 8;
-  while (RC > 1 && rot_smem_bytes(p, RC, ND, l.tb->rot_len, sizeof(R)) > 160 * 1024) RC /= 2;
-  size_t shm = rot_smem_bytes(p, RC, ND, l.tb->rot_len, sizeof(R));
+  const int p = l.p;
+  // 16 columns per chunk in FP32, 8 in FP64, fewer only if LDS runs out
+  int RC = sizeof(R) == 4 ? 16 : 8;
+  while (RC > 1 && rot_smem_bytes(p, RC, l.tb->rot_len, sizeof(R)) > 80 * 1024) RC /= 2;
+  size_t shm = rot_smem_bytes(p, RC, l.tb->rot_len, sizeof(R));
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   switch (nrc) {
-    case 1: k_m2l_rot<4, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, e.M, e.L); break;
-    case 2: k_m2l_rot<8, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, e.M, e.L); break;
-    case 4: k_m2l_rot<16, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, e.M, e.L); break;
+    case 1: k_m2l_rot<4, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
+    case 2: k_m2l_rot<8, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
+    case 4: k_m2l_rot<16, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

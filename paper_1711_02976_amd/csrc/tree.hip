@@ -509,6 +509,43 @@ __global__ void k_leaf_compact(Tree t, const int* off, int* ids) {
   if (b < t.nbox && t.nchild[b] == 0) ids[off[b]] = b;
 }
 
+hipError_t radix_sort(uint64_t** keys, int** vals, uint64_t* kalt, int* valt, int64_t n, int key_passes,
+                      int sys_passes, const int* sys_begin, int nsys, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t rblk = (n + RS_TILE - 1) / RS_TILE;
+  int64_t hn = 256 * rblk;
+  int *hist = nullptr, *stmp = nullptr;
+  hipError_t e = hipMalloc(&hist, sizeof(int) * hn);
+  if (e == hipSuccess) e = hipMalloc(&stmp, sizeof(int) * scan_tmp_ints(hn));
+  uint64_t *k0 = *keys, *k1 = kalt;
+  int *v0 = *vals, *v1 = valt;
+  for (int pass = 0; e == hipSuccess && pass < key_passes + sys_passes; ++pass) {
+    int mode = pass < key_passes ? 0 : 1;
+    int shift = pass < key_passes ? 8 * pass : 8 * (pass - key_passes);
+    k_rs_hist<<<(unsigned)rblk, RS_T, 0, s>>>(k0, v0, n, shift, mode, sys_begin, nsys, hist, (int)rblk);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_exclusive(hist, hist, hn, stmp, s);
+    if (e == hipSuccess) {
+      k_rs_scatter<<<(unsigned)rblk, RS_T, 0, s>>>(k0, v0, k1, v1, n, shift, mode, sys_begin, nsys, hist,
+                                                   (int)rblk);
+      e = hipGetLastError();
+    }
+    std::swap(k0, k1);
+    std::swap(v0, v1);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess && e == hipSuccess) e = hipErrorUnknown;
+  if (hist) (void)hipFree(hist);
+  if (stmp) (void)hipFree(stmp);
+  // result in k0/v0; hand the other buffers back through kalt/valt's owners
+  if (k0 != *keys) {
+    // the sorted data lives in the alternate buffers: copy back
+    if (e == hipSuccess) e = hipMemcpyAsync(*keys, k0, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(*vals, v0, sizeof(int) * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  return e;
+}
+
 // ---------------------------------------------------------------- driver --
 namespace {
 
@@ -625,27 +662,10 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
     return -3;
   if (n > 0) k_morton<<<nblocks(n, 256), 256, 0, s>>>(A.pos, n, B->d_sys_begin, nsys, B->d_lo, B->d_side, k0, v0);
   RPY_HIP(hipGetLastError());
-  int64_t rblk = (n + RS_TILE - 1) / RS_TILE;
-  int64_t hn = 256 * std::max<int64_t>(rblk, 1);
-  int *hist = nullptr, *stmp = nullptr;
-  if (dalloc(&hist, hn, B, err) || dalloc(&stmp, (int64_t)scan_tmp_ints(hn), B, err)) return -3;
   int npass_sys = nsys > 1 ? (nsys > 256 ? 2 : 1) : 0;
-  if (n > 0) {
-    for (int pass = 0; pass < 8 + npass_sys; ++pass) {
-      int mode = pass < 8 ? 0 : 1;
-      int shift = pass < 8 ? 8 * pass : 8 * (pass - 8);
-      k_rs_hist<<<(unsigned)rblk, RS_T, 0, s>>>(k0, v0, n, shift, mode, B->d_sys_begin, nsys, hist, (int)rblk);
-      RPY_HIP(hipGetLastError());
-      RPY_HIP(scan_exclusive(hist, hist, hn, stmp, s));
-      k_rs_scatter<<<(unsigned)rblk, RS_T, 0, s>>>(k0, v0, k1, v1, n, shift, mode, B->d_sys_begin, nsys, hist,
-                                                   (int)rblk);
-      RPY_HIP(hipGetLastError());
-      std::swap(k0, k1);
-      std::swap(v0, v1);
-    }
-  }
-  (void)hipFree(k1); (void)hipFree(v1); (void)hipFree(hist); (void)hipFree(stmp);
-  B->bytes -= (sizeof(uint64_t) + sizeof(int)) * std::max<int64_t>(n, 1) + sizeof(int) * (hn + scan_tmp_ints(hn));
+  RPY_HIP(radix_sort(&k0, &v0, k1, v1, n, 8, npass_sys, B->d_sys_begin, nsys, s));
+  (void)hipFree(k1); (void)hipFree(v1);
+  B->bytes -= (sizeof(uint64_t) + sizeof(int)) * std::max<int64_t>(n, 1);
   B->keys = k0;
   B->perm = v0;
   if (dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) return -3;

@@ -209,3 +209,26 @@ def test_m2l_rotation_matches_dense(orc, p):
     if p <= 13:
         ref = orc.fmm(w.pos, w.forces, w.a, w.eta, p, 30)
         assert orc.rel_l2(ur, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["uniform-p16-offset", "uniform-p7-offset", "clustered-p20", "nrhs5"])
+def test_mixed_precision_accuracy(orc, case):
+    """Mixed form (FP32 near field and M->L, FP64 expansions and sums):
+    error against the FP64 direct sum within the requested eps, and close to
+    the FP64 FMM of the same plan."""
+    if case == "uniform-p16-offset":
+        w, eps, s = W.uniform_cube(20_000, 2.0, 0.01, nrhs=1, seed=101), 1e-6, 60
+    elif case == "uniform-p7-offset":
+        w, eps, s = W.uniform_cube(20_000, 2.0, 0.01, nrhs=2, seed=102), 1e-3, 60
+    elif case == "clustered-p20":
+        w, eps, s = W.clustered(20_000, 30, 30.0, 1.0, 0.5, 1, seed=103), 1e-6, 40
+    else:
+        w, eps, s = W.uniform_cube(8_000, 1.5, 0.01, nrhs=5, seed=104), 1e-6, 50
+    log(f"mixed {case} n={w.n} nrhs={w.nrhs} eps={eps}")
+    um, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, eps, leaf_size=s, precision="mixed")
+    ud, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, eps, leaf_size=s, precision="fp64")
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta)
+    e_mix, e_fp64, e_rel = orc.rel_l2(um, ref), orc.rel_l2(ud, ref), orc.rel_l2(um, ud)
+    log(f"  p={st['order']} mixed vs direct {e_mix:.3e}, fp64 vs direct {e_fp64:.3e}, mixed vs fp64 {e_rel:.3e}")
+    assert e_mix <= eps
+    assert e_rel <= max(3e-7, 0.5 * eps)
