@@ -53,12 +53,12 @@ def algorithmic_counts(P, p, nrc):
     p2p_flops = pairs * (20 + 18 * nrc)
     # M2L (dense): per V pair and density, T x (p+1)^2 complex multiply-adds.
     m2l_flops = npair_v * 4 * nrc * T * (p + 1) ** 2 * 8
-    # M2L (rotation): per V pair and density, two real rotations of
-    # sum_n (2n+1)^2 multiply-adds and the z translation, sum_l (p-l+1)^2
-    # multiply-adds on the real and (l > 0) imaginary parts.
-    rot = (p + 1) * (2 * p + 1) * (2 * p + 3) // 3
-    zt = (p + 1) * (p + 2) * (2 * p + 3) // 6
-    m2l_rot_flops = npair_v * 4 * nrc * 2 * (2 * rot + 2 * zt - (p + 1))
+    # M2L (rotation): per V pair and density, four real-split rotations of
+    # 2 (n+1)^2 multiply-adds per degree n and the z translation with
+    # 2 (p-l+1)^2 per order l: 10 S multiply-adds, S = sum_n (n+1)^2
+    # (the O(p^2) diagonal phase and scale factors are not counted).
+    S = (p + 1) * (p + 2) * (2 * p + 3) // 6
+    m2l_rot_flops = npair_v * 4 * nrc * 20 * S
     return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "m2l_flops": m2l_flops,
             "m2l_rot_flops": m2l_rot_flops}
 
@@ -96,7 +96,7 @@ def run(args):
     for prec in args.precisions:
         torch.cuda.synchronize()
         P = R.Plan(pos, w.a, w.eta, w.eps, precision=prec, leaf_size=args.leaf_size, order=args.order,
-                   max_depth=w.max_depth, counts=counts)
+                   max_depth=w.max_depth, counts=counts, m2l=args.m2l)
         st = P.stats()
         for _ in range(args.warmup):
             P.matvec(F, out=U)
@@ -200,6 +200,8 @@ def main():
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--m2l", default="auto", choices=["auto", "dense", "rotation"],
+                    help="multipole-to-local operator (auto = the library's choice per precision)")
     args = ap.parse_args()
     args.precisions = [p.strip() for p in args.precisions.split(",") if p.strip()]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

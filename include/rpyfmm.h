@@ -53,12 +53,14 @@ typedef struct {
   uint32_t struct_size;  /* sizeof(rpy_options); lets the struct grow */
   int32_t precision;     /* rpy_precision */
   int32_t leaf_size;     /* refinement limit: max beads per leaf (Sec. 4.2
-                            "threshold"); 0 = chosen by the library */
+                            "threshold"); 0 = chosen by the library: trees
+                            are built for limits 16 * 1.5^k and the one with
+                            the lowest modelled matvec time is kept */
   int32_t order;         /* expansion order p; 0 = chosen from eps */
   int32_t max_depth;     /* deepest tree level, 1..21; 0 = 14 */
-  int32_t m2l_mode;      /* multipole-to-local operator: 0 = library choice,
-                            1 = dense O(p^4) translation, 2 = rotation to the
-                            z axis, O(p^3) */
+  int32_t m2l_mode;      /* multipole-to-local operator: 0 = library choice
+                            (rotation), 1 = dense O(p^4) translation,
+                            2 = rotation to the z axis, O(p^3) */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
 } rpy_options;
 

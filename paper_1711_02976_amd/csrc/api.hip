@@ -44,6 +44,66 @@ int order_for_eps(double eps, bool adaptive) {
   return std::min(p, rpy::MAX_ORDER);
 }
 
+// ---- leaf-size choice ------------------------------------------------------
+// Modelled time of one matvec (one right-hand side) on a built tree, from its
+// interaction counts and per-unit kernel times measured on MI355X for this
+// library at p = 16 (1M-bead cube): P2P per ordered bead pair, M2L per
+// (V pair, density), per-box upward/downward work per density, and the
+// adaptive W/X terms per (bead, box).  Also returns the range of refinement
+// limits that produce this same tree.
+struct TreeCost {
+  double ns = 0;
+  int same_lo = 0;     // largest leaf that a larger limit could not split
+  int same_hi = 0;     // smallest count among split boxes: limits below it keep every split
+  bool adaptive = false;
+};
+
+static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, int max_depth, TreeCost* out) {
+  const rpy::Tree& t = B.tree;
+  const int nbox = t.nbox;
+  std::vector<int> beg(nbox), end(nbox), child(nbox), lev(nbox);
+  auto get = [&](std::vector<int>& h, const int* d, size_t n) {
+    return n == 0 || hipMemcpy(h.data(), d, sizeof(int) * n, hipMemcpyDeviceToHost) == hipSuccess;
+  };
+  if (!get(beg, t.begin, nbox) || !get(end, t.end, nbox) || !get(child, t.child, nbox) || !get(lev, t.level, nbox))
+    return -4;
+  const rpy::List& U = B.lists[rpy::LU];
+  const rpy::List& W = B.lists[rpy::LW];
+  const rpy::List& X = B.lists[rpy::LX];
+  std::vector<int> uo(nbox + 1), ue(U.len), wo(nbox + 1), xo(nbox + 1), xe(X.len);
+  if (!get(uo, U.off, nbox + 1) || !get(ue, U.ent, U.len) || !get(wo, W.off, nbox + 1) || !get(xo, X.off, nbox + 1) ||
+      !get(xe, X.ent, X.len))
+    return -4;
+  const bool adaptive = W.len > 0 || X.len > 0;
+  const int p = order ? order : order_for_eps(eps, adaptive);
+  double pairs = 0, wterm = 0, xterm = 0;
+  int lo = 0, hi = 0x7fffffff;
+  for (int b = 0; b < nbox; ++b) {
+    const int nb = end[b] - beg[b];
+    if (child[b] < 0) {
+      if (lev[b] < max_depth) lo = std::max(lo, nb);
+      double src = 0;
+      for (int k = uo[b]; k < uo[b + 1]; ++k) src += end[ue[k]] - beg[ue[k]];
+      pairs += (double)nb * src;
+      wterm += (double)nb * (wo[b + 1] - wo[b]);
+    } else {
+      hi = std::min(hi, nb);
+    }
+    for (int k = xo[b]; k < xo[b + 1]; ++k) xterm += end[xe[k]] - beg[xe[k]];
+  }
+  const double S = (p + 1.0) * (p + 2.0) * (2.0 * p + 3.0) / 6.0, S16 = 17.0 * 18.0 * 35.0 / 6.0;
+  const double T = (p + 1.0) * (p + 2.0) / 2.0, T16 = 153.0;
+  const double c_pair = mixed ? 0.97 : 1.41;          // ns per ordered pair
+  const double c_v = (mixed ? 2210.0 : 2650.0) * S / S16;  // ns per (V pair, density)
+  const double c_box = 45.0 * T / T16;                // ns per (box, density)
+  const double c_wx = 3.0 * T / T16;                  // ns per (bead, W or X box, density)
+  out->ns = pairs * c_pair + 4.0 * (B.lists[rpy::LV].len * c_v + nbox * c_box + (wterm + xterm) * c_wx);
+  out->same_lo = lo;
+  out->same_hi = hi;
+  out->adaptive = adaptive;
+  return 0;
+}
+
 }  // namespace
 
 struct rpy_plan_s {
@@ -193,18 +253,53 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   P->precision = o.precision;
   P->stream = (hipStream_t)o.stream;
   P->p = o.order;
-  P->leaf_size = o.leaf_size ? o.leaf_size : 100;
+  P->leaf_size = o.leaf_size;
   P->max_depth = o.max_depth;
-  // library choice: FP64 uses the dense operator (it measures faster than the
-  // cooperative rotation kernel at the orders used); the mixed form uses the
-  // rotation operator in FP32.
-  P->m2l_mode = o.m2l_mode != 0 ? o.m2l_mode : (o.precision == RPY_PREC_MIXED ? 2 : 1);
+  // library choice: the rotation operator (measured 5x faster than the dense
+  // one at p = 16 in FP64); the mixed form runs it in FP32.
+  P->m2l_mode = o.m2l_mode != 0 ? o.m2l_mode : 2;
 
   std::vector<int64_t> sb(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) sb[s + 1] = sb[s] + counts[s];
-  rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
   rpy::Error err{0, ""};
-  int rc = rpy::build_tree(ba, &P->B, &err);
+  int rc = 0;
+  if (o.leaf_size > 0) {
+    rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
+    rc = rpy::build_tree(ba, &P->B, &err);
+  } else {
+    // Refinement limit chosen by the cost model over a ladder of limits
+    // (16 * 1.5^k); limits that provably give the tree already built are
+    // skipped, and the search stops once the modelled time has grown well
+    // past the best (the model is unimodal in the limit in practice).
+    int64_t nmax = 1;
+    for (int s = 0; s < nsys; ++s) nmax = std::max<int64_t>(nmax, counts[s]);
+    double best = 0, sl = 16;
+    for (;;) {
+      const int cand = (int)sl;
+      rpy::Built Bc;
+      rpy::BuildArgs ba{n, nsys, sb.data(), positions, cand, P->max_depth, a, P->stream};
+      rc = rpy::build_tree(ba, &Bc, &err);
+      TreeCost tc;
+      if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, &tc);
+      if (rc != 0) {
+        rpy::free_built(&Bc);
+        break;
+      }
+      const bool first = P->leaf_size == 0;
+      if (first || tc.ns < best) {
+        if (!first) rpy::free_built(&P->B);
+        P->B = Bc;
+        P->leaf_size = cand;
+        best = tc.ns;
+      } else {
+        rpy::free_built(&Bc);
+        if (tc.ns > 1.5 * best) break;
+      }
+      if (cand >= nmax || tc.same_hi > nmax) break;  // one leaf per system from here on
+      do sl *= 1.5;
+      while ((int64_t)sl < tc.same_hi);
+    }
+  }
   if (rc == 0 && P->p == 0)
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);

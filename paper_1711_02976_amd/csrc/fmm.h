@@ -23,16 +23,20 @@ struct Tables {
   int p;
   double2* oct;    // [8][(p+1)^2] R_j^mu(d/h_parent), d = child - parent centre
   double2* itab;   // [343][(2p+1)^2] I_j^mu(t), t integer offset in box units
-  // Rotation-based M->L: the real rotation by +90 degrees about y for every
-  // degree n <= p, split for real-symmetric coefficient sets into
-  // rot[n][m][m'] = (A+, A-) with m' padded to a multiple of 4.
-  double2* rot;
-  int* rot_off;    // [p+2] start of degree n in rot
+  // Rotation-based M->L, FP64 and FP32 copies.  rot: per degree n, the
+  // +90 degree rotation about y as (n+1) rows of n+1 slots holding the
+  // nonzero real-split entries (A+ on real parts, then A- on imaginary
+  // parts; the two are checkerboard-sparse).  zt: per order l the
+  // z-translation matrix H_l ((p-l+1)^2, rows = output degree).  geo: per
+  // integer offset slot, e^{-i(pi/2-phi)}, e^{i theta}, 1/|t| (8 doubles).
+  double* rot64;
+  float* rot32;
+  double* zt64;
+  float* zt32;
+  double* geo;
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
-  // per integer offset t (343 slots): e^{-i m (pi/2 - phi_t)}, e^{i m theta_t}
-  // (m = 0..p, complex) and j!/|t|^{j+1} (j = 0..2p)
-  double* offtab;
-  int rot_len;
+  int rot_len;     // sum_n (n+1)^2
+  int zt_len;      // sum_l (p-l+1)^2
   int64_t bytes;
 };
 

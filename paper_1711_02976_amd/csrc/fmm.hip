@@ -257,20 +257,40 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
         host_irregular(tx, ty, tz, 2 * p, tmp);
         std::copy(tmp.begin(), tmp.end(), itab.begin() + (size_t)o * F2);
       }
-  // rotation tables
-  std::vector<int> roff(p + 2, 0);
-  for (int n = 0; n <= p; ++n) roff[n + 1] = roff[n] + (n + 1) * (4 * ((n + 4) / 4));
-  std::vector<double2> rot(roff[p + 1], make_double2(0, 0));
+  // rotation-based M->L: the +90 degree rotation about y per degree n, split
+  // for coefficient sets with x_{-m} = (-1)^m conj(x_m) into real matrices
+  // acting on the real parts (A+) and on the imaginary parts (A-).  Both are
+  // checkerboard-sparse: A+[m'][m] vanishes unless m' + m + n is even and
+  // A-[m'][m] unless it is odd (and m >= 1).  Row m' of degree n stores the
+  // nonzero A+ entries (m = q, q+2, ..., q = (n+m') mod 2), then the A-
+  // entries (m = 1-q, 3-q, ..., m >= 1), in a row of n+1 slots.  The inverse
+  // rotation S R S (S = diag((-1)^m)) is the same table with the signs
+  // (-1)^n on A+ and -(-1)^n on A-.
+  const int rlen = (p + 1) * (p + 2) * (2 * p + 3) / 6;
+  std::vector<double> rot((size_t)rlen, 0.0);
   std::vector<double> D;
-  for (int n = 0; n <= p; ++n) {
+  for (int n = 0, off = 0; n <= p; off += (n + 1) * (n + 1), ++n) {
     host_rot90(n, D);
-    const int W = 2 * n + 1, pad = 4 * ((n + 4) / 4);
-    for (int m = 0; m <= n; ++m)
-      for (int mp = 0; mp <= n; ++mp) {
-        double dp = D[(size_t)(mp + n) * W + (m + n)], dm = D[(size_t)(mp + n) * W + (n - m)];
-        double2 v = m == 0 ? make_double2(dp, 0.0) : make_double2(dp + dm, dp - dm);
-        rot[roff[n] + m * pad + mp] = v;
+    const int W = 2 * n + 1, K = n + 1;
+    for (int mp = 0; mp <= n; ++mp) {
+      const int q = (n + mp) & 1;
+      int j = 0;
+      for (int m = 0; m <= n; ++m) {
+        const double dp = D[(size_t)(mp + n) * W + (m + n)], dm = D[(size_t)(mp + n) * W + (n - m)];
+        const double ap = m == 0 ? dp : dp + dm, am = m == 0 ? 0.0 : dp - dm;
+        if (((m & 1) != q && std::fabs(ap) > 1e-12) || ((m & 1) == q && std::fabs(am) > 1e-12)) {
+          err->code = -4;
+          err->msg = "rotation table: unexpected nonzero entry";
+          return -4;
+        }
       }
+      for (int m = q; m <= n; m += 2) {
+        const double dp = D[(size_t)(mp + n) * W + (m + n)], dm = D[(size_t)(mp + n) * W + (n - m)];
+        rot[off + mp * K + j++] = m == 0 ? dp : dp + dm;
+      }
+      for (int m = (q == 1 ? 2 : 1); m <= n; m += 2)
+        rot[off + mp * K + j++] = D[(size_t)(mp + n) * W + (m + n)] - D[(size_t)(mp + n) * W + (n - m)];
+    }
   }
   std::vector<double> sf(ncoef(p));
   for (int n = 0; n <= p; ++n)
@@ -281,56 +301,69 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
       for (int k = 2; k <= n + m; ++k) g *= k;
       sf[tri(n) + m] = std::sqrt(f * g);
     }
-  // per-offset phases and z-translation factors of the rotation M->L
-  const int OT = 4 * (p + 1) + 2 * p + 1;
-  std::vector<double> offt((size_t)343 * OT, 0.0);
+  // z translation by rho (box units) on rotated sets, per order l:
+  //   L'_k^l = rho^-(k+1) sum_n H_l[k-l][n-l] rho^-n M'_n^l,
+  //   H_l[k-l][n-l] = (-1)^(n+l) (n+k)! / (s_k^l s_n^l).
+  const int zlen = (p + 1) * (p + 2) * (2 * p + 3) / 6;
+  std::vector<double> zt(zlen, 0.0);
+  {
+    std::vector<double> fac(2 * p + 2, 1.0);
+    for (int j = 1; j <= 2 * p + 1; ++j) fac[j] = fac[j - 1] * j;
+    for (int l = 0, off = 0; l <= p; off += (p - l + 1) * (p - l + 1), ++l) {
+      const int K = p - l + 1;
+      for (int k = l; k <= p; ++k)
+        for (int n = l; n <= p; ++n)
+          zt[off + (k - l) * K + (n - l)] =
+              (((n + l) & 1) ? -1.0 : 1.0) * fac[n + k] / (sf[tri(k) + l] * sf[tri(n) + l]);
+    }
+  }
+  // per integer offset t (343 slots): e^{-i(pi/2 - phi_t)}, e^{i theta_t}, 1/|t|
+  std::vector<double> geo((size_t)343 * 8, 0.0);
   for (int tx = -3; tx <= 3; ++tx)
     for (int ty = -3; ty <= 3; ++ty)
       for (int tz = -3; tz <= 3; ++tz) {
         if (std::abs(tx) <= 1 && std::abs(ty) <= 1 && std::abs(tz) <= 1) continue;
-        double* q = offt.data() + (size_t)((tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)) * OT;
+        double* q = geo.data() + (size_t)((tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)) * 8;
         const double rho = std::sqrt((double)(tx * tx + ty * ty + tz * tz));
         const double th = std::acos(tz / rho), ph = std::atan2((double)ty, (double)tx);
-        for (int m = 0; m <= p; ++m) {
-          q[2 * m] = std::cos(m * (0.5 * M_PI - ph));
-          q[2 * m + 1] = -std::sin(m * (0.5 * M_PI - ph));
-          q[2 * (p + 1) + 2 * m] = std::cos(m * th);
-          q[2 * (p + 1) + 2 * m + 1] = std::sin(m * th);
-        }
-        double f = 1.0, rp = 1.0 / rho;
-        for (int j = 0; j <= 2 * p; ++j) {
-          if (j > 0) f *= j;
-          q[4 * (p + 1) + j] = f * rp;
-          rp /= rho;
-        }
+        q[0] = std::cos(0.5 * M_PI - ph);
+        q[1] = -std::sin(0.5 * M_PI - ph);
+        q[2] = std::cos(th);
+        q[3] = std::sin(th);
+        q[4] = 1.0 / rho;
       }
-  tb->rot_len = roff[p + 1];
+  std::vector<float> rot32(rot.begin(), rot.end()), zt32(zt.begin(), zt.end());
+  tb->rot_len = rlen;
+  tb->zt_len = zlen;
   RPY_HIP(hipMalloc(&tb->oct, sizeof(double2) * oct.size()));
   RPY_HIP(hipMalloc(&tb->itab, sizeof(double2) * itab.size()));
-  RPY_HIP(hipMalloc(&tb->rot, sizeof(double2) * rot.size()));
-  RPY_HIP(hipMalloc(&tb->rot_off, sizeof(int) * roff.size()));
+  RPY_HIP(hipMalloc(&tb->rot64, sizeof(double) * rot.size()));
+  RPY_HIP(hipMalloc(&tb->rot32, sizeof(float) * rot32.size()));
+  RPY_HIP(hipMalloc(&tb->zt64, sizeof(double) * zt.size()));
+  RPY_HIP(hipMalloc(&tb->zt32, sizeof(float) * zt32.size()));
+  RPY_HIP(hipMalloc(&tb->geo, sizeof(double) * geo.size()));
   RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
-  RPY_HIP(hipMalloc(&tb->offtab, sizeof(double) * offt.size()));
-  RPY_HIP(hipMemcpy(tb->offtab, offt.data(), sizeof(double) * offt.size(), hipMemcpyHostToDevice));
-  tb->bytes = sizeof(double2) * (oct.size() + itab.size() + rot.size()) + sizeof(int) * roff.size() +
-              sizeof(double) * (sf.size() + offt.size());
+  tb->bytes = sizeof(double2) * (oct.size() + itab.size()) + (sizeof(double) + sizeof(float)) * (rot.size() + zt.size()) +
+              sizeof(double) * (geo.size() + sf.size());
   RPY_HIP(hipMemcpy(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice));
-  RPY_HIP(hipMemcpy(tb->rot, rot.data(), sizeof(double2) * rot.size(), hipMemcpyHostToDevice));
-  RPY_HIP(hipMemcpy(tb->rot_off, roff.data(), sizeof(int) * roff.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->rot64, rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->rot32, rot32.data(), sizeof(float) * rot32.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->zt64, zt.data(), sizeof(double) * zt.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->zt32, zt32.data(), sizeof(float) * zt32.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->geo, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->sfac, sf.data(), sizeof(double) * sf.size(), hipMemcpyHostToDevice));
   (void)s;
   return 0;
 }
 
 void free_tables(Tables* tb) {
-  void* ps[] = {tb->oct, tb->itab, tb->rot, tb->rot_off, tb->sfac, tb->offtab};
+  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac};
   for (void* q : ps)
     if (q) (void)hipFree(q);
-  tb->oct = tb->itab = tb->rot = nullptr;
-  tb->rot_off = nullptr;
-  tb->sfac = nullptr;
-  tb->offtab = nullptr;
+  tb->oct = tb->itab = nullptr;
+  tb->rot64 = tb->zt64 = tb->geo = tb->sfac = nullptr;
+  tb->rot32 = tb->zt32 = nullptr;
 }
 
 // ------------------------------------------------------------- permutes ----

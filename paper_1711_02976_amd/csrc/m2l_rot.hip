@@ -1,25 +1,34 @@
-// Multipole-to-local translation (M->L over V lists) by rotation:
-// every V-list source multipole is rotated so that the translation vector
-// lies on the z axis, translated along z (an O(p^3) operator that keeps the
-// order m), and rotated back.  The paper's FMM diagonalises this step with
-// exponential expansions (arXiv:1711.02976, Sec. 1 and 3.2); this kernel
-// uses the rotation factorisation instead and computes the same truncated
-// operator as the dense M->L.
+// Multipole-to-local translation (M->L over V lists) by rotation: every
+// V-list source multipole is rotated so that the translation vector lies on
+// the z axis, translated along z (an O(p^3) operator that keeps the order m),
+// and rotated back.  The paper's FMM diagonalises this step with exponential
+// expansions (arXiv:1711.02976, Sec. 1 and 3.2); this kernel computes the
+// same truncated operator as the dense M->L instead.
 //
 // Coefficients are handled in the paper's normalisation (Sec. 2: Y_n^m =
-// sqrt((n-|m|)!/(n+|m|)!) P_n^|m| e^{i m phi}), where rotations are real
-// orthogonal per degree.  A rotation taking the offset t = (rho, theta, phi)
-// to +z is Phi(-pi/2) R90^T Phi(-theta) R90 Phi(pi/2 - phi), with
-// Phi(a) = diag(e^{-i m a}) and R90 the fixed rotation by +90 degrees about
-// y, whose inverse is S R90 S, S = diag((-1)^m).  The whole M->L is
-//   Phi(phi - pi/2) R90^-1 Phi(theta) R90 Z(rho) R90^-1 Phi(-theta) R90 Phi(pi/2 - phi)
-// with Z(rho) the translation along +z:
-//   L'_k^l = sum_{n>=l} M'_n^l (-1)^{n+l} (n+k)! / (s_k^l s_n^l rho^{n+k+1}),
-//   s_n^m = sqrt((n-m)!(n+m)!).
+// sqrt((n-|m|)!/(n+|m|)!) P_n^|m| e^{i m phi}), where a rotation is a real
+// orthogonal matrix per degree.  For the offset t = (rho, theta, phi) the
+// whole M->L is
+//   Phi(phi - pi/2) R^-1 Phi(theta) R Z(rho) R^-1 Phi(-theta) R Phi(pi/2 - phi)
+// with Phi(a) = diag(e^{-i m a}), R the fixed rotation by +90 degrees about y
+// (inverse S R S, S = diag((-1)^m)) and Z(rho) the translation along +z,
+//   L'_k^l = rho^-(k+1) sum_n H_l[k][n] rho^-n M'_n^l,
+//   H_l[k][n] = (-1)^{n+l} (n+k)! / (s_k^l s_n^l),  s_n^m = sqrt((n-m)!(n+m)!).
 //
-// One block per target box; its V-list sources times densities form the
-// columns, processed RC at a time through two LDS buffers; each thread owns
-// up to four outputs of one degree (or order) of one column.
+// GPU organisation.  One block of RW waves per target box; its V-list
+// (source, density) pairs are the columns, taken NC (64, or 32 when LDS is
+// short) at a time into an LDS array X[coefficient][column].  Each batch
+// runs four phases separated by barriers:
+//   0. all threads gather the columns' multipoles into X;
+//   1. per degree n: Phi(pi/2-phi), R, Phi(-theta), S R S;
+//   2. per order l: the z translation;
+//   3. per degree n: R, Phi(theta), S R S, Phi(phi - pi/2);
+// then every thread sums the columns of the outputs it owns into FP64
+// accumulators kept in registers across batches.  A wave processes whole
+// degrees (or orders), one column per lane, so the rotation and translation
+// matrices are the same for every lane: they are read as scalar operands,
+// and each lane's coefficients of one degree stay in registers.  Degrees and
+// orders are assigned to waves by a host-side longest-first schedule.
 #include <hip/hip_runtime.h>
 
 #include "fmm.h"
@@ -28,287 +37,435 @@ namespace rpy {
 
 namespace {
 
-constexpr int ROT_T = 256;
+constexpr int RW = 8;          // waves per block
+constexpr int RT = 64 * RW;    // threads per block
+constexpr int MAXK = MAX_ORDER + 1;
 
-template <class R> struct V2;
-template <> struct V2<double> { using T = double2; };
-template <> struct V2<float> { using T = float2; };
+template <class R> struct Cx;
+template <> struct Cx<double> { using T = double2; };
+template <> struct Cx<float> { using T = float2; };
 
-template <class R>
-struct RotSmem {
-  using C = typename V2<R>::T;
-  C* rot;         // rot_len
-  double* sf;     // T
-  C* X;           // RC * T
-  C* Y;           // RC * T
-  R* G;           // RC * (2p+1)
-  C* E1;          // RC * (p+1)
-  C* E2;          // RC * (p+1)
-  int* colS;      // RC
-  int* colD;      // RC
-  int* roff;      // p+2
+// Degrees (phases 1 and 3) and orders (phase 2) handled by each wave.
+struct RotSched {
+  unsigned char deg[RW][MAXK];
+  unsigned char ord[RW][MAXK];
+  unsigned char ndeg[RW];
+  unsigned char nord[RW];
 };
 
-template <class C>
-__device__ inline C cmul2(C a, C b) {
-  C r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
+// Per-column data of a batch, in LDS (structure of arrays, one slot per lane).
+struct ColData {
+  int* src;      // source box, -1 for an empty column
+  double* e1x;   // e^{-i(pi/2 - phi)}
+  double* e1y;
+  double* e2x;   // e^{i theta}
+  double* e2y;
+  double* rinv;  // 1/rho (box units)
+  double* wx;    // source centre - target centre (re-centres the fourth density)
+  double* wy;
+  double* wz;
+};
+
+__host__ __device__ constexpr int rot_block(int n) { return n * (n + 1) * (2 * n + 1) / 6; }  // sum_{j<n} (j+1)^2
+
+// One row of the real-split rotation of degree N whose A+ part uses the
+// inputs of parity Q: yr = sum A+ Re x, yi = sum A- Im x over the nonzero
+// entries, stored in that order in the row a.
+template <int N, int Q, class R>
+__device__ inline void rot_row(const R* __restrict__ a, const R* xr, const R* xi, R& yr, R& yi) {
+  constexpr int NP = N >= Q ? (N - Q) / 2 + 1 : 0;
+  constexpr int MS = Q == 1 ? 2 : 1;
+  constexpr int NM = N >= MS ? (N - MS) / 2 + 1 : 0;
+  R r = 0, i = 0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) r = fma(a[j], xr[Q + 2 * j], r);
+#pragma unroll
+  for (int j = 0; j < NM; ++j) i = fma(a[NP + j], xi[MS + 2 * j], i);
+  yr = r;
+  yi = i;
 }
 
-// Y[c] = (inv ? S R90 S : R90) X[c] for every column, then times the phase
-// (mode 0: none, 1: E, 2: conj(E)).
-template <class R>
-__device__ void dense_step(const RotSmem<R>& sm, int p, int RC, const typename V2<R>::T* X, typename V2<R>::T* Y,
-                           bool inv, int mode, const typename V2<R>::T* E) {
-  using C = typename V2<R>::T;
-  const int T = ncoef(p);
-  // items: (n, g) pairs enumerated degree by degree, times columns
-  int ng = 0;
-  for (int n = 0; n <= p; ++n) ng += (n + 4) / 4;
-  const int nitem = ng * RC;
-  for (int item = threadIdx.x; item < nitem; item += ROT_T) {
-    const int c = item % RC;
-    int it = item / RC, n = 0;
-    while (it >= (n + 4) / 4) {
-      it -= (n + 4) / 4;
-      ++n;
-    }
-    const int g = it, pad = 4 * ((n + 4) / 4);
-    const C* A = sm.rot + sm.roff[n] + 4 * g;
-    const C* x = X + c * T + tri(n);
-    R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    for (int m = 0; m <= n; ++m) {
-      C v = x[m];
-      if (inv && (m & 1)) { v.x = -v.x; v.y = -v.y; }
-      const C* a = A + m * pad;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        C q = a[r];
-        ar[r] = fma(q.x, v.x, ar[r]);
-        ai[r] = fma(q.y, v.y, ai[r]);
-      }
-    }
-    C* y = Y + c * T + tri(n);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int mp = 4 * g + r;
-      if (mp > n) break;
-      C v;
-      v.x = ar[r];
-      v.y = ai[r];
-      if (inv && (mp & 1)) { v.x = -v.x; v.y = -v.y; }
-      if (mode) {
-        C e = E[c * (p + 1) + mp];
-        if (mode == 2) e.y = -e.y;
-        v = cmul2(v, e);
-      }
-      y[mp] = v;
-    }
+// Stores (SR yr + i SI yi) times e (if PH) to col[mp] and advances e by (bx, by).
+template <bool PH, int SR, int SI, class R>
+__device__ inline void put_row(typename Cx<R>::T* col, int mp, int ld, R yr, R yi, double& fr, double& fi, double bx,
+                               double by) {
+  typename Cx<R>::T o;
+  if (SR < 0) yr = -yr;
+  if (SI < 0) yi = -yi;
+  if (PH) {
+    const R er = (R)fr, ei = (R)fi;
+    o.x = yr * er - yi * ei;
+    o.y = yr * ei + yi * er;
+    const double tr = fr * bx - fi * by;
+    fi = fr * by + fi * bx;
+    fr = tr;
+  } else {
+    o.x = yr;
+    o.y = yi;
+  }
+  col[mp * ld] = o;
+}
+
+// col[mp] = e^{mp} (SR Re(R x)_mp + i SI Im(R x)_mp) for mp = 0..N, with
+// e = (bx, by) when PH (else 1); SR = SI = 1 gives R, SR = (-1)^N and
+// SI = -(-1)^N give the inverse rotation S R S on the same table.
+template <int N, bool PH, int SR, int SI, class R>
+__device__ inline void rot_apply(const R* __restrict__ A, const R* xr, const R* xi, double bx, double by,
+                                 typename Cx<R>::T* col, int ld) {
+  constexpr int K = N + 1;
+  double fr = 1.0, fi = 0.0;
+#pragma unroll 1
+  for (int mp = 0; mp < K - 1; mp += 2) {
+    R yr, yi;
+    rot_row<N, (N & 1), R>(A + mp * K, xr, xi, yr, yi);
+    put_row<PH, SR, SI, R>(col, mp, ld, yr, yi, fr, fi, bx, by);
+    rot_row<N, ((N + 1) & 1), R>(A + (mp + 1) * K, xr, xi, yr, yi);
+    put_row<PH, SR, SI, R>(col, mp + 1, ld, yr, yi, fr, fi, bx, by);
+  }
+  if (K & 1) {
+    R yr, yi;
+    rot_row<N, (N & 1), R>(A + N * K, xr, xi, yr, yi);
+    put_row<PH, SR, SI, R>(col, N, ld, yr, yi, fr, fi, bx, by);
   }
 }
 
-// Translation along +z by rho (per column, through G[c][j] = j!/rho^{j+1}).
-template <class R>
-__device__ void ztrans_step(const RotSmem<R>& sm, int p, int RC, const typename V2<R>::T* X, typename V2<R>::T* Y) {
-  using C = typename V2<R>::T;
-  const int T = ncoef(p);
-  int nz = 0;
-  for (int l = 0; l <= p; ++l) nz += (p - l + 4) / 4;
-  const int nitem = nz * RC;
-  for (int item = threadIdx.x; item < nitem; item += ROT_T) {
-    const int c = item % RC;
-    int it = item / RC, l = 0;
-    while (it >= (p - l + 4) / 4) {
-      it -= (p - l + 4) / 4;
-      ++l;
-    }
-    const int k0 = l + 4 * it;
-    const R* G = sm.G + c * (2 * p + 1);
-    const C* x = X + c * T;
-    R accr[4] = {0, 0, 0, 0}, acci[4] = {0, 0, 0, 0};
-    for (int n = l; n <= p; ++n) {
-      R w = (R)(((n & 1) ? -1.0 : 1.0) / sm.sf[tri(n) + l]);
-      C v = x[tri(n) + l];
-      R vx = v.x * w, vy = v.y * w;
+template <int N, class R>
+__device__ inline void load_col(const typename Cx<R>::T* col, int ld, R* xr, R* xi) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int k = k0 + r;
-        R gk = k <= p ? G[n + k] : (R)0;
-        accr[r] = fma(gk, vx, accr[r]);
-        acci[r] = fma(gk, vy, acci[r]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int k = k0 + r;
-      if (k > p) break;
-      R w = (R)(((l & 1) ? -1.0 : 1.0) / sm.sf[tri(k) + l]);
-      C o;
-      o.x = accr[r] * w;
-      o.y = acci[r] * w;
-      Y[c * T + tri(k) + l] = o;
-    }
+  for (int m = 0; m <= N; ++m) {
+    const auto v = col[m * ld];
+    xr[m] = v.x;
+    xi[m] = v.y;
   }
 }
+
+// Phase 1 for degree N of column c (the column's coefficients are already in
+// X, scaled to the paper's normalisation): Phi(pi/2 - phi), R, Phi(-theta),
+// S R S.
+template <int N, class R>
+__device__ void first_half(int c, int ld, const ColData& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
+  using C = typename Cx<R>::T;
+  constexpr int K = N + 1, t0 = N * (N + 1) / 2;
+  constexpr int SG = (N & 1) ? -1 : 1;
+  C* col = X + t0 * ld + c;
+  R xr[K], xi[K];
+  {
+    const double ax = cd.e1x[c], ay = cd.e1y[c];
+    double er = 1.0, ei = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const C v = col[m * ld];
+      const R fr = (R)er, fi = (R)ei;
+      xr[m] = v.x * fr - v.y * fi;
+      xi[m] = v.x * fi + v.y * fr;
+      const double tr = er * ax - ei * ay;
+      ei = er * ay + ei * ax;
+      er = tr;
+    }
+  }
+  rot_apply<N, true, 1, 1, R>(A, xr, xi, cd.e2x[c], cd.e2y[c], col, ld);
+  load_col<N, R>(col, ld, xr, xi);
+  rot_apply<N, false, SG, -SG, R>(A, xr, xi, 0.0, 0.0, col, ld);
+}
+
+// Phase 2: z translation of order l (KK = p - l + 1 degrees) of column c.
+template <int KK, class R>
+__device__ void ztrans(int l, int c, int ld, const ColData& cd, const R* __restrict__ H, typename Cx<R>::T* X) {
+  using C = typename Cx<R>::T;
+  const double ri = cd.rinv[c];
+  double s = 1.0;
+  for (int j = 0; j < l; ++j) s *= ri;
+  R vr[KK], vi[KK];
+#pragma unroll
+  for (int j = 0; j < KK; ++j) {
+    const int n = l + j;
+    C v = X[(n * (n + 1) / 2 + l) * ld + c];
+    vr[j] = v.x * (R)s;
+    vi[j] = v.y * (R)s;
+    s *= ri;
+  }
+  double so = 1.0;
+  for (int j = 0; j <= l; ++j) so *= ri;
+#pragma unroll 2
+  for (int kk = 0; kk < KK; ++kk) {
+    const R* h = H + kk * KK;
+    R ar = 0, ai = 0;
+#pragma unroll
+    for (int j = 0; j < KK; ++j) {
+      ar = fma(h[j], vr[j], ar);
+      ai = fma(h[j], vi[j], ai);
+    }
+    const int k = l + kk;
+    C o;
+    o.x = ar * (R)so;
+    o.y = ai * (R)so;
+    X[(k * (k + 1) / 2 + l) * ld + c] = o;
+    so *= ri;
+  }
+}
+
+// Phase 3 for degree N of column c: R, Phi(theta), S R S, Phi(phi - pi/2).
+template <int N, class R>
+__device__ void second_half(int c, int ld, const ColData& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
+  using C = typename Cx<R>::T;
+  constexpr int K = N + 1, t0 = N * (N + 1) / 2;
+  constexpr int SG = (N & 1) ? -1 : 1;
+  C* col = X + t0 * ld + c;
+  R xr[K], xi[K];
+  load_col<N, R>(col, ld, xr, xi);
+  rot_apply<N, true, 1, 1, R>(A, xr, xi, cd.e2x[c], -cd.e2y[c], col, ld);
+  load_col<N, R>(col, ld, xr, xi);
+  rot_apply<N, true, SG, -SG, R>(A, xr, xi, cd.e1x[c], -cd.e1y[c], col, ld);
+}
+
+#define RPY_DEG_CASES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21)
 
 }  // namespace
 
 template <int ND, class R>
-__global__ void __launch_bounds__(ROT_T) k_m2l_rot(int p, int RC, Tree t, List V, const double2* rot,
-                                                   const int* roff, int rot_len, const double* sfac,
-                                                   const double* offtab, const double2* M, double2* L) {
-  using C = typename V2<R>::T;
+__global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, RotSched sched,
+                                                const R* __restrict__ rot, const R* __restrict__ zt, int rot_len,
+                                                const double* __restrict__ geo, const double* __restrict__ sf,
+                                                const double2* __restrict__ M, double2* __restrict__ L) {
+  using C = typename Cx<R>::T;
+  constexpr int NACC = (ND * ncoef(MAX_ORDER) + RT - 1) / RT;
   extern __shared__ double2 smem[];
-  const int b = blockIdx.x;
-  const int T = ncoef(p), OT = 4 * (p + 1) + 2 * p + 1;
-  RotSmem<R> sm;
+  const int T = ncoef(p);
+  const int ld = nc + 1;  // padded row: column-wise and row-wise LDS accesses both avoid bank conflicts
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // contiguous runs of target boxes per XCD (blocks are dealt to the 8 XCDs
+  // round-robin), so that neighbouring targets share sources in one L2
+  int b;
   {
-    double* d = reinterpret_cast<double*>(smem);
-    sm.sf = d; d += T;
-    C* cq = reinterpret_cast<C*>(d);
-    sm.rot = cq; cq += rot_len;
-    sm.X = cq; cq += RC * T;
-    sm.Y = cq; cq += RC * T;
-    sm.E1 = cq; cq += RC * (p + 1);
-    sm.E2 = cq; cq += RC * (p + 1);
-    R* rq = reinterpret_cast<R*>(cq);
-    sm.G = rq; rq += RC * (2 * p + 1);
-    int* iq = reinterpret_cast<int*>(rq);
-    sm.colS = iq; iq += RC;
-    sm.colD = iq; iq += RC;
-    sm.roff = iq;
+    const int G = gridDim.x, q = G / 8, r = G % 8, x = blockIdx.x % 8;
+    b = x * q + min(x, r) + blockIdx.x / 8;
   }
-  for (int i = threadIdx.x; i < rot_len; i += ROT_T) {
-    C v;
-    v.x = (R)rot[i].x;
-    v.y = (R)rot[i].y;
-    sm.rot[i] = v;
+  C* X = reinterpret_cast<C*>(smem);
+  ColData cd;
+  {
+    double* dq = reinterpret_cast<double*>(X + (size_t)T * ld);
+    cd.e1x = dq; dq += nc;
+    cd.e1y = dq; dq += nc;
+    cd.e2x = dq; dq += nc;
+    cd.e2y = dq; dq += nc;
+    cd.rinv = dq; dq += nc;
+    cd.wx = dq; dq += nc;
+    cd.wy = dq; dq += nc;
+    cd.wz = dq; dq += nc;
+    cd.src = reinterpret_cast<int*>(dq);
   }
-  for (int i = threadIdx.x; i < T; i += ROT_T) sm.sf[i] = sfac[i];
-  for (int i = threadIdx.x; i < p + 2; i += ROT_T) sm.roff[i] = roff[i];
-  double2* Lb = L + (int64_t)b * ND * T;
-  for (int i = threadIdx.x; i < ND * T; i += ROT_T) Lb[i] = make_double2(0, 0);
+  double2 acc[NACC];
+#pragma unroll
+  for (int r = 0; r < NACC; ++r) acc[r] = make_double2(0.0, 0.0);
+
   const int e0 = V.off[b], e1 = V.off[b + 1];
   const int ncols = (e1 - e0) * ND;
-  for (int c0 = 0; c0 < ncols; c0 += RC) {
-    __syncthreads();
-    if ((int)threadIdx.x < RC) {
-      const int c = threadIdx.x, gc = c0 + c;
-      sm.colS[c] = gc < ncols ? V.ent[e0 + gc / ND] : -1;
-      sm.colD[c] = gc % ND;
-    }
-    __syncthreads();
-    // per-column phases and translation factors from the offset tables
-    const int per = 2 * (p + 1) + 2 * (p + 1) + 2 * p + 1;
-    for (int i = threadIdx.x; i < RC * per; i += ROT_T) {
-      const int c = i / per, k = i % per;
-      const int S = sm.colS[c] >= 0 ? sm.colS[c] : V.ent[e0];
-      const int o = (t.ax[S] - t.ax[b] + 3) * 49 + (t.ay[S] - t.ay[b] + 3) * 7 + (t.az[S] - t.az[b] + 3);
-      const double* q = offtab + (int64_t)o * OT;
-      if (k < 2 * (p + 1)) {
-        R* e = reinterpret_cast<R*>(sm.E1 + c * (p + 1));
-        e[k] = (R)q[k];
-      } else if (k < 4 * (p + 1)) {
-        R* e = reinterpret_cast<R*>(sm.E2 + c * (p + 1));
-        e[k - 2 * (p + 1)] = (R)q[k];
-      } else {
-        sm.G[c * (2 * p + 1) + (k - 4 * (p + 1))] = (R)q[k];
+  const int bx = t.ax[b], by = t.ay[b], bz = t.az[b];
+  const double cbx = t.cx[b], cby = t.cy[b], cbz = t.cz[b];
+
+  for (int c0 = 0; c0 < ncols; c0 += nc) {
+    if (tid < nc) {
+      const int g = c0 + tid;
+      int S = -1;
+      double q0 = 1.0, q1 = 0.0, q2 = 1.0, q3 = 0.0, q4 = 0.5, w0 = 0.0, w1 = 0.0, w2 = 0.0;
+      if (g < ncols) {
+        S = V.ent[e0 + g / ND];
+        const int o = (t.ax[S] - bx + 3) * 49 + (t.ay[S] - by + 3) * 7 + (t.az[S] - bz + 3);
+        const double* gq = geo + (size_t)o * 8;
+        q0 = gq[0];
+        q1 = gq[1];
+        q2 = gq[2];
+        q3 = gq[3];
+        q4 = gq[4];
+        w0 = t.cx[S] - cbx;
+        w1 = t.cy[S] - cby;
+        w2 = t.cz[S] - cbz;
       }
+      cd.src[tid] = S;
+      cd.e1x[tid] = q0;
+      cd.e1y[tid] = q1;
+      cd.e2x[tid] = q2;
+      cd.e2y[tid] = q3;
+      cd.rinv[tid] = q4;
+      cd.wx[tid] = w0;
+      cd.wy[tid] = w1;
+      cd.wz[tid] = w2;
     }
     __syncthreads();
-    // load: multipole (stored R-normalised, box-scaled) -> paper
-    // normalisation, fourth density re-centred on this machine, times E1.
-    for (int i = threadIdx.x; i < RC * T; i += ROT_T) {
-      const int c = i / T, f = i % T;
-      const int S = sm.colS[c];
-      C out;
-      out.x = 0;
-      out.y = 0;
-      if (S >= 0) {
-        const int d = sm.colD[c];
-        const double2* src = M + (int64_t)S * ND * T;
-        double2 v = src[d * T + f];
-        if ((d & 3) == 3) {
-          const int base = d - 3;
-          const double w[3] = {t.cx[S] - t.cx[b], t.cy[S] - t.cy[b], t.cz[S] - t.cz[b]};
-          for (int k = 0; k < 3; ++k) {
-            double2 u = src[(base + k) * T + f];
-            v.x += w[k] * u.x;
-            v.y += w[k] * u.y;
+    // phase 0: gather the batch's multipoles (coefficient-contiguous reads),
+    // re-centre the fourth density on this machine, convert to the paper's
+    // normalisation (times s_n^m) and store them column-wise
+    {
+      int c = tid / T, f = tid - (tid / T) * T;
+      const int cs = RT / T, fs = RT - (RT / T) * T;
+      while (c < nc) {
+        const int S = cd.src[c], d = c % ND;
+        C o;
+        o.x = 0;
+        o.y = 0;
+        if (S >= 0) {
+          const double2* src = M + ((int64_t)S * ND + d) * T + f;
+          double2 v = src[0];
+          if ((d & 3) == 3) {
+            const double2 u0 = src[-3 * T], u1 = src[-2 * T], u2 = src[-T];
+            const double w0 = cd.wx[c], w1 = cd.wy[c], w2 = cd.wz[c];
+            v.x += w0 * u0.x + w1 * u1.x + w2 * u2.x;
+            v.y += w0 * u0.y + w1 * u1.y + w2 * u2.y;
           }
+          const double s = sf[f];
+          o.x = (R)(v.x * s);
+          o.y = (R)(v.y * s);
         }
-        int n = 0;
-        while (tri(n + 1) <= f) ++n;
-        const int m = f - tri(n);
-        const double s = sm.sf[f];
-        const C e = sm.E1[c * (p + 1) + m];
-        double2 ed = make_double2((double)e.x, (double)e.y);
-        v = cmul2(make_double2(v.x * s, v.y * s), ed);
-        out.x = (R)v.x;
-        out.y = (R)v.y;
+        X[f * ld + c] = o;
+        c += cs;
+        f += fs;
+        if (f >= T) {
+          f -= T;
+          ++c;
+        }
       }
-      sm.X[i] = out;
     }
     __syncthreads();
-    dense_step(sm, p, RC, sm.X, sm.Y, false, 1, sm.E2);
-    __syncthreads();
-    dense_step(sm, p, RC, sm.Y, sm.X, true, 0, nullptr);
-    __syncthreads();
-    ztrans_step(sm, p, RC, sm.X, sm.Y);
-    __syncthreads();
-    dense_step(sm, p, RC, sm.Y, sm.X, false, 2, sm.E2);
-    __syncthreads();
-    dense_step(sm, p, RC, sm.X, sm.Y, true, 2, sm.E1);
-    __syncthreads();
-    // sum the columns of each density into this box's local expansion
-    // (paper normalisation -> R-normalised storage, times s_k^l)
-    for (int i = threadIdx.x; i < ND * T; i += ROT_T) {
-      const int d = i / T, f = i % T;
-      double ax = 0.0, ay = 0.0;
-      bool any = false;
-      for (int c = 0; c < RC; ++c)
-        if (sm.colS[c] >= 0 && sm.colD[c] == d) {
-          ax += (double)sm.Y[c * T + f].x;
-          ay += (double)sm.Y[c * T + f].y;
-          any = true;
+    if (lane < nc) {
+      const int nd = sched.ndeg[wv];
+      for (int i = 0; i < nd; ++i) {
+        const int n = sched.deg[wv][i];
+        const R* A = rot + rot_block(n);
+        switch (n) {
+#define RPY_P1(k) \
+  case k: first_half<k, R>(lane, ld, cd, A, X); break;
+          RPY_DEG_CASES(RPY_P1)
+#undef RPY_P1
+          default: break;
         }
-      if (any) {
-        const double s = sm.sf[f];
-        double2 v = Lb[i];
-        Lb[i] = make_double2(v.x + ax * s, v.y + ay * s);
       }
+    }
+    __syncthreads();
+    if (lane < nc) {
+      const int no = sched.nord[wv];
+      for (int i = 0; i < no; ++i) {
+        const int l = sched.ord[wv][i];
+        const int kk = p - l + 1;
+        // rows of orders below l: sum_{l' < l} (p - l' + 1)^2
+        const int zo = (p + 1) * (p + 2) * (2 * p + 3) / 6 - kk * (kk + 1) * (2 * kk + 1) / 6;
+        switch (kk) {
+#define RPY_P2(k) \
+  case k + 1: ztrans<k + 1, R>(l, lane, ld, cd, zt + zo, X); break;
+          RPY_DEG_CASES(RPY_P2)
+#undef RPY_P2
+          default: break;
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < nc) {
+      const int nd = sched.ndeg[wv];
+      for (int i = 0; i < nd; ++i) {
+        const int n = sched.deg[wv][i];
+        const R* A = rot + rot_block(n);
+        switch (n) {
+#define RPY_P3(k) \
+  case k: second_half<k, R>(lane, ld, cd, A, X); break;
+          RPY_DEG_CASES(RPY_P3)
+#undef RPY_P3
+          default: break;
+        }
+      }
+    }
+    __syncthreads();
+    // sum the columns of each (coefficient, density) into the accumulators
+#pragma unroll
+    for (int r = 0; r < NACC; ++r) {
+      const int i = tid + r * RT;
+      if (i < ND * T) {
+        const int f = i / ND, d = i % ND;
+        const C* row = X + (size_t)f * ld + d;
+        double sx = 0.0, sy = 0.0;
+        for (int j = 0; j < nc; j += ND) {
+          const C v = row[j];
+          sx += (double)v.x;
+          sy += (double)v.y;
+        }
+        acc[r].x += sx;
+        acc[r].y += sy;
+      }
+    }
+    __syncthreads();
+  }
+  // paper normalisation -> stored normalisation (times s_k^l)
+  double2* Lb = L + (int64_t)b * ND * T;
+#pragma unroll
+  for (int r = 0; r < NACC; ++r) {
+    const int i = tid + r * RT;
+    if (i < ND * T) {
+      const int f = i / ND, d = i % ND;
+      const double s = sf[f];
+      Lb[(size_t)d * T + f] = make_double2(acc[r].x * s, acc[r].y * s);
     }
   }
 }
 
-static size_t rot_smem_bytes(int p, int RC, int rot_len, size_t real) {
-  const int T = ncoef(p);
-  return sizeof(double) * T + 2 * real * (rot_len + 2 * RC * T + 2 * RC * (p + 1)) + real * RC * (2 * p + 1) +
-         sizeof(int) * (2 * RC + p + 2) + 16;
+// Longest-first assignment of degrees (cost (n+1)^2) and orders (cost
+// (p-l+1)^2) to the block's waves.
+static RotSched make_sched(int p) {
+  RotSched s{};
+  for (int pass = 0; pass < 2; ++pass) {
+    long load[RW] = {0};
+    for (int j = p; j >= 0; --j) {
+      // items in decreasing cost: degree j, or order p - j
+      const int item = pass == 0 ? j : p - j;
+      int w = 0;
+      for (int k = 1; k < RW; ++k)
+        if (load[k] < load[w]) w = k;
+      load[w] += (long)(j + 1) * (j + 1);
+      if (pass == 0) s.deg[w][s.ndeg[w]++] = (unsigned char)item;
+      else s.ord[w][s.nord[w]++] = (unsigned char)item;
+    }
+  }
+  return s;
 }
 
-template <class R>
-static hipError_t launch_rot(const Launch& l, int nrc, Exp e) {
+static size_t rot_smem_bytes(int p, int nc, size_t real) {
+  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * sizeof(double) + sizeof(int));
+}
+
+template <class R, int ND>
+static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const RotSched& sc, const R* rot,
+                            const R* zt) {
   const Built* B = l.B;
-  const int p = l.p;
-  // 16 columns per chunk in FP32, 8 in FP64, fewer only if LDS runs out
-  int RC = sizeof(R) == 4 ? 16 : 8;
-  while (RC > 1 && rot_smem_bytes(p, RC, l.tb->rot_len, sizeof(R)) > 80 * 1024) RC /= 2;
-  size_t shm = rot_smem_bytes(p, RC, l.tb->rot_len, sizeof(R));
-  if (shm > 160 * 1024) return hipErrorInvalidValue;
-  switch (nrc) {
-    case 1: k_m2l_rot<4, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
-    case 2: k_m2l_rot<8, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
-    case 4: k_m2l_rot<16, R><<<B->tree.nbox, ROT_T, shm, l.s>>>(p, RC, B->tree, B->lists[LV], l.tb->rot, l.tb->rot_off, l.tb->rot_len, l.tb->sfac, l.tb->offtab, e.M, e.L); break;
-    default: return hipErrorInvalidValue;
-  }
+  auto kern = k_m2l_rot<ND, R>;
+  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (he != hipSuccess) return he;
+  kern<<<B->tree.nbox, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
+                                       l.tb->sfac, e.M, e.L);
   return hipGetLastError();
 }
 
+template <class R>
+static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, const R* zt) {
+  const int p = l.p;
+  if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
+  if (l.B->tree.nbox == 0) return hipSuccess;
+  // 64 columns per batch, 32 when the LDS (160 KB per CU) cannot hold 64
+  int nc = 64;
+  if (rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc = 32;
+  const size_t shm = rot_smem_bytes(p, nc, sizeof(R));
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  const RotSched sc = make_sched(p);
+  switch (nrc) {
+    case 1: return launch_nd<R, 4>(l, e, nc, shm, sc, rot, zt);
+    case 2: return launch_nd<R, 8>(l, e, nc, shm, sc, rot, zt);
+    case 4: return launch_nd<R, 16>(l, e, nc, shm, sc, rot, zt);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32) {
-  return fp32 ? launch_rot<float>(l, nrc, e) : launch_rot<double>(l, nrc, e);
+  return fp32 ? launch_rot<float>(l, nrc, e, l.tb->rot32, l.tb->zt32)
+              : launch_rot<double>(l, nrc, e, l.tb->rot64, l.tb->zt64);
 }
 
 }  // namespace rpy
