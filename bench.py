@@ -189,6 +189,19 @@ def run(args):
     return 0
 
 
+def copy_probe(mib):
+    """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,10 +213,14 @@ def main():
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--m2l", default="auto", choices=["auto", "dense", "rotation"],
                     help="multipole-to-local operator (auto = the library's choice per precision)")
     args = ap.parse_args()
     args.precisions = [p.strip() for p in args.precisions.split(",") if p.strip()]
+    if args.copy_probe > 0:
+        return copy_probe(args.copy_probe)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)

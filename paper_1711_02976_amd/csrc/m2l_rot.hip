@@ -295,36 +295,36 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
     }
     __syncthreads();
     // phase 0: gather the batch's multipoles (coefficient-contiguous reads),
-    // re-centre the fourth density on this machine, convert to the paper's
-    // normalisation (times s_n^m) and store them column-wise
+    // convert to the paper's normalisation (times s_n^m) and store them
+    // column-wise.  A thread takes the four densities of one right-hand side
+    // of one source at one coefficient, so the fourth density is re-centred
+    // on this machine from registers: M4 + (c_S - c_B) . (M1, M2, M3).
     {
-      int c = tid / T, f = tid - (tid / T) * T;
-      const int cs = RT / T, fs = RT - (RT / T) * T;
-      while (c < nc) {
-        const int S = cd.src[c], d = c % ND;
-        C o;
-        o.x = 0;
-        o.y = 0;
+      const int ng = nc / 4;  // (source, rhs) groups in the batch
+      for (int it = tid; it < ng * T; it += RT) {
+        const int g = it / T, f = it - (it / T) * T;
+        const int c = 4 * g, S = cd.src[c];
+        C o[4];
         if (S >= 0) {
-          const double2* src = M + ((int64_t)S * ND + d) * T + f;
-          double2 v = src[0];
-          if ((d & 3) == 3) {
-            const double2 u0 = src[-3 * T], u1 = src[-2 * T], u2 = src[-T];
-            const double w0 = cd.wx[c], w1 = cd.wy[c], w2 = cd.wz[c];
-            v.x += w0 * u0.x + w1 * u1.x + w2 * u2.x;
-            v.y += w0 * u0.y + w1 * u1.y + w2 * u2.y;
-          }
+          const double2* src = M + ((int64_t)S * ND + (c % ND)) * T + f;
+          double2 v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = src[k * T];
+          const double w0 = cd.wx[c], w1 = cd.wy[c], w2 = cd.wz[c];
+          v[3].x += w0 * v[0].x + w1 * v[1].x + w2 * v[2].x;
+          v[3].y += w0 * v[0].y + w1 * v[1].y + w2 * v[2].y;
           const double s = sf[f];
-          o.x = (R)(v.x * s);
-          o.y = (R)(v.y * s);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            o[k].x = (R)(v[k].x * s);
+            o[k].y = (R)(v[k].y * s);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) o[k].x = o[k].y = 0;
         }
-        X[f * ld + c] = o;
-        c += cs;
-        f += fs;
-        if (f >= T) {
-          f -= T;
-          ++c;
-        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) X[f * ld + c + k] = o[k];
       }
     }
     __syncthreads();

@@ -10,6 +10,8 @@
 // (positions and forces, SoA) and read back as wave-wide broadcasts.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fmm.h"
 
 namespace rpy {
@@ -71,14 +73,6 @@ struct RpyConst {
   double c0k3;    // c0 * 3/(32a)
 };
 
-// 1/r from the single-precision estimate refined by one Newton step
-// (relative error below 2^-44); 0 for coincident beads (r^2 < 1e-30).
-__device__ inline double rinv64(double r2) {
-  double y = (double)__builtin_amdgcn_rsqf((float)r2);
-  y = y * fma(-0.5 * r2, y * y, 1.5);
-  return r2 < 1e-30 ? 0.0 : y;
-}
-
 // Far (r >= 2a) block: A = c1/r (1 + 2a^2/(3r^2)), B = c1/r^3 (1 - 2a^2/r^2).
 __device__ inline void rpy_far(double rinv, const RpyConst& k, double& A, double& B) {
   const double ri2 = rinv * rinv, ri3 = ri2 * rinv;
@@ -92,19 +86,53 @@ __device__ inline void rpy_overlap(double r2, double rinv, const RpyConst& k, do
   B = k.c0k3 * rinv;
 }
 
-struct RpyConstF {
-  float c0, c1, c1a3, c1a2, four_a2, k9, c0k3;
+// Pair coefficients of the P2P sum with the far prefactor c1 = 1/(8 pi eta)
+// taken out of the sum (applied once per target):
+//   far      A' = 1/r + (2a^2/3)/r^3,        B' = (1 - 2a^2/r^2)/r^3,
+//   overlap  A' = (c0/c1)(1 - 9r/(32a)),     B' = (c0/c1)(3/(32a))/r.
+template <class R>
+struct PairK {
+  R a3;       // 2a^2/3
+  R a2;       // 2a^2
+  R four_a2;  // (2a)^2
+  R oc;       // c0/c1
+  R ock9;     // (c0/c1) 9/(32a)
+  R ob;       // (c0/c1) 3/(32a)
+  R r2min;    // clamp of r^2 before the reciprocal square root (coincident beads)
 };
+
+template <class R>
+static PairK<R> pair_const(const RpyConst& k, double a) {
+  const double oc = k.c0 / k.c1;
+  return PairK<R>{(R)(2.0 * a * a / 3.0), (R)(2.0 * a * a), (R)k.four_a2, (R)oc, (R)(oc * k.k9),
+                  (R)(oc * 3.0 / (32.0 * a)), (R)1e-30};
+}
+
+__device__ inline float rinv_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
+// single-precision estimate refined by one Newton step (relative error
+// below 2^-44); r2 >= 1e-30 here, so the estimate is finite
+__device__ inline double rinv_of(double r2) {
+  double y = (double)__builtin_amdgcn_rsqf((float)r2);
+  return y * fma(-0.5 * r2, y * y, 1.5);
+}
 
 // --------------------------------------------------------------- P2P -----
 // The overlap formula is evaluated only when some lane of the wave has a
-// source closer than 2a (a wave-uniform branch), since such pairs are rare.
+// source closer than 2a (a wave-uniform branch), since such pairs are rare
+// apart from each target's own bead.  For r = 0 (the bead itself, or a
+// coincident bead) r^2 is clamped before the reciprocal square root: the far
+// values are then finite and discarded, and the overlap values give the
+// r -> 0 limit A' = c0/c1, B' d = 0.
+// In the mixed form the pair difference is formed in FP64 and rounded, and
+// the pair arithmetic and per-source-leaf sums run in FP32.
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
-                                               RpyConst k, RpyConstF kf, double* u) {
+                                               PairK<typename std::conditional<MIXED, float, double>::type> k,
+                                               double c1, double* u) {
+  using R = typename std::conditional<MIXED, float, double>::type;
   __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
-  __shared__ double fs[NRC * 3][P2P_T];
+  __shared__ R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
@@ -112,76 +140,58 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   const double xi = sx[i], yi = sy[i], zi = sz[i];
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
-  for (int e = U.off[b]; e < U.off[b + 1]; ++e) {
-    const int C = U.ent[e];
-    const int j1 = t.end[C];
-    for (int jc = t.begin[C]; jc < j1; jc += P2P_T) {
+  const int e0 = __builtin_amdgcn_readfirstlane(U.off[b]), e1 = __builtin_amdgcn_readfirstlane(U.off[b + 1]);
+  for (int e = e0; e < e1; ++e) {
+    const int C = __builtin_amdgcn_readfirstlane(U.ent[e]);
+    const int j1 = __builtin_amdgcn_readfirstlane(t.end[C]);
+    for (int jc = __builtin_amdgcn_readfirstlane(t.begin[C]); jc < j1; jc += P2P_T) {
       const int ns = min(P2P_T, j1 - jc);
+      // the tile is padded to a multiple of 4 sources with inert ones: zero
+      // force at 1e30, where 1/r, A' and B' all evaluate to exactly zero
+      const int ns4 = (ns + 3) & ~3;
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
         xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
-        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = sF[(int64_t)q * n + j];
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
+      } else if ((int)threadIdx.x < ns4) {
+        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
-      if (MIXED) {
-        float af[NRC][3];
-        for (int r = 0; r < NRC; ++r) af[r][0] = af[r][1] = af[r][2] = 0.0f;
-#pragma unroll 2
-        for (int s = 0; s < ns; ++s) {
-          const float dx = (float)(xi - xs[s]), dy = (float)(yi - ys[s]), dz = (float)(zi - zs[s]);
-          const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          const float rinv = r2 < 1e-30f ? 0.0f : __builtin_amdgcn_rsqf(r2);
-          const float ri2 = rinv * rinv, ri3 = ri2 * rinv;
-          float A = fmaf(kf.c1a3, ri3, kf.c1 * rinv);
-          float B = fmaf(-kf.c1a2 * ri2, ri3, kf.c1 * ri3);
-          const bool ov = r2 < kf.four_a2;
-          if (__builtin_expect(__any(ov), 0)) {
-            const float Ao = kf.c0 * fmaf(-kf.k9, r2 * rinv, 1.0f), Bo = kf.c0k3 * rinv;
-            A = ov ? Ao : A;
-            B = ov ? Bo : B;
-          }
+      R ar[NRC][3];
+      for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
+      for (int s0 = 0; s0 < ns4; s0 += 4)
 #pragma unroll
-          for (int r = 0; r < NRC; ++r) {
-            const float fx = (float)fs[3 * r][s], fy = (float)fs[3 * r + 1][s], fz = (float)fs[3 * r + 2][s];
-            const float sdf = B * fmaf(dx, fx, fmaf(dy, fy, dz * fz));
-            af[r][0] = fmaf(A, fx, fmaf(sdf, dx, af[r][0]));
-            af[r][1] = fmaf(A, fy, fmaf(sdf, dy, af[r][1]));
-            af[r][2] = fmaf(A, fz, fmaf(sdf, dz, af[r][2]));
-          }
+      for (int s = s0; s < s0 + 4; ++s) {
+        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const R rinv = rinv_of(max(r2, k.r2min));
+        const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
+        R A = fma(k.a3, ri3, rinv);
+        R B = ri3 * fma(-k.a2, ri2, (R)1);
+        const bool ov = r2 < k.four_a2;
+        if (__builtin_expect(__any(ov), 0)) {
+          const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
+          A = ov ? Ao : A;
+          B = ov ? Bo : B;
         }
-        for (int r = 0; r < NRC; ++r)
-          for (int c = 0; c < 3; ++c) acc[r][c] += (double)af[r][c];
-      } else {
-#pragma unroll 2
-        for (int s = 0; s < ns; ++s) {
-          const double dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          const double rinv = rinv64(r2);
-          double A, B;
-          rpy_far(rinv, k, A, B);
-          const bool ov = r2 < k.four_a2;
-          if (__builtin_expect(__any(ov), 0)) {
-            double Ao, Bo;
-            rpy_overlap(r2, rinv, k, Ao, Bo);
-            A = ov ? Ao : A;
-            B = ov ? Bo : B;
-          }
 #pragma unroll
-          for (int r = 0; r < NRC; ++r) {
-            const double fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
-            const double sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
-            acc[r][0] = fma(A, fx, fma(sdf, dx, acc[r][0]));
-            acc[r][1] = fma(A, fy, fma(sdf, dy, acc[r][1]));
-            acc[r][2] = fma(A, fz, fma(sdf, dz, acc[r][2]));
-          }
+        for (int r = 0; r < NRC; ++r) {
+          const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
+          const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
+          ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
+          ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
+          ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
         }
       }
+      for (int r = 0; r < NRC; ++r)
+        for (int c = 0; c < 3; ++c) acc[r][c] += (double)ar[r][c];
     }
   }
   if (valid)
     for (int r = 0; r < NRC; ++r)
-      for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] = acc[r][c];
+      for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] = c1 * acc[r][c];
 }
 
 // ------------------------------------------------------- overlap (O) -----
@@ -247,22 +257,20 @@ static RpyConst rpy_const(double a, double eta) {
   return k;
 }
 
-static RpyConstF rpy_const_f(const RpyConst& k) {
-  return RpyConstF{(float)k.c0, (float)k.c1, (float)k.c1a3, (float)k.c1a2, (float)k.four_a2, (float)k.k9,
-                   (float)k.c0k3};
-}
-
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   if (tiles.n == 0) return hipSuccess;
   const Built* B = l.B;
-  RpyConst k = rpy_const(l.a, l.eta);
-  RpyConstF kf = rpy_const_f(k);
-#define P2P_CASE(NR)                                                                                            \
-  case NR:                                                                                                      \
-    if (mixed)                                                                                                  \
-      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, kf, u); \
-    else                                                                                                        \
-      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, k, kf, u); \
+  const RpyConst k = rpy_const(l.a, l.eta);
+  const PairK<float> kf = pair_const<float>(k, l.a);
+  const PairK<double> kd = pair_const<double>(k, l.a);
+#define P2P_CASE(NR)                                                                                               \
+  case NR:                                                                                                         \
+    if (mixed)                                                                                                     \
+      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, kf, \
+                                                  k.c1, u);                                                        \
+    else                                                                                                           \
+      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, kd, \
+                                                   k.c1, u);                                                       \
     break;
   switch (nrc) {
     P2P_CASE(1)
