@@ -35,6 +35,7 @@ struct Tables {
   float* zt32;
   double* geo;
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
+  double* rnm;     // [ncoef(p+2)] 1/((n+m)(n-m)) (0 for n < m+2)
   int rot_len;     // sum_n (n+1)^2
   int zt_len;      // sum_l (p-l+1)^2
   int64_t bytes;

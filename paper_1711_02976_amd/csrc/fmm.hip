@@ -46,7 +46,7 @@ __device__ inline double2 getc(const double2* C, int n, int m, int nmax) {
 }
 
 // Column m of the regular harmonics R_n^m(v), n = m..nmax, into H[tri(n)+m].
-__device__ inline void regular_column(double x, double y, double z, int m, int nmax, double2* H) {
+__device__ inline void regular_column(double x, double y, double z, int m, int nmax, const double* rnm, double2* H) {
   double r2 = x * x + y * y + z * z;
   double2 rmm = make_double2(1.0, 0.0);
   for (int k = 1; k <= m; ++k) {
@@ -60,7 +60,7 @@ __device__ inline void regular_column(double x, double y, double z, int m, int n
   H[tri(m + 1) + m] = r1;
   double2 r0 = rmm;
   for (int n = m + 2; n <= nmax; ++n) {
-    double inv = 1.0 / ((double)(n + m) * (n - m));
+    const double inv = rnm[tri(n) + m];
     double a = (2 * n - 1) * z * inv, b = r2 * inv;
     double2 rn = make_double2(a * r1.x - b * r0.x, a * r1.y - b * r0.y);
     H[tri(n) + m] = rn;
@@ -292,6 +292,10 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
         rot[off + mp * K + j++] = D[(size_t)(mp + n) * W + (m + n)] - D[(size_t)(mp + n) * W + (n - m)];
     }
   }
+  // 1/((n+m)(n-m)) for the regular-harmonic recurrence, degrees <= p + 2
+  std::vector<double> rnm(ncoef(p + 2), 0.0);
+  for (int n = 0; n <= p + 2; ++n)
+    for (int m = 0; m + 2 <= n; ++m) rnm[tri(n) + m] = 1.0 / ((double)(n + m) * (n - m));
   std::vector<double> sf(ncoef(p));
   for (int n = 0; n <= p; ++n)
     for (int m = 0; m <= n; ++m) {
@@ -343,8 +347,10 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   RPY_HIP(hipMalloc(&tb->zt32, sizeof(float) * zt32.size()));
   RPY_HIP(hipMalloc(&tb->geo, sizeof(double) * geo.size()));
   RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
+  RPY_HIP(hipMalloc(&tb->rnm, sizeof(double) * rnm.size()));
+  RPY_HIP(hipMemcpy(tb->rnm, rnm.data(), sizeof(double) * rnm.size(), hipMemcpyHostToDevice));
   tb->bytes = sizeof(double2) * (oct.size() + itab.size()) + (sizeof(double) + sizeof(float)) * (rot.size() + zt.size()) +
-              sizeof(double) * (geo.size() + sf.size());
+              sizeof(double) * (geo.size() + sf.size() + rnm.size());
   RPY_HIP(hipMemcpy(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->rot64, rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice));
@@ -358,11 +364,11 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
 }
 
 void free_tables(Tables* tb) {
-  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac};
+  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rnm};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   tb->oct = tb->itab = nullptr;
-  tb->rot64 = tb->zt64 = tb->geo = tb->sfac = nullptr;
+  tb->rot64 = tb->zt64 = tb->geo = tb->sfac = tb->rnm = nullptr;
   tb->rot32 = tb->zt32 = nullptr;
 }
 
@@ -414,7 +420,7 @@ constexpr int P2E_CH = 16;
 template <int ND, bool LOCAL>
 __global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, List X, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
-                                               double2* E) {
+                                               const double* __restrict__ rnm, double2* E) {
   constexpr int NRC = ND / 4;
   const int T = ncoef(p);
   const int b = ids ? ids[blockIdx.x] : blockIdx.x;
@@ -424,7 +430,7 @@ __global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, Li
     s1 = X.off[b + 1];
     if (s0 == s1) return;
   }
-  __shared__ double2 H[P2E_CH * ncoef(MAX_ORDER)];
+  extern __shared__ double2 H[];  // P2E_CH * ncoef(p)
   __shared__ double q[P2E_CH][ND];
   __shared__ double xi[P2E_CH][3];
   const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
@@ -451,7 +457,7 @@ __global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, Li
       for (int w = threadIdx.x; w < nb * (p + 1); w += P2E_T) {
         int bj = w / (p + 1), m = w % (p + 1);
         if (LOCAL) irregular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, H + bj * T);
-        else regular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, H + bj * T);
+        else regular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, rnm, H + bj * T);
       }
       __syncthreads();
       if (threadIdx.x < T) {
@@ -486,62 +492,56 @@ __global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, Li
 // M_n^m(P) = sum_{k<=n,l} 2^-k M_k^l(C) conj(R_{n-k}^{m-l}(d/h_P)).
 constexpr int TR_T = 256;
 
+// One block per (parent box, density): thread t = output (n,m), summing the
+// children's translated multipoles in turn (Rt and the child's density
+// staged in LDS; the fourth density re-centred on the child first).
 template <int ND>
 __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const double2* oct, double2* M) {
-  const int b = ls + blockIdx.x;
+  const int b = ls + blockIdx.x, d = blockIdx.y;
   const int nc = t.nchild[b];
   if (nc == 0) return;
   const int T = ncoef(p), F1 = (p + 1) * (p + 1);
   extern __shared__ double2 sm[];
   double2* Rt = sm;        // F1
-  double2* Mc = sm + F1;   // ND * F1
-  double2 acc[ND];
-  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  double2* Mc = sm + F1;   // F1
+  double2 acc = make_double2(0, 0);
   int n = 0, m = 0;
   if (threadIdx.x < T) {
-    n = (int)floor((sqrt(8.0 * threadIdx.x + 1.0) - 1.0) * 0.5);
     while (tri(n + 1) <= (int)threadIdx.x) ++n;
-    while (tri(n) > (int)threadIdx.x) --n;
     m = threadIdx.x - tri(n);
   }
+  const int dd = d & 3, base = d - dd;
   for (int C = t.child[b]; C < t.child[b] + nc; ++C) {
     const int o = (t.ax[C] & 1) | ((t.ay[C] & 1) << 1) | ((t.az[C] & 1) << 2);
     const double w[3] = {t.cx[C] - t.cx[b], t.cy[C] - t.cy[b], t.cz[C] - t.cz[b]};
     __syncthreads();
     for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
     const double2* src = M + (int64_t)C * ND * T;
-    for (int i = threadIdx.x; i < ND * F1; i += TR_T) {
-      int d = i / F1, f = i % F1;
+    for (int f = threadIdx.x; f < F1; f += TR_T) {
       int k = (int)sqrt((double)f);
       while (k * k > f) --k;
       while ((k + 1) * (k + 1) <= f) ++k;
-      int l = f - k * k - k;
-      int dd = d & 3, base = d - dd;
+      const int l = f - k * k - k;
       double2 v = getc(src + d * T, k, l, p);
       if (dd == 3)
         for (int c = 0; c < 3; ++c) {
-          double2 u = getc(src + (base + c) * T, k, l, p);
+          const double2 u = getc(src + (base + c) * T, k, l, p);
           v.x += w[c] * u.x;
           v.y += w[c] * u.y;
         }
-      double sc = ldexp(1.0, -k);
-      Mc[d * F1 + f] = make_double2(v.x * sc, v.y * sc);
+      const double sc = ldexp(1.0, -k);
+      Mc[f] = make_double2(v.x * sc, v.y * sc);
     }
     __syncthreads();
     if (threadIdx.x < T) {
       for (int k = 0; k <= n; ++k) {
-        int j = n - k;
-        int lmin = max(-k, m - j), lmax = min(k, m + j);
-        for (int l = lmin; l <= lmax; ++l) {
-          double2 r = Rt[fidx(j, m - l)];
-#pragma unroll
-          for (int d = 0; d < ND; ++d) cfmac(acc[d], Mc[d * F1 + fidx(k, l)], r);
-        }
+        const int j = n - k;
+        const int lmin = max(-k, m - j), lmax = min(k, m + j);
+        for (int l = lmin; l <= lmax; ++l) cfmac(acc, Mc[fidx(k, l)], Rt[fidx(j, m - l)]);
       }
     }
   }
-  if (threadIdx.x < T)
-    for (int d = 0; d < ND; ++d) M[(int64_t)b * ND * T + d * T + threadIdx.x] = acc[d];
+  if (threadIdx.x < T) M[(int64_t)b * ND * T + d * T + threadIdx.x] = acc;
 }
 
 // ------------------------------------------------------------------ L->L --
@@ -549,55 +549,47 @@ __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const doubl
 // L_k^l(C) += 2^-(k+1) sum_{n>=k,m} L_n^m(P) R_{n-k}^{m-l}(d/h_P).
 template <int ND>
 __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const double2* oct, double2* L) {
-  const int b = ls + blockIdx.x;
+  const int b = ls + blockIdx.x, d = blockIdx.y;
   const int P = t.parent[b];
   if (P < 0) return;
   const int T = ncoef(p), F1 = (p + 1) * (p + 1);
   extern __shared__ double2 sm[];
   double2* Rt = sm;        // F1
-  double2* Lp = sm + F1;   // ND * F1
+  double2* Lp = sm + F1;   // F1
   const int o = (t.ax[b] & 1) | ((t.ay[b] & 1) << 1) | ((t.az[b] & 1) << 2);
   const double w[3] = {t.cx[P] - t.cx[b], t.cy[P] - t.cy[b], t.cz[P] - t.cz[b]};
   for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
   const double2* src = L + (int64_t)P * ND * T;
-  for (int i = threadIdx.x; i < ND * F1; i += TR_T) {
-    int d = i / F1, f = i % F1;
+  const int dd = d & 3, base = d - dd;
+  for (int f = threadIdx.x; f < F1; f += TR_T) {
     int k = (int)sqrt((double)f);
     while (k * k > f) --k;
     while ((k + 1) * (k + 1) <= f) ++k;
-    int l = f - k * k - k;
-    int dd = d & 3, base = d - dd;
+    const int l = f - k * k - k;
     double2 v = getc(src + d * T, k, l, p);
     if (dd == 3)
       for (int c = 0; c < 3; ++c) {
-        double2 u = getc(src + (base + c) * T, k, l, p);
+        const double2 u = getc(src + (base + c) * T, k, l, p);
         v.x += w[c] * u.x;
         v.y += w[c] * u.y;
       }
-    Lp[d * F1 + f] = v;
+    Lp[f] = v;
   }
   __syncthreads();
   if (threadIdx.x >= T) return;
   int k = 0;
   while (tri(k + 1) <= (int)threadIdx.x) ++k;
   const int l = threadIdx.x - tri(k);
-  double2 acc[ND];
-  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
+  double2 acc = make_double2(0, 0);
   for (int n = k; n <= p; ++n) {
-    int j = n - k;
-    int mmin = max(-n, l - j), mmax = min(n, l + j);
-    for (int m = mmin; m <= mmax; ++m) {
-      double2 r = Rt[fidx(j, m - l)];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) cfma(acc[d], Lp[d * F1 + fidx(n, m)], r);
-    }
+    const int j = n - k;
+    const int mmin = max(-n, l - j), mmax = min(n, l + j);
+    for (int m = mmin; m <= mmax; ++m) cfma(acc, Lp[fidx(n, m)], Rt[fidx(j, m - l)]);
   }
   const double sc = ldexp(1.0, -(k + 1));
-  double2* out = L + (int64_t)b * ND * T + threadIdx.x;
-  for (int d = 0; d < ND; ++d) {
-    double2 v = out[d * T];
-    out[d * T] = make_double2(v.x + sc * acc[d].x, v.y + sc * acc[d].y);
-  }
+  double2* out = L + (int64_t)b * ND * T + d * T + threadIdx.x;
+  const double2 v = *out;
+  *out = make_double2(v.x + sc * acc.x, v.y + sc * acc.y);
 }
 
 // ----------------------------------------------------------- M->L (V) -----
@@ -694,181 +686,225 @@ __device__ inline double2 dcoef(const double2* C, int nmax, int n, int m, int ax
 
 // Build the 12 derived sets (E_x,E_y,E_z,G_xx,G_xy,G_xz,G_yx,...) of degree
 // <= nout from the four sets in src (degree <= nin).  scale = 1/h.
-__device__ void derived_sets(const double2* src, int nin, int nout, bool mult, double ih, double C1, double C2,
-                             double2* D, double2* LC, double2* G1) {
+// Builds the 12 evaluation sets of one expansion in LDS:
+//   D[3 + 3i + k] = h^-2 d_i L_k          (k, i = 0..2),
+//   D[i]          = C1 h^-1 L_i + C1 h^-2 d_i L_4 - C2 h^-3 d_i L_C,
+// with L_C = sum_k d_k L_k, so that at a target x (offset v from the centre)
+//   u_i = Re sum_c [D_i - C1 sum_k v_k D_{3+3i+k}]_c h_c(x/h)
+// (eq. 2.8 with Theorem 2, or Theorem 1 for a multipole: mult = true, sets
+// of degree nin + 2).  G4 (3 sets) and LC are scratch.
+__device__ void derived_sets(const double2* src, int nin, int nout, bool mult, double h, double C1, double C2,
+                             double2* D, double2* G4, double2* LC) {
   const int To = ncoef(nout);
-  // G1[k][i] = d_i L_k for k = 0..3 (sets of degree <= nout), and the L_C set.
+  const double ih = 1.0 / h, ih2 = ih * ih, ih3 = ih2 * ih;
   for (int w = threadIdx.x; w < 12 * To; w += EV_T) {
-    int k = w / (3 * To), rem = w % (3 * To), i = rem / To, c = rem % To;
+    const int k = w / (3 * To), rem = w - k * 3 * To, i = rem / To, c = rem - i * To;
     int n = 0;
     while (tri(n + 1) <= c) ++n;
-    int m = c - tri(n);
-    G1[w] = dcoef(src + k * ncoef(nin), nin, n, m, i, mult);
+    const int m = c - tri(n);
+    const double2 g = dcoef(src + k * ncoef(nin), nin, n, m, i, mult);
+    if (k < 3) D[(3 + 3 * i + k) * To + c] = make_double2(ih2 * g.x, ih2 * g.y);
+    else G4[i * To + c] = g;
   }
   __syncthreads();
+  const double h2 = h * h;
   for (int c = threadIdx.x; c < To; c += EV_T) {
-    double2 a = G1[0 * 3 * To + 0 * To + c], b = G1[1 * 3 * To + 1 * To + c], d = G1[2 * 3 * To + 2 * To + c];
-    LC[c] = make_double2(a.x + b.x + d.x, a.y + b.y + d.y);
+    const double2 a = D[3 * To + c], b = D[7 * To + c], d = D[11 * To + c];
+    LC[c] = make_double2(h2 * (a.x + b.x + d.x), h2 * (a.y + b.y + d.y));
   }
   __syncthreads();
-  const double ih2 = ih * ih, ih3 = ih2 * ih;
   for (int w = threadIdx.x; w < 3 * To; w += EV_T) {
-    int i = w / To, c = w % To;
+    const int i = w / To, c = w - i * To;
     int n = 0;
     while (tri(n + 1) <= c) ++n;
-    int m = c - tri(n);
-    double2 l = getc(src + i * ncoef(nin), n, m, nin);
-    double2 g4 = G1[3 * 3 * To + i * To + c];
-    double2 dc = dcoef(LC, nout, n, m, i, mult);
+    const int m = c - tri(n);
+    const double2 l = getc(src + i * ncoef(nin), n, m, nin);
+    const double2 g4 = G4[i * To + c];
+    const double2 dc = dcoef(LC, nout, n, m, i, mult);
     D[i * To + c] = make_double2(C1 * ih * l.x + C1 * ih2 * g4.x - C2 * ih3 * dc.x,
                                  C1 * ih * l.y + C1 * ih2 * g4.y - C2 * ih3 * dc.y);
   }
-  for (int w = threadIdx.x; w < 9 * To; w += EV_T) {
-    int i = w / (3 * To), rem = w % (3 * To), k = rem / To, c = rem % To;
-    double2 g = G1[k * 3 * To + i * To + c];
-    D[(3 + 3 * i + k) * To + c] = make_double2(ih2 * g.x, ih2 * g.y);
-  }
   __syncthreads();
 }
 
-// Sum the 12 sets against the target's harmonics (regular or irregular) of
-// xi, n <= nmax, generating columns on the fly.
-template <bool MULT>
-__device__ inline void apply_sets(const double2* D, int nmax, double x, double y, double z, const double v[3],
-                                  double C1, double u[3]) {
+// Evaluates the 12 sets at BPT targets per thread (x, y, z in box units, v
+// the offset in absolute units) and adds u.  Regular harmonics R_n^m
+// (local expansion) or irregular I_n^m (multipole, MULT) by recurrence in m
+// and then n; each set coefficient read from LDS serves all BPT targets.
+// rnm[tri(n)+m] = 1/((n+m)(n-m)).
+template <bool MULT, int BPT>
+__device__ inline void apply_sets(const double2* D, int nmax, const double* __restrict__ rnm, const double* x,
+                                  const double* y, const double* z, const double (*v)[3], double C1, double (*u)[3]) {
   const int To = ncoef(nmax);
-  double s[12];
-  for (int e = 0; e < 12; ++e) s[e] = 0.0;
-  double r2 = x * x + y * y + z * z;
-  double ir2 = MULT ? 1.0 / r2 : 0.0;
-  double2 hmm = make_double2(MULT ? sqrt(ir2) : 1.0, 0.0);
+  double s[BPT][12];
+  double r2[BPT], ir2[BPT];
+  double2 hmm[BPT];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+#pragma unroll
+    for (int e = 0; e < 12; ++e) s[q][e] = 0.0;
+    r2[q] = x[q] * x[q] + y[q] * y[q] + z[q] * z[q];
+    ir2[q] = MULT ? 1.0 / r2[q] : 0.0;
+    hmm[q] = make_double2(MULT ? sqrt(ir2[q]) : 1.0, 0.0);
+  }
   for (int m = 0; m <= nmax; ++m) {
-    if (m > 0) {
-      double f = MULT ? -(2 * m - 1) * ir2 : -0.5 / m;
-      hmm = make_double2(f * (x * hmm.x - y * hmm.y), f * (x * hmm.y + y * hmm.x));
-    }
     const double wm = m ? 2.0 : 1.0;
-    double2 hm2 = make_double2(0, 0), hm1 = make_double2(0, 0);
-    for (int n = m; n <= nmax; ++n) {
-      double2 h;
-      if (n == m) {
-        h = hmm;
-      } else if (n == m + 1) {
-        double f = MULT ? (2 * m + 1) * z * ir2 : z;
-        h = make_double2(f * hmm.x, f * hmm.y);
-      } else if (MULT) {
-        double a = (2 * n - 1) * z * ir2, bb = (double)(n + m - 1) * (n - m - 1) * ir2;
-        h = make_double2(a * hm1.x - bb * hm2.x, a * hm1.y - bb * hm2.y);
-      } else {
-        double inv = 1.0 / ((double)(n + m) * (n - m));
-        double a = (2 * n - 1) * z * inv, bb = r2 * inv;
-        h = make_double2(a * hm1.x - bb * hm2.x, a * hm1.y - bb * hm2.y);
+    double2 h1[BPT], h2[BPT];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      if (m > 0) {
+        const double f = MULT ? -(2 * m - 1) * ir2[q] : -0.5 / m;
+        hmm[q] = make_double2(f * (x[q] * hmm[q].x - y[q] * hmm[q].y), f * (x[q] * hmm[q].y + y[q] * hmm[q].x));
       }
-      hm2 = hm1;
-      hm1 = h;
+      h1[q] = make_double2(0, 0);
+      h2[q] = make_double2(0, 0);
+    }
+    for (int n = m; n <= nmax; ++n) {
       const int c = tri(n) + m;
-      const double hx = wm * h.x, hy = wm * h.y;
+      const double inv = rnm[c];
+      double hx[BPT], hy[BPT];
+#pragma unroll
+      for (int q = 0; q < BPT; ++q) {
+        double2 hv;
+        if (n == m) {
+          hv = hmm[q];
+        } else if (n == m + 1) {
+          const double f = MULT ? (2 * m + 1) * z[q] * ir2[q] : z[q];
+          hv = make_double2(f * hmm[q].x, f * hmm[q].y);
+        } else if (MULT) {
+          const double a = (2 * n - 1) * z[q] * ir2[q], bb = (double)(n + m - 1) * (n - m - 1) * ir2[q];
+          hv = make_double2(a * h1[q].x - bb * h2[q].x, a * h1[q].y - bb * h2[q].y);
+        } else {
+          const double a = (2 * n - 1) * z[q] * inv, bb = r2[q] * inv;
+          hv = make_double2(a * h1[q].x - bb * h2[q].x, a * h1[q].y - bb * h2[q].y);
+        }
+        h2[q] = h1[q];
+        h1[q] = hv;
+        hx[q] = wm * hv.x;
+        hy[q] = wm * hv.y;
+      }
 #pragma unroll
       for (int e = 0; e < 12; ++e) {
-        double2 q = D[e * To + c];
-        s[e] = fma(q.x, hx, fma(-q.y, hy, s[e]));
+        const double2 d = D[e * To + c];
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) s[q][e] = fma(d.x, hx[q], fma(-d.y, hy[q], s[q][e]));
       }
     }
   }
-  for (int i = 0; i < 3; ++i) {
-    double t = s[i];
-    for (int k = 0; k < 3; ++k) t -= C1 * v[k] * s[3 + 3 * i + k];
-    u[i] += t;
-  }
+#pragma unroll
+  for (int q = 0; q < BPT; ++q)
+    for (int i = 0; i < 3; ++i) {
+      double t = s[q][i];
+      for (int k = 0; k < 3; ++k) t -= C1 * v[q][k] * s[q][3 + 3 * i + k];
+      u[q][i] += t;
+    }
 }
 
+// Target evaluation, one block per leaf: the leaf's local expansion (and each
+// W-list multipole, Theorem 1) is turned into the 12 sets of eq. (2.8) in
+// LDS, then every thread evaluates them at EVB beads.
+constexpr int EVB = 2;
+
 template <int NRC>
-__global__ void __launch_bounds__(EV_T) k_eval(int p, const int* leaves, Tree t, List W, const double* sx,
-                                               const double* sy, const double* sz, int64_t n, const double2* M,
-                                               const double2* L, double C1, double C2, double* u) {
+__global__ void __launch_bounds__(EV_T) k_eval(int p, int pw, const int* leaves, Tree t, List W, const double* sx,
+                                               const double* sy, const double* sz, int64_t n,
+                                               const double2* M, const double2* L, const double* __restrict__ rnm,
+                                               double C1, double C2, double* u) {
   constexpr int ND = 4 * NRC;
   const int b = leaves[blockIdx.x];
-  const int T = ncoef(p), Tw = ncoef(p + 2);
+  const int T = ncoef(p), To = ncoef(pw);
   extern __shared__ double2 sm[];
-  double2* D = sm;                 // 12 * Tw
-  double2* G1 = D + 12 * Tw;       // 12 * Tw
-  double2* LC = G1 + 12 * Tw;      // Tw
-  double2* src = LC + Tw;          // 4 * T
+  double2* D = sm;                 // 12 * To
+  double2* G4 = D + 12 * To;       // 3 * To
+  double2* LC = G4 + 3 * To;       // To
+  double2* src = LC + To;          // 4 * T
   const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], h = t.h[b];
   const int j0 = t.begin[b], j1 = t.end[b];
+  const int w0 = W.off[b], w1 = W.off[b + 1];
   for (int r = 0; r < NRC; ++r) {
-    // local expansion of this box
-    __syncthreads();
-    for (int i = threadIdx.x; i < 4 * T; i += EV_T) src[i] = L[(int64_t)b * ND * T + (4 * r) * T + i];
-    __syncthreads();
-    derived_sets(src, p, p, false, 1.0 / h, C1, C2, D, LC, G1);
-    for (int j = j0 + threadIdx.x; j < j1; j += EV_T) {
-      double v[3] = {sx[j] - cx, sy[j] - cy, sz[j] - cz};
-      double uu[3] = {0, 0, 0};
-      apply_sets<false>(D, p, v[0] / h, v[1] / h, v[2] / h, v, C1, uu);
-      for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[k];
-    }
-    // W list: multipoles evaluated directly at this leaf's targets.
-    for (int e = W.off[b]; e < W.off[b + 1]; ++e) {
-      const int C = W.ent[e];
-      const double hc = t.h[C];
-      const double w[3] = {t.cx[C] - cx, t.cy[C] - cy, t.cz[C] - cz};
+    for (int e = w0 - 1; e < w1; ++e) {
+      // e = w0 - 1: this leaf's local expansion; then its W-list multipoles
+      const bool mult = e >= w0;
+      const int C = mult ? W.ent[e] : b;
+      const double hc = t.h[C], ccx = t.cx[C], ccy = t.cy[C], ccz = t.cz[C];
+      const double wx = ccx - cx, wy = ccy - cy, wz = ccz - cz;
       __syncthreads();
       for (int i = threadIdx.x; i < 4 * T; i += EV_T) {
-        int d = i / T, c = i % T;
-        double2 v = M[(int64_t)C * ND * T + (4 * r + d) * T + c];
-        if (d == 3)
+        const int d = i / T, c = i - d * T;
+        const double2* E = mult ? M : L;
+        double2 v = E[(int64_t)C * ND * T + (4 * r + d) * T + c];
+        if (mult && d == 3) {
+          // re-centre the fourth density from the W box on this leaf
+          const double w[3] = {wx, wy, wz};
           for (int k = 0; k < 3; ++k) {
-            double2 q = M[(int64_t)C * ND * T + (4 * r + k) * T + c];
+            const double2 q = M[(int64_t)C * ND * T + (4 * r + k) * T + c];
             v.x += w[k] * q.x;
             v.y += w[k] * q.y;
           }
+        }
         src[i] = v;
       }
       __syncthreads();
-      derived_sets(src, p, p + 2, true, 1.0 / hc, C1, C2, D, LC, G1);
-      for (int j = j0 + threadIdx.x; j < j1; j += EV_T) {
-        double v[3] = {sx[j] - cx, sy[j] - cy, sz[j] - cz};
-        double xc = (sx[j] - t.cx[C]) / hc, yc = (sy[j] - t.cy[C]) / hc, zc = (sz[j] - t.cz[C]) / hc;
-        double uu[3] = {0, 0, 0};
-        apply_sets<true>(D, p + 2, xc, yc, zc, v, C1, uu);
-        for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[k];
+      derived_sets(src, p, mult ? p + 2 : p, mult, hc, C1, C2, D, G4, LC);
+      for (int jb = j0; jb < j1; jb += EV_T * EVB) {
+        double x[EVB], y[EVB], z[EVB], v[EVB][3], uu[EVB][3];
+#pragma unroll
+        for (int q = 0; q < EVB; ++q) {
+          int j = jb + threadIdx.x + q * EV_T;
+          if (j >= j1) j = j0;  // idle slot: a valid bead, result not stored
+          v[q][0] = sx[j] - cx;
+          v[q][1] = sy[j] - cy;
+          v[q][2] = sz[j] - cz;
+          x[q] = (sx[j] - ccx) / hc;
+          y[q] = (sy[j] - ccy) / hc;
+          z[q] = (sz[j] - ccz) / hc;
+          uu[q][0] = uu[q][1] = uu[q][2] = 0.0;
+        }
+        if (mult) apply_sets<true, EVB>(D, p + 2, rnm, x, y, z, v, C1, uu);
+        else apply_sets<false, EVB>(D, p, rnm, x, y, z, v, C1, uu);
+#pragma unroll
+        for (int q = 0; q < EVB; ++q) {
+          const int j = jb + threadIdx.x + q * EV_T;
+          if (j < j1)
+            for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[q][k];
+        }
       }
     }
   }
 }
 
-// ------------------------------------------------------------ launchers ---
-#define DISPATCH_ND(nrc, KERNEL_CALL)               \
-  switch (nrc) {                                    \
+#define DISPATCH_ND(nrc, KERNEL_CALL)                      \
+  switch (nrc) {                                           \
     case 1: { constexpr int ND = 4; KERNEL_CALL; break; }  \
     case 2: { constexpr int ND = 8; KERNEL_CALL; break; }  \
     case 4: { constexpr int ND = 16; KERNEL_CALL; break; } \
-    default: return hipErrorInvalidValue;           \
+    default: return hipErrorInvalidValue;                  \
   }
 
 hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e) {
   const Built* B = l.B;
   if (B->nleaf == 0) return hipSuccess;
-  DISPATCH_ND(nrc, (k_p2e<ND, false><<<B->nleaf, P2E_T, 0, l.s>>>(l.p, B->leaf_ids, B->tree, B->lists[LX], B->sx,
-                                                                   B->sy, B->sz, sF, B->n, e.M)));
+  const size_t shm = sizeof(double2) * P2E_CH * ncoef(l.p);
+  DISPATCH_ND(nrc, (k_p2e<ND, false><<<B->nleaf, P2E_T, shm, l.s>>>(l.p, B->leaf_ids, B->tree, B->lists[LX], B->sx,
+                                                                     B->sy, B->sz, sF, B->n, l.tb->rnm, e.M)));
   return hipGetLastError();
 }
 
 hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
   const Built* B = l.B;
   if (B->lists[LX].len == 0) return hipSuccess;
-  DISPATCH_ND(nrc, (k_p2e<ND, true><<<B->tree.nbox, P2E_T, 0, l.s>>>(l.p, nullptr, B->tree, B->lists[LX], B->sx,
-                                                                      B->sy, B->sz, sF, B->n, e.L)));
+  const size_t shm = sizeof(double2) * P2E_CH * ncoef(l.p);
+  DISPATCH_ND(nrc, (k_p2e<ND, true><<<B->tree.nbox, P2E_T, shm, l.s>>>(l.p, nullptr, B->tree, B->lists[LX], B->sx,
+                                                                        B->sy, B->sz, sF, B->n, l.tb->rnm, e.L)));
   return hipGetLastError();
 }
 
 hipError_t run_m2m(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
+  const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
   for (int lev = B->depth - 1; lev >= 0; --lev) {
-    int ls = B->level_start[lev], le = B->level_start[lev + 1];
-    size_t shm = sizeof(double2) * (1 + 4 * nrc) * (l.p + 1) * (l.p + 1);
-    DISPATCH_ND(nrc, (k_m2m<ND><<<le - ls, TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
+    const int ls = B->level_start[lev], le = B->level_start[lev + 1];
+    DISPATCH_ND(nrc, (k_m2m<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -886,10 +922,10 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e) {
 
 hipError_t run_l2l(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
+  const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
   for (int lev = 2; lev <= B->depth; ++lev) {
-    int ls = B->level_start[lev], le = B->level_start[lev + 1];
-    size_t shm = sizeof(double2) * (1 + 4 * nrc) * (l.p + 1) * (l.p + 1);
-    DISPATCH_ND(nrc, (k_l2l<ND><<<le - ls, TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
+    const int ls = B->level_start[lev], le = B->level_start[lev + 1];
+    DISPATCH_ND(nrc, (k_l2l<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -900,14 +936,21 @@ hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u) {
   const Built* B = l.B;
   if (B->nleaf == 0) return hipSuccess;
   const int p = l.p;
+  const int pw = B->lists[LW].len > 0 ? p + 2 : p;
   const double C1 = 1.0 / (8.0 * PI * l.eta), C2 = l.a * l.a / (12.0 * PI * l.eta);
-  size_t shm = sizeof(double2) * (25 * ncoef(p + 2) + 4 * ncoef(p));
+  const size_t shm = sizeof(double2) * (16 * ncoef(pw) + 4 * ncoef(p));
+#define EVAL_CASE(NR)                                                                                          \
+  case NR:                                                                                                     \
+    k_eval<NR><<<B->nleaf, EV_T, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, \
+                                              B->n, e.M, e.L, l.tb->rnm, C1, C2, u);                          \
+    break;
   switch (nrc) {
-    case 1: k_eval<1><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
-    case 2: k_eval<2><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
-    case 4: k_eval<4><<<B->nleaf, EV_T, shm, l.s>>>(p, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, B->n, e.M, e.L, C1, C2, u); break;
+    EVAL_CASE(1)
+    EVAL_CASE(2)
+    EVAL_CASE(4)
     default: return hipErrorInvalidValue;
   }
+#undef EVAL_CASE
   return hipGetLastError();
 }
 
