@@ -189,6 +189,53 @@ def run(args):
     return 0
 
 
+PMC_KERNELS = {  # rocprofv3 kernel-name prefix -> (phase, precision form, source file)
+    "rpy::k_p2p<1, true>": ("p2p", "mixed", "nearfield.hip"),
+    "rpy::k_p2p<1, false>": ("p2p", "fp64", "nearfield.hip"),
+    "rpy::k_m2l_rot<4, float>": ("m2l", "mixed", "m2l_rot.hip"),
+    "rpy::k_m2l_rot<4, double>": ("m2l", "fp64", "m2l_rot.hip"),
+}
+
+
+def pmc_summary(args):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB
+    per dispatch), each scaled by what the same counter reads for a plain
+    device copy of known size (--copy-probe run); writes
+    profiles/pmc_traffic.json keyed by phase:workload:form with the kernel
+    source hash, so stale figures are not reported."""
+    import csv
+    import re
+
+    def load(d):
+        out = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            name = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "").strip()
+            out.setdefault((name, r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+        return out
+
+    fdir, wdir, cfdir, cwdir = args.pmc_summary
+    f, w, cf, cw = load(fdir), load(wdir), load(cfdir), load(cwdir)
+    copy_bytes = args.copy_probe * (1 << 20)
+    mean = lambda v: sum(v) / len(v)
+    kf = copy_bytes / (1024.0 * mean(cf[("__amd_rocclr_copyBuffer", "FETCH_SIZE")]))
+    kw = copy_bytes / (1024.0 * mean(cw[("__amd_rocclr_copyBuffer", "WRITE_SIZE")]))
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    for name, (phase, form, src) in PMC_KERNELS.items():
+        if (name, "FETCH_SIZE") not in f or (name, "WRITE_SIZE") not in w:
+            continue
+        fb = mean(f[(name, "FETCH_SIZE")]) * 1024.0 * kf
+        wb = mean(w[(name, "WRITE_SIZE")]) * 1024.0 * kw
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1711_02976_amd", "csrc", src), "rb").read())
+        rec[f"{phase}:{args.workload}:{form}"] = {
+            "kernel": name, "fetch_bytes": round(fb), "write_bytes": round(wb),
+            "bytes_per_launch": round(fb + wb), "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
+            "source_sha": sha.hexdigest()[:16]}
+    json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
+    print(json.dumps(rec, indent=1, sort_keys=True))
+    return 0
+
+
 def copy_probe(mib):
     """A plain device copy of known size, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -215,10 +262,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="turn four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a benchmark run "
+                         "and of a --copy-probe run of the size given by --copy-probe) into "
+                         "profiles/pmc_traffic.json, then exit")
     ap.add_argument("--m2l", default="auto", choices=["auto", "dense", "rotation"],
                     help="multipole-to-local operator (auto = the library's choice per precision)")
     args = ap.parse_args()
     args.precisions = [p.strip() for p in args.precisions.split(",") if p.strip()]
+    if args.pmc_summary:
+        return pmc_summary(args)
     if args.copy_probe > 0:
         return copy_probe(args.copy_probe)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
