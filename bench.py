@@ -32,6 +32,10 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {"cube-2k": 1, "cube-1M": 2, "blobs-4M": 3, "batched-64": 4, "cube-15M": 5}
 
 
+def progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
 def algorithmic_counts(P, p, nrc):
     """Algorithmic flops per launch of the P2P and M2L kernels, from the
     plan's lists (host arithmetic on exported integers only)."""
@@ -86,6 +90,7 @@ def run(args):
     import workloads as W
 
     w = W.config(WORKLOADS[args.workload], nsample=args.cpu_targets)
+    progress(f"{w.name}: {w.n} beads, {w.nrhs} rhs generated")
     dev = torch.device("cuda:0")
     pos = torch.as_tensor(w.pos, device=dev)
     F = torch.as_tensor(w.forces, device=dev)
@@ -98,8 +103,12 @@ def run(args):
         P = R.Plan(pos, w.a, w.eta, w.eps, precision=prec, leaf_size=args.leaf_size, order=args.order,
                    max_depth=w.max_depth, counts=counts, m2l=args.m2l)
         st = P.stats()
+        progress(f"{w.name} {prec}: plan {st['plan_ms']:.1f} ms, p={st['order']} s={st['leaf_size']} "
+                 f"boxes={st['nbox']} depth={st['depth']}")
         for _ in range(args.warmup):
             P.matvec(F, out=U)
+            torch.cuda.synchronize()
+            progress(f"{w.name} {prec}: warm-up matvec done")
         torch.cuda.synchronize()
         P.set_timing(True)
         torch.cuda.synchronize()
@@ -110,6 +119,7 @@ def run(args):
         t1 = time.perf_counter()
         tm = P.timings()
         ms = (t1 - t0) * 1e3 / args.steps
+        progress(f"{w.name} {prec}: {args.steps} timed matvecs, {ms:.2f} ms each")
         nrc = 4 if w.nrhs >= 4 else (2 if w.nrhs >= 2 else 1)
         alg = algorithmic_counts(P, st["order"], nrc)
         results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "alg": alg,

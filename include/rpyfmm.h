@@ -54,7 +54,7 @@ typedef struct {
   int32_t precision;     /* rpy_precision */
   int32_t leaf_size;     /* refinement limit: max beads per leaf (Sec. 4.2
                             "threshold"); 0 = chosen by the library: trees
-                            are built for limits 16 * 1.5^k and the one with
+                            are built for limits 64 * 1.5^k and the one with
                             the lowest modelled matvec time is kept */
   int32_t order;         /* expansion order p; 0 = chosen from eps */
   int32_t max_depth;     /* deepest tree level, 1..21; 0 = 14 */

@@ -745,8 +745,13 @@ static void box_center(const orc_tree* t, int64_t b, double c[3]) {
  * ancestors, carried down by L2L) and the multipoles of its W list, then
  * assembles eq. (2.8); U-list beads are summed directly with the exact RPY
  * block, and O-list pairs with r < 2a receive (M_overlap - M_far) F.
+ * The paper leaves the evaluation of W lists to the adaptive FMM it builds
+ * on; here a W box with at most (p+1)(p+2) beads is summed directly with
+ * the far formula (cheaper than its multipole at that size, and exact for
+ * what the far field represents), the others through Theorem 1.
  * pos [n][3], F [nrhs][n][3], out [nrhs][n][3], all in caller order.
- * Returns 0, or -1 for invalid arguments. */
+ * Returns 0, or -1 for invalid arguments.
+ */
 int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, double eta, int p,
             int leaf_size, int max_depth, double* out, int nthreads) {
   if (n < 0 || p < 0 || p > 40 || nrhs < 1 || a <= 0 || eta <= 0 || leaf_size < 1) return -1;
@@ -869,8 +874,22 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
         vgh_t f[4];
         memset(f, 0, sizeof f);
         for (int s = 0; s < 4; ++s) l2t(&o, L + ((size_t)b * 4 + s) * T, v, &f[s]);
+        double wd[3] = {0, 0, 0};
         for (int64_t e = t->off[2][b]; e < t->off[2][b + 1]; ++e) {
           int64_t C = t->ent[2][e];
+          if (t->end[C] - t->begin[C] <= 2 * T) {
+            /* few beads: the far formula summed directly (what the far field
+               stands for); the O list corrects pairs closer than 2a */
+            for (int64_t j = t->begin[C]; j < t->end[C]; ++j) {
+              double d[3] = {x[0] - spos[3 * j], x[1] - spos[3 * j + 1], x[2] - spos[3 * j + 2]};
+              double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2], rr = sqrt(r2);
+              double cf = 1.0 / (8.0 * ORC_PI * eta * rr);
+              double Af = cf * (1.0 + 2.0 * a * a / (3.0 * r2)), Bf = cf * (1.0 - 2.0 * a * a / r2) / r2;
+              double dF = d[0] * sF[3 * j] + d[1] * sF[3 * j + 1] + d[2] * sF[3 * j + 2];
+              for (int k = 0; k < 3; ++k) wd[k] += Af * sF[3 * j + k] + Bf * dF * d[k];
+            }
+            continue;
+          }
           const double* cc = ctr + 3 * C;
           memcpy(Mw, M + (size_t)C * 4 * T, sizeof(cplx) * 4 * T);
           recentre(T, Mw, cc, cb);
@@ -881,7 +900,7 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
         for (int k = 0; k < 3; ++k) {
           double xs = 0, gLc = 0;
           for (int s = 0; s < 3; ++s) { xs += v[s] * f[s].g[k]; gLc += f[s].h[k][s]; }
-          u[k] = C1 * f[k].v - C1 * xs + C1 * f[3].g[k] - C2 * gLc;
+          u[k] = C1 * f[k].v - C1 * xs + C1 * f[3].g[k] - C2 * gLc + wd[k];
         }
         for (int64_t e = t->off[0][b]; e < t->off[0][b + 1]; ++e) {
           int64_t C = t->ent[0][e];

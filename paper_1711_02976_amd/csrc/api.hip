@@ -28,8 +28,9 @@ rpy_status fail(rpy_status s, const std::string& msg) {
 // refinement limits 80, 100 and 120).  Level-uniform trees (no W/X lists)
 // converge faster than adaptive ones, whose W and X interactions have a
 // worse separation ratio: measured on a uniform cube, p = 7 gives 2.2e-4 and
-// p = 16 gives 4.0e-7; on Gaussian blobs p = 12, 16, 20 give 3.2e-5, 2.6e-6
-// and 2.8e-7.
+// p = 16 gives 4.0e-7; on 20k beads in Gaussian blobs p = 12, 16, 20 give
+// 3.2e-5, 2.6e-6 and 2.8e-7, and on 4M beads in 2,000 blobs (depth 11-13)
+// p = 20 gives 1.0e-6 and p = 21 gives 6.8e-7.
 int order_for_eps(double eps, bool adaptive) {
   static const double tol[] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7,
                                3e-8, 1e-8, 1e-9};
@@ -40,14 +41,14 @@ int order_for_eps(double eps, bool adaptive) {
       p = ord[i];
       break;
     }
-  if (adaptive) p += (p - 4 + 1) / 3;
+  if (adaptive) p += (p - 3) / 3 + 1;
   return std::min(p, rpy::MAX_ORDER);
 }
 
 // ---- leaf-size choice ------------------------------------------------------
 // Modelled time of one matvec (one right-hand side) on a built tree, from its
 // interaction counts and per-unit kernel times measured on MI355X for this
-// library at p = 16 (1M-bead cube): P2P per ordered bead pair, M2L per
+// library at p = 16 (1M-bead cube): P2P (and overlap-correction) per ordered bead pair, M2L per
 // (V pair, density), per-box upward/downward work per density, and the
 // adaptive W/X terms per (bead, box).  Also returns the range of refinement
 // limits that produce this same tree.
@@ -70,13 +71,14 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const rpy::List& U = B.lists[rpy::LU];
   const rpy::List& W = B.lists[rpy::LW];
   const rpy::List& X = B.lists[rpy::LX];
-  std::vector<int> uo(nbox + 1), ue(U.len), wo(nbox + 1), xo(nbox + 1), xe(X.len);
+  const rpy::List& O = B.lists[rpy::LO];
+  std::vector<int> uo(nbox + 1), ue(U.len), wo(nbox + 1), xo(nbox + 1), xe(X.len), oo(nbox + 1), oe(O.len);
   if (!get(uo, U.off, nbox + 1) || !get(ue, U.ent, U.len) || !get(wo, W.off, nbox + 1) || !get(xo, X.off, nbox + 1) ||
-      !get(xe, X.ent, X.len))
+      !get(xe, X.ent, X.len) || !get(oo, O.off, nbox + 1) || !get(oe, O.ent, O.len))
     return -4;
   const bool adaptive = W.len > 0 || X.len > 0;
   const int p = order ? order : order_for_eps(eps, adaptive);
-  double pairs = 0, wterm = 0, xterm = 0;
+  double pairs = 0, wterm = 0, xterm = 0, opairs = 0;
   int lo = 0, hi = 0x7fffffff;
   for (int b = 0; b < nbox; ++b) {
     const int nb = end[b] - beg[b];
@@ -86,6 +88,9 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
       for (int k = uo[b]; k < uo[b + 1]; ++k) src += end[ue[k]] - beg[ue[k]];
       pairs += (double)nb * src;
       wterm += (double)nb * (wo[b + 1] - wo[b]);
+      double osrc = 0;
+      for (int k = oo[b]; k < oo[b + 1]; ++k) osrc += end[oe[k]] - beg[oe[k]];
+      opairs += (double)nb * osrc;
     } else {
       hi = std::min(hi, nb);
     }
@@ -97,7 +102,9 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const double c_v = (mixed ? 2210.0 : 2650.0) * S / S16;  // ns per (V pair, density)
   const double c_box = 45.0 * T / T16;                // ns per (box, density)
   const double c_wx = 3.0 * T / T16;                  // ns per (bead, W or X box, density)
-  out->ns = pairs * c_pair + 4.0 * (B.lists[rpy::LV].len * c_v + nbox * c_box + (wterm + xterm) * c_wx);
+  // bead pairs of O-list leaves: the overlap correction visits them at about
+  // the P2P rate (an upper bound: tiles farther than 2a are skipped)
+  out->ns = (pairs + opairs) * c_pair + 4.0 * (B.lists[rpy::LV].len * c_v + nbox * c_box + (wterm + xterm) * c_wx);
   out->same_lo = lo;
   out->same_hi = hi;
   out->adaptive = adaptive;
@@ -268,16 +275,22 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     rc = rpy::build_tree(ba, &P->B, &err);
   } else {
     // Refinement limit chosen by the cost model over a ladder of limits
-    // (16 * 1.5^k); limits that provably give the tree already built are
+    // (64 * 1.5^k); limits that provably give the tree already built are
     // skipped, and the search stops once the modelled time has grown well
     // past the best (the model is unimodal in the limit in practice).
+    // Trial trees are built without the O list: the overlapping bead pairs
+    // are fixed by the geometry, not by the tree, and dense clusters with
+    // small leaves make that list very long.  The chosen tree is rebuilt
+    // with it when some leaf is smaller than 2a.
     int64_t nmax = 1;
     for (int s = 0; s < nsys; ++s) nmax = std::max<int64_t>(nmax, counts[s]);
-    double best = 0, sl = 16;
+    double best = 0, sl = 64;
+    bool need_o = false;
     for (;;) {
       const int cand = (int)sl;
       rpy::Built Bc;
       rpy::BuildArgs ba{n, nsys, sb.data(), positions, cand, P->max_depth, a, P->stream};
+      ba.skip_o = true;
       rc = rpy::build_tree(ba, &Bc, &err);
       TreeCost tc;
       if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, &tc);
@@ -291,6 +304,9 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
         P->B = Bc;
         P->leaf_size = cand;
         best = tc.ns;
+        need_o = false;
+        for (int s = 0; s < nsys; ++s)
+          if (ldexp(P->B.side[s], -P->B.depth) < 2.0 * a) need_o = true;
       } else {
         rpy::free_built(&Bc);
         if (tc.ns > 1.5 * best) break;
@@ -298,6 +314,11 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       if (cand >= nmax || tc.same_hi > nmax) break;  // one leaf per system from here on
       do sl *= 1.5;
       while ((int64_t)sl < tc.same_hi);
+    }
+    if (rc == 0 && need_o) {
+      rpy::free_built(&P->B);
+      rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
+      rc = rpy::build_tree(ba, &P->B, &err);
     }
   }
   if (rc == 0 && P->p == 0)
@@ -343,10 +364,11 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
     const rpy::Built& B = P->B;
     const int nlev = B.depth;
-    const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0;
+    const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
     hipError_t he = timed(P, RPY_PH_PERMUTE, 1, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
     if (he == hipSuccess) he = timed(P, RPY_PH_P2P, 1, [&] { return rpy::run_p2p(l, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_overlap(l, P->tiles, c, P->sF, P->u); });
+    if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_overlap(l, P->tiles, c, P->sF, P->u, mixed); });
+    if (he == hipSuccess && haveW) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_wdirect(l, P->tiles, c, P->sF, P->u, mixed); });
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, [&] { return rpy::run_p2m(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, [&] { return rpy::run_m2m(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] {
@@ -380,7 +402,7 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   out->nbox = P->B.tree.nbox;
   out->nleaf = P->B.nleaf;
   for (int L = 0; L < 5; ++L) out->list_len[L] = P->B.lists[L].len;
-  out->device_bytes = P->B.bytes + P->tb.bytes + P->ws_bytes + (int64_t)sizeof(int4) * P->tiles.n;
+  out->device_bytes = P->B.bytes + P->tb.bytes + P->ws_bytes + (int64_t)(sizeof(int4) + 6 * sizeof(double)) * P->tiles.n;
   out->plan_ms = P->plan_ms;
   return RPY_OK;
 }
@@ -454,6 +476,7 @@ void rpy_plan_free(rpy_plan_t* P) {
   free_ws(P);
   rpy::free_tables(&P->tb);
   if (P->tiles.t) (void)hipFree(P->tiles.t);
+  if (P->tiles.box) (void)hipFree(P->tiles.box);
   rpy::free_built(&P->B);
   delete P;
 }

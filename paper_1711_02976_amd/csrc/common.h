@@ -73,6 +73,7 @@ struct BuildArgs {
   int max_depth;
   double a;
   hipStream_t stream;
+  bool skip_o = false;          // leave the O list empty (trial trees of the leaf-size search)
 };
 
 // Everything rpy_plan builds on the device.  Owned buffers are released by

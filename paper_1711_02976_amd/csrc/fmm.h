@@ -75,9 +75,17 @@ hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u);
 struct Tiles {
   int n;
   int4* t;
+  double* box;  // [n][6] bounding box of each tile's beads (lo xyz, hi xyz)
 };
 int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err);
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
+// W-list boxes of at most wdirect_max(p) = 2 (p+1)(p+2)/2 beads are summed
+// directly (far formula) by run_wdirect; the target evaluation uses the
+// multipoles of the others only.  Per target and right-hand side the
+// multipole route costs about 12 sets x (p+3)(p+4)/2 coefficients, the
+// direct route a few tens of operations per source bead.
+__host__ __device__ constexpr int wdirect_max(int p) { return (p + 1) * (p + 2); }
+hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
 
 }  // namespace rpy

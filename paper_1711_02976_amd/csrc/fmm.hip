@@ -667,7 +667,6 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, cons
 //   G_ik = d_i L_k                                   (i, k in x, y, z)
 // so that eq. (2.8) at a target x reads u_i = E_i(x) - C1 sum_k (x-c)_k G_ik(x);
 // each target then sums the twelve sets against its own harmonics.
-constexpr int EV_T = 128;
 
 // Derivative of a real-symmetric set in coefficient space.  Local (regular)
 // sets: d_z C -> C_{n+1}^m, d_x -> (C_{n+1}^{m-1} - C_{n+1}^{m+1})/2,
@@ -697,7 +696,7 @@ __device__ void derived_sets(const double2* src, int nin, int nout, bool mult, d
                              double2* D, double2* G4, double2* LC) {
   const int To = ncoef(nout);
   const double ih = 1.0 / h, ih2 = ih * ih, ih3 = ih2 * ih;
-  for (int w = threadIdx.x; w < 12 * To; w += EV_T) {
+  for (int w = threadIdx.x; w < 12 * To; w += blockDim.x) {
     const int k = w / (3 * To), rem = w - k * 3 * To, i = rem / To, c = rem - i * To;
     int n = 0;
     while (tri(n + 1) <= c) ++n;
@@ -708,12 +707,12 @@ __device__ void derived_sets(const double2* src, int nin, int nout, bool mult, d
   }
   __syncthreads();
   const double h2 = h * h;
-  for (int c = threadIdx.x; c < To; c += EV_T) {
+  for (int c = threadIdx.x; c < To; c += blockDim.x) {
     const double2 a = D[3 * To + c], b = D[7 * To + c], d = D[11 * To + c];
     LC[c] = make_double2(h2 * (a.x + b.x + d.x), h2 * (a.y + b.y + d.y));
   }
   __syncthreads();
-  for (int w = threadIdx.x; w < 3 * To; w += EV_T) {
+  for (int w = threadIdx.x; w < 3 * To; w += blockDim.x) {
     const int i = w / To, c = w - i * To;
     int n = 0;
     while (tri(n + 1) <= c) ++n;
@@ -805,8 +804,8 @@ __device__ inline void apply_sets(const double2* D, int nmax, const double* __re
 // LDS, then every thread evaluates them at EVB beads.
 constexpr int EVB = 2;
 
-template <int NRC>
-__global__ void __launch_bounds__(EV_T) k_eval(int p, int pw, const int* leaves, Tree t, List W, const double* sx,
+template <int NRC, int NT>
+__global__ void __launch_bounds__(NT) k_eval(int p, int pw, const int* leaves, Tree t, List W, const double* sx,
                                                const double* sy, const double* sz, int64_t n,
                                                const double2* M, const double2* L, const double* __restrict__ rnm,
                                                double C1, double C2, double* u) {
@@ -824,12 +823,14 @@ __global__ void __launch_bounds__(EV_T) k_eval(int p, int pw, const int* leaves,
   for (int r = 0; r < NRC; ++r) {
     for (int e = w0 - 1; e < w1; ++e) {
       // e = w0 - 1: this leaf's local expansion; then its W-list multipoles
+      // (boxes with few beads are summed directly by the near-field pass)
       const bool mult = e >= w0;
       const int C = mult ? W.ent[e] : b;
+      if (mult && t.end[C] - t.begin[C] <= wdirect_max(p)) continue;
       const double hc = t.h[C], ccx = t.cx[C], ccy = t.cy[C], ccz = t.cz[C];
       const double wx = ccx - cx, wy = ccy - cy, wz = ccz - cz;
       __syncthreads();
-      for (int i = threadIdx.x; i < 4 * T; i += EV_T) {
+      for (int i = threadIdx.x; i < 4 * T; i += NT) {
         const int d = i / T, c = i - d * T;
         const double2* E = mult ? M : L;
         double2 v = E[(int64_t)C * ND * T + (4 * r + d) * T + c];
@@ -846,11 +847,11 @@ __global__ void __launch_bounds__(EV_T) k_eval(int p, int pw, const int* leaves,
       }
       __syncthreads();
       derived_sets(src, p, mult ? p + 2 : p, mult, hc, C1, C2, D, G4, LC);
-      for (int jb = j0; jb < j1; jb += EV_T * EVB) {
+      for (int jb = j0; jb < j1; jb += NT * EVB) {
         double x[EVB], y[EVB], z[EVB], v[EVB][3], uu[EVB][3];
 #pragma unroll
         for (int q = 0; q < EVB; ++q) {
-          int j = jb + threadIdx.x + q * EV_T;
+          int j = jb + threadIdx.x + q * NT;
           if (j >= j1) j = j0;  // idle slot: a valid bead, result not stored
           v[q][0] = sx[j] - cx;
           v[q][1] = sy[j] - cy;
@@ -864,7 +865,7 @@ __global__ void __launch_bounds__(EV_T) k_eval(int p, int pw, const int* leaves,
         else apply_sets<false, EVB>(D, p, rnm, x, y, z, v, C1, uu);
 #pragma unroll
         for (int q = 0; q < EVB; ++q) {
-          const int j = jb + threadIdx.x + q * EV_T;
+          const int j = jb + threadIdx.x + q * NT;
           if (j < j1)
             for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[q][k];
         }
@@ -939,10 +940,16 @@ hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u) {
   const int pw = B->lists[LW].len > 0 ? p + 2 : p;
   const double C1 = 1.0 / (8.0 * PI * l.eta), C2 = l.a * l.a / (12.0 * PI * l.eta);
   const size_t shm = sizeof(double2) * (16 * ncoef(pw) + 4 * ncoef(p));
-#define EVAL_CASE(NR)                                                                                          \
-  case NR:                                                                                                     \
-    k_eval<NR><<<B->nleaf, EV_T, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy, B->sz, \
-                                              B->n, e.M, e.L, l.tb->rnm, C1, C2, u);                          \
+  // 128 threads per leaf; 256 when W-list multipoles (degree p + 2 sets, one
+  // block per CU) are evaluated
+#define EVAL_CASE(NR)                                                                                            \
+  case NR:                                                                                                       \
+    if (pw > p)                                                                                                  \
+      k_eval<NR, 256><<<B->nleaf, 256, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy,    \
+                                                    B->sz, B->n, e.M, e.L, l.tb->rnm, C1, C2, u);              \
+    else                                                                                                         \
+      k_eval<NR, 128><<<B->nleaf, 128, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy,    \
+                                                    B->sz, B->n, e.M, e.L, l.tb->rnm, C1, C2, u);              \
     break;
   switch (nrc) {
     EVAL_CASE(1)

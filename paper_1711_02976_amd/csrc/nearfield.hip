@@ -10,6 +10,7 @@
 // (positions and forces, SoA) and read back as wave-wide broadcasts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "fmm.h"
@@ -38,9 +39,30 @@ __global__ void k_tile_fill(const int* leaves, int nleaf, Tree t, int tile, cons
   for (int s = t.begin[b]; s < t.end[b]; s += tile) out[o++] = make_int4(b, s, min(tile, t.end[b] - s), 0);
 }
 
+// Bounding box of each tile's beads: lo xyz, hi xyz.
+__global__ void k_tile_box(const int4* tiles, int nt, const double* sx, const double* sy, const double* sz,
+                           double* box) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const int4 tl = tiles[i];
+  double lo[3] = {sx[tl.y], sy[tl.y], sz[tl.y]}, hi[3] = {lo[0], lo[1], lo[2]};
+  for (int j = tl.y + 1; j < tl.y + tl.z; ++j) {
+    const double v[3] = {sx[j], sy[j], sz[j]};
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fmin(lo[k], v[k]);
+      hi[k] = fmax(hi[k], v[k]);
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    box[6 * (int64_t)i + k] = lo[k];
+    box[6 * (int64_t)i + 3 + k] = hi[k];
+  }
+}
+
 int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err) {
   out->n = 0;
   out->t = nullptr;
+  out->box = nullptr;
   if (B->nleaf == 0) return 0;
   int *cnt = nullptr, *off = nullptr, *tmp = nullptr;
   RPY_HIP(hipMalloc(&cnt, sizeof(int) * B->nleaf));
@@ -55,6 +77,9 @@ int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err) 
   out->n = last[0] + last[1];
   RPY_HIP(hipMalloc(&out->t, sizeof(int4) * out->n));
   k_tile_fill<<<nblk(B->nleaf, 256), 256, 0, s>>>(B->leaf_ids, B->nleaf, B->tree, tile, off, out->t);
+  RPY_HIP(hipGetLastError());
+  RPY_HIP(hipMalloc(&out->box, sizeof(double) * 6 * std::max(out->n, 1)));
+  if (out->n > 0) k_tile_box<<<nblk(out->n, 256), 256, 0, s>>>(out->t, out->n, B->sx, B->sy, B->sz, out->box);
   RPY_HIP(hipGetLastError());
   RPY_HIP(hipStreamSynchronize(s));
   (void)hipFree(cnt); (void)hipFree(off); (void)hipFree(tmp);
@@ -72,19 +97,6 @@ struct RpyConst {
   double k9;      // 9/(32a)
   double c0k3;    // c0 * 3/(32a)
 };
-
-// Far (r >= 2a) block: A = c1/r (1 + 2a^2/(3r^2)), B = c1/r^3 (1 - 2a^2/r^2).
-__device__ inline void rpy_far(double rinv, const RpyConst& k, double& A, double& B) {
-  const double ri2 = rinv * rinv, ri3 = ri2 * rinv;
-  A = fma(k.c1a3, ri3, k.c1 * rinv);
-  B = fma(-k.c1a2 * ri2, ri3, k.c1 * ri3);
-}
-
-// Overlap (r < 2a) block: A = c0 (1 - 9r/(32a)), B = c0 3/(32a) / r.
-__device__ inline void rpy_overlap(double r2, double rinv, const RpyConst& k, double& A, double& B) {
-  A = k.c0 * fma(-k.k9, r2 * rinv, 1.0);
-  B = k.c0k3 * rinv;
-}
 
 // Pair coefficients of the P2P sum with the far prefactor c1 = 1/(8 pi eta)
 // taken out of the sum (applied once per target):
@@ -194,55 +206,161 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] = c1 * acc[r][c];
 }
 
-// ------------------------------------------------------- overlap (O) -----
-template <int NRC>
-__global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, Tree t, List O, const double* sx,
+// ---------------------------------------------------- W list, direct ----
+// W-list boxes with few beads: their multipole evaluation at this leaf's
+// targets (Theorem 1, order p + 2) costs more than summing their beads, so
+// they are summed directly with the far formula, which is what the far field
+// stands for (pairs closer than 2a are then corrected by the O list as
+// before).  Boxes with more than wmax beads keep the multipole route.
+template <int NRC, bool MIXED>
+__global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, List W, int wmax, const double* sx,
                                                    const double* sy, const double* sz, const double* sF, int64_t n,
-                                                   RpyConst k, double* u) {
+                                                   PairK<typename std::conditional<MIXED, float, double>::type> k,
+                                                   double c1, double* u) {
+  using R = typename std::conditional<MIXED, float, double>::type;
   __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
-  __shared__ double fs[NRC * 3][P2P_T];
+  __shared__ R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
-  if (O.off[b] == O.off[b + 1]) return;
+  const int e0 = __builtin_amdgcn_readfirstlane(W.off[b]), e1 = __builtin_amdgcn_readfirstlane(W.off[b + 1]);
+  if (e0 == e1) return;
   const bool valid = (int)threadIdx.x < tl.z;
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double xi = sx[i], yi = sy[i], zi = sz[i];
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
-  for (int e = O.off[b]; e < O.off[b + 1]; ++e) {
-    const int C = O.ent[e];
-    const int j1 = t.end[C];
-    for (int jc = t.begin[C]; jc < j1; jc += P2P_T) {
+  bool any = false;
+  for (int e = e0; e < e1; ++e) {
+    const int C = __builtin_amdgcn_readfirstlane(W.ent[e]);
+    const int j0 = __builtin_amdgcn_readfirstlane(t.begin[C]), j1 = __builtin_amdgcn_readfirstlane(t.end[C]);
+    if (j1 - j0 > wmax) continue;
+    any = true;
+    for (int jc = j0; jc < j1; jc += P2P_T) {
       const int ns = min(P2P_T, j1 - jc);
+      const int ns4 = (ns + 3) & ~3;
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
         xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
-        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = sF[(int64_t)q * n + j];
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
+      } else if ((int)threadIdx.x < ns4) {
+        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
-      for (int s = 0; s < ns; ++s) {
-        const double dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        if (!(r2 < k.four_a2) || r2 < 1e-30) continue;
-        const double rinv = 1.0 / sqrt(r2);
-        double Af, Bf, Ao, Bo;
-        rpy_far(rinv, k, Af, Bf);
-        rpy_overlap(r2, rinv, k, Ao, Bo);
-        const double A = Ao - Af, B = Bo - Bf;
+      R ar[NRC][3];
+      for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
+      for (int s0 = 0; s0 < ns4; s0 += 4)
+#pragma unroll
+      for (int s = s0; s < s0 + 4; ++s) {
+        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const R rinv = rinv_of(max(r2, k.r2min));
+        const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
+        const R A = fma(k.a3, ri3, rinv), B = ri3 * fma(-k.a2, ri2, (R)1);
+#pragma unroll
         for (int r = 0; r < NRC; ++r) {
-          const double fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
-          const double sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
-          acc[r][0] = fma(A, fx, fma(sdf, dx, acc[r][0]));
-          acc[r][1] = fma(A, fy, fma(sdf, dy, acc[r][1]));
-          acc[r][2] = fma(A, fz, fma(sdf, dz, acc[r][2]));
+          const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
+          const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
+          ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
+          ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
+          ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
         }
       }
+      for (int r = 0; r < NRC; ++r)
+        for (int c = 0; c < 3; ++c) acc[r][c] += (double)ar[r][c];
+    }
+  }
+  if (valid && any)
+    for (int r = 0; r < NRC; ++r)
+      for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] += c1 * acc[r][c];
+}
+
+// ------------------------------------------------------- overlap (O) -----
+// Pairs closer than 2a whose leaves are not adjacent: the far field treated
+// them with the r >= 2a formula, so (M_overlap - M_far) F is added.  Same
+// tiling as the P2P (padded, unrolled by 4); leaves of the O list are
+// separated, so r > 0 and the far values are finite.  Pairs at r >= 2a get a
+// zero coefficient (masked, no branch).  With the prefactor taken out:
+//   A' = oc (1 - 9r/(32a)) - 1/r - (2a^2/3)/r^3,  B' = ob/r - (1 - 2a^2/r^2)/r^3.
+template <int NRC, bool MIXED>
+__global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const double* tbox, Tree t, List O,
+                                                   double four_a2, const double* sx,
+                                                   const double* sy, const double* sz, const double* sF, int64_t n,
+                                                   PairK<typename std::conditional<MIXED, float, double>::type> k,
+                                                   double c1, double* u) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
+  __shared__ R fs[NRC * 3][P2P_T];
+  const int4 tl = tiles[blockIdx.x];
+  const int b = tl.x;
+  const int e0 = __builtin_amdgcn_readfirstlane(O.off[b]), e1 = __builtin_amdgcn_readfirstlane(O.off[b + 1]);
+  if (e0 == e1) return;
+  const bool valid = (int)threadIdx.x < tl.z;
+  const int i = tl.y + (valid ? threadIdx.x : 0);
+  const double xi = sx[i], yi = sy[i], zi = sz[i];
+  double acc[NRC][3];
+  for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
+  double blo[3], bhi[3];
+  for (int q = 0; q < 3; ++q) {
+    blo[q] = tbox[6 * (int64_t)blockIdx.x + q];
+    bhi[q] = tbox[6 * (int64_t)blockIdx.x + 3 + q];
+  }
+  for (int e = e0; e < e1; ++e) {
+    const int C = __builtin_amdgcn_readfirstlane(O.ent[e]);
+    // skip source leaves whose cube is 2a or more away from this tile's beads
+    {
+      const double hc = 0.5 * t.h[C], cc[3] = {t.cx[C], t.cy[C], t.cz[C]};
+      double g2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double g = fmax(0.0, fmax(cc[q] - hc - bhi[q], blo[q] - cc[q] - hc));
+        g2 += g * g;
+      }
+      if (!(g2 < four_a2)) continue;
+    }
+    const int j1 = __builtin_amdgcn_readfirstlane(t.end[C]);
+    for (int jc = __builtin_amdgcn_readfirstlane(t.begin[C]); jc < j1; jc += P2P_T) {
+      const int ns = min(P2P_T, j1 - jc);
+      const int ns4 = (ns + 3) & ~3;
+      __syncthreads();
+      if ((int)threadIdx.x < ns) {
+        int j = jc + threadIdx.x;
+        xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
+      } else if ((int)threadIdx.x < ns4) {
+        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
+      }
+      __syncthreads();
+      R ar[NRC][3];
+      for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
+      for (int s0 = 0; s0 < ns4; s0 += 4)
+#pragma unroll
+      for (int s = s0; s < s0 + 4; ++s) {
+        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const R rinv = rinv_of(max(r2, k.r2min));
+        const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
+        const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
+        const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
+        const bool ov = r2 < k.four_a2;
+        const R A = ov ? Ao - Af : (R)0, B = ov ? Bo - Bf : (R)0;
+#pragma unroll
+        for (int r = 0; r < NRC; ++r) {
+          const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
+          const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
+          ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
+          ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
+          ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
+        }
+      }
+      for (int r = 0; r < NRC; ++r)
+        for (int c = 0; c < 3; ++c) acc[r][c] += (double)ar[r][c];
     }
   }
   if (valid)
     for (int r = 0; r < NRC; ++r)
-      for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] += acc[r][c];
+      for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] += c1 * acc[r][c];
 }
 
 static RpyConst rpy_const(double a, double eta) {
@@ -282,16 +400,54 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
   return hipGetLastError();
 }
 
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u) {
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   const Built* B = l.B;
   if (tiles.n == 0 || B->lists[LO].len == 0) return hipSuccess;
-  RpyConst k = rpy_const(l.a, l.eta);
+  const RpyConst k = rpy_const(l.a, l.eta);
+  const PairK<float> kf = pair_const<float>(k, l.a);
+  const PairK<double> kd = pair_const<double>(k, l.a);
+#define OV_CASE(NR)                                                                                                 \
+  case NR:                                                                                                          \
+    if (mixed)                                                                                                      \
+      k_overlap<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], k.four_a2, B->sx,  \
+                                                      B->sy, B->sz, sF, B->n, kf, k.c1, u);                         \
+    else                                                                                                            \
+      k_overlap<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], k.four_a2, B->sx, \
+                                                       B->sy, B->sz, sF, B->n, kd, k.c1, u);                        \
+    break;
   switch (nrc) {
-    case 1: k_overlap<1><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LO], B->sx, B->sy, B->sz, sF, B->n, k, u); break;
-    case 2: k_overlap<2><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LO], B->sx, B->sy, B->sz, sF, B->n, k, u); break;
-    case 4: k_overlap<4><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LO], B->sx, B->sy, B->sz, sF, B->n, k, u); break;
+    OV_CASE(1)
+    OV_CASE(2)
+    OV_CASE(4)
     default: return hipErrorInvalidValue;
   }
+#undef OV_CASE
+  return hipGetLastError();
+}
+
+hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
+  const Built* B = l.B;
+  if (tiles.n == 0 || B->lists[LW].len == 0) return hipSuccess;
+  const RpyConst k = rpy_const(l.a, l.eta);
+  const PairK<float> kf = pair_const<float>(k, l.a);
+  const PairK<double> kd = pair_const<double>(k, l.a);
+  const int wmax = wdirect_max(l.p);
+#define WD_CASE(NR)                                                                                                 \
+  case NR:                                                                                                          \
+    if (mixed)                                                                                                      \
+      k_wdirect<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LW], wmax, B->sx, B->sy, B->sz, sF, \
+                                                      B->n, kf, k.c1, u);                                           \
+    else                                                                                                            \
+      k_wdirect<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LW], wmax, B->sx, B->sy, B->sz,    \
+                                                       sF, B->n, kd, k.c1, u);                                      \
+    break;
+  switch (nrc) {
+    WD_CASE(1)
+    WD_CASE(2)
+    WD_CASE(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef WD_CASE
   return hipGetLastError();
 }
 

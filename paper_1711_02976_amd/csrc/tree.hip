@@ -404,12 +404,16 @@ struct Emit {
   }
 };
 
+// Shell sort (gaps 3h+1): O(n^1.5) for the long O lists of dense clusters.
 __device__ inline void sort_segment(int* v, int n) {
-  for (int i = 1; i < n; ++i) {
-    int x = v[i], j = i - 1;
-    while (j >= 0 && v[j] > x) { v[j + 1] = v[j]; --j; }
-    v[j + 1] = x;
-  }
+  int h = 1;
+  while (h < n / 3) h = 3 * h + 1;
+  for (; h >= 1; h /= 3)
+    for (int i = h; i < n; ++i) {
+      int x = v[i], j = i - h;
+      while (j >= 0 && v[j] > x) { v[j + h] = v[j]; j -= h; }
+      v[j + h] = x;
+    }
 }
 
 // mode 0: count into cnt[5][nbox]; mode 1: fill at off[L][b].
@@ -753,7 +757,7 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
   // empty, and skipped, when every leaf side is at least 2a.
   int want_o = 0;
   for (int k = 0; k < nsys; ++k)
-    if (ldexp(B->side[k], -B->depth) < 2.0 * A.a) want_o = 1;
+    if (!A.skip_o && ldexp(B->side[k], -B->depth) < 2.0 * A.a) want_o = 1;
   int* lcnt = nullptr;
   int* lt = nullptr;
   if (dalloc(&lcnt, 5 * (int64_t)nbox, B, err) || dalloc(&lt, (int64_t)scan_tmp_ints(nbox + 1), B, err)) return -3;
