@@ -98,8 +98,8 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   }
   const double S = (p + 1.0) * (p + 2.0) * (2.0 * p + 3.0) / 6.0, S16 = 17.0 * 18.0 * 35.0 / 6.0;
   const double T = (p + 1.0) * (p + 2.0) / 2.0, T16 = 153.0;
-  const double c_pair = mixed ? 0.97 : 1.41;          // ns per ordered pair
-  const double c_v = (mixed ? 2210.0 : 2650.0) * S / S16;  // ns per (V pair, density)
+  const double c_pair = mixed ? 0.84 : 1.55;          // ns per ordered pair
+  const double c_v = (mixed ? 1400.0 : 1900.0) * S / S16;  // ns per (V pair, density)
   const double c_box = 45.0 * T / T16;                // ns per (box, density)
   const double c_wx = 3.0 * T / T16;                  // ns per (bead, W or X box, density)
   // bead pairs of O-list leaves: the overlap correction visits them at about
@@ -275,9 +275,10 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     rc = rpy::build_tree(ba, &P->B, &err);
   } else {
     // Refinement limit chosen by the cost model over a ladder of limits
-    // (64 * 1.5^k); limits that provably give the tree already built are
-    // skipped, and the search stops once the modelled time has grown well
-    // past the best (the model is unimodal in the limit in practice).
+    // (64 * 1.5^k) up to the largest system; limits that provably give the
+    // tree already built are skipped, so only distinct trees are built.  The
+    // whole ladder is searched: partly refined (adaptive) trees in between
+    // need a higher order, so the modelled time is not unimodal in the limit.
     // Trial trees are built without the O list: the overlapping bead pairs
     // are fixed by the geometry, not by the tree, and dense clusters with
     // small leaves make that list very long.  The chosen tree is rebuilt
@@ -309,7 +310,6 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
           if (ldexp(P->B.side[s], -P->B.depth) < 2.0 * a) need_o = true;
       } else {
         rpy::free_built(&Bc);
-        if (tc.ns > 1.5 * best) break;
       }
       if (cand >= nmax || tc.same_hi > nmax) break;  // one leaf per system from here on
       do sl *= 1.5;
