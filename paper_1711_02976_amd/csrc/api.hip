@@ -120,13 +120,20 @@ struct rpy_plan_s {
   int p = 0, leaf_size = 0, max_depth = 14, precision = 0, m2l_mode = 2;
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
+  // The near field (P2P, overlap and direct W sums) runs on a second stream
+  // of the plan, concurrently with the far-field chain on `stream`, into a
+  // separate velocity buffer; events order the two, and the result is
+  // combined on `stream`.
+  hipStream_t near = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int sticky = 0;
   // matvec workspace, sized for `ws_nrc` right-hand sides per pass
   int ws_nrc = 0;
   double2* M = nullptr;
   double2* L = nullptr;
   double* sF = nullptr;
-  double* u = nullptr;
+  double* u = nullptr;   // near-field velocities, tree order
+  double* uf = nullptr;  // far-field velocities, tree order
   int64_t ws_bytes = 0;
   double plan_ms = 0;
   // per-phase timing
@@ -147,14 +154,14 @@ static hipEvent_t get_event(rpy_plan_t* P) {
   return e;
 }
 
-// Runs one phase, bracketed by events when timing is on.
+// Runs one phase, bracketed by events on its stream when timing is on.
 template <class F>
-static hipError_t timed(rpy_plan_t* P, int phase, int launches, F&& f) {
+static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, F&& f) {
   if (!P->timing) return f();
   hipEvent_t a = get_event(P), b = get_event(P);
-  if (a) (void)hipEventRecord(a, P->stream);
+  if (a) (void)hipEventRecord(a, st);
   hipError_t e = f();
-  if (b) (void)hipEventRecord(b, P->stream);
+  if (b) (void)hipEventRecord(b, st);
   if (a && b) P->ev_pending.push_back({phase, {a, b}});
   P->acc.launches[phase] += launches;
   return e;
@@ -171,11 +178,11 @@ static void fold_events(rpy_plan_t* P) {
 }
 
 static void free_ws(rpy_plan_t* P) {
-  void* ps[] = {P->M, P->L, P->sF, P->u};
+  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   P->M = P->L = nullptr;
-  P->sF = P->u = nullptr;
+  P->sF = P->u = P->uf = nullptr;
   P->ws_nrc = 0;
   P->ws_bytes = 0;
 }
@@ -189,12 +196,13 @@ static int alloc_ws(rpy_plan_t* P, int nrc) {
   size_t ex = sizeof(double2) * nbox * 4 * nrc * T;
   size_t vb = sizeof(double) * 3 * nrc * n;
   if (hipMalloc(&P->M, ex) != hipSuccess || hipMalloc(&P->L, ex) != hipSuccess ||
-      hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess) {
+      hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess ||
+      hipMalloc(&P->uf, vb) != hipSuccess) {
     free_ws(P);
     return -1;
   }
   P->ws_nrc = nrc;
-  P->ws_bytes = 2 * ex + 2 * vb;
+  P->ws_bytes = 2 * ex + 3 * vb;
   return 0;
 }
 
@@ -325,6 +333,20 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
+  if (rc == 0) {
+    // default priority (no priority argument); without it the near field
+    // runs on the plan's stream
+    if (hipStreamCreateWithFlags(&P->near, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (P->near) (void)hipStreamDestroy(P->near);
+      if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+      if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+      P->near = nullptr;
+      P->ev_fork = P->ev_join = nullptr;
+    }
+  }
 
   if (rc != 0) {
     rpy_status st = rc == -2 ? RPY_ENONFINITE : rc == -3 ? RPY_ENOMEM : RPY_EDEVICE;
@@ -365,20 +387,32 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     const rpy::Built& B = P->B;
     const int nlev = B.depth;
     const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
-    hipError_t he = timed(P, RPY_PH_PERMUTE, 1, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_P2P, 1, [&] { return rpy::run_p2p(l, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_overlap(l, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && haveW) he = timed(P, RPY_PH_OVERLAP, 1, [&] { return rpy::run_wdirect(l, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, [&] { return rpy::run_p2m(l, c, P->sF, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, [&] { return rpy::run_m2m(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, [&] {
+    const hipStream_t s0 = P->stream, s1 = P->near ? P->near : P->stream;
+    rpy::Launch ln = l;
+    ln.s = s1;
+    hipError_t he = timed(P, RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
+    // near field on s1, after the permute
+    if (he == hipSuccess && P->near) {
+      he = hipEventRecord(P->ev_fork, s0);
+      if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
+    }
+    if (he == hipSuccess) he = timed(P, RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, P->sF, P->u, mixed); });
+    if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, P->sF, P->u, mixed); });
+    if (he == hipSuccess && haveW) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, P->sF, P->u, mixed); });
+    if (he == hipSuccess && P->near) he = hipEventRecord(P->ev_join, s1);
+    // far field on s0
+    if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, s0, [&] { return rpy::run_m2m(l, c, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, s0, [&] {
       if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
       return rpy::run_m2l_rot(l, c, e, mixed);
     });
-    if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, [&] { return rpy::run_p2l(l, c, P->sF, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, [&] { return rpy::run_l2l(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, [&] { return rpy::run_eval(l, c, e, P->u); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_UNPERMUTE, 1, [&] { return rpy::unpermute_velocities(l, P->u, r0, c, velocities); });
+    if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, c, e, P->uf); });
+    // join, then near + far back to caller order
+    if (he == hipSuccess && P->near) he = hipStreamWaitEvent(s0, P->ev_join, 0);
+    if (he == hipSuccess) he = timed(P, RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
     if (P->timing) P->acc.passes += 1;
     if (he != hipSuccess) {
       P->sticky = 1;
@@ -471,7 +505,11 @@ void rpy_plan_free(rpy_plan_t* P) {
   if (!P) return;
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
+  if (P->near) (void)hipStreamSynchronize(P->near);
   fold_events(P);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->near) (void)hipStreamDestroy(P->near);
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   free_ws(P);
   rpy::free_tables(&P->tb);

@@ -60,8 +60,8 @@ struct Launch {
 
 // Forces (caller order, [nrhs][n][3]) -> sorted SoA [nrc][3][n] for rhs r0..r0+nrc-1.
 hipError_t permute_forces(const Launch& l, const double* F, int nrhs_total, int r0, int nrc, double* sF);
-// Sorted SoA velocities -> caller order output.
-hipError_t unpermute_velocities(const Launch& l, const double* u, int r0, int nrc, double* out);
+// Near- plus far-field velocities (sorted SoA) -> caller order output.
+hipError_t unpermute_velocities(const Launch& l, const double* u, const double* uf, int r0, int nrc, double* out);
 
 hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_m2m(const Launch& l, int nrc, Exp e);
@@ -69,6 +69,7 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e);       // dense O(p^4)
 hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32);  // rotation, O(p^3)
 hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_l2l(const Launch& l, int nrc, Exp e);
+// Writes the far-field velocities of every bead (assigns; sorted SoA).
 hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u);
 
 // Near field.  `tiles` lists (leaf, first bead, count) work items.

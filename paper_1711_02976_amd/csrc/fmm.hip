@@ -383,13 +383,14 @@ __global__ void k_permute_forces(const double* F, const int* perm, int64_t n, in
   }
 }
 
-__global__ void k_unpermute(const double* u, const int* perm, int64_t n, int r0, int nrc, double* out) {
+__global__ void k_unpermute(const double* u, const double* uf, const int* perm, int64_t n, int r0, int nrc,
+                            double* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t j = perm[i];
   for (int r = 0; r < nrc; ++r) {
     double* o = out + ((int64_t)(r0 + r) * n + j) * 3;
-    for (int k = 0; k < 3; ++k) o[k] = u[((int64_t)r * 3 + k) * n + i];
+    for (int k = 0; k < 3; ++k) o[k] = u[((int64_t)r * 3 + k) * n + i] + uf[((int64_t)r * 3 + k) * n + i];
   }
 }
 
@@ -401,10 +402,10 @@ hipError_t permute_forces(const Launch& l, const double* F, int nrhs_total, int 
   return hipGetLastError();
 }
 
-hipError_t unpermute_velocities(const Launch& l, const double* u, int r0, int nrc, double* out) {
+hipError_t unpermute_velocities(const Launch& l, const double* u, const double* uf, int r0, int nrc, double* out) {
   int64_t n = l.B->n;
   if (n == 0) return hipSuccess;
-  k_unpermute<<<nblk(n, 256), 256, 0, l.s>>>(u, l.B->perm, n, r0, nrc, out);
+  k_unpermute<<<nblk(n, 256), 256, 0, l.s>>>(u, uf, l.B->perm, n, r0, nrc, out);
   return hipGetLastError();
 }
 
@@ -867,7 +868,10 @@ __global__ void __launch_bounds__(NT) k_eval(int p, int pw, const int* leaves, T
         for (int q = 0; q < EVB; ++q) {
           const int j = jb + threadIdx.x + q * NT;
           if (j < j1)
-            for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + j] += uu[q][k];
+            for (int k = 0; k < 3; ++k) {
+              double* o = u + ((int64_t)r * 3 + k) * n + j;
+              *o = mult ? *o + uu[q][k] : uu[q][k];  // the leaf's own expansion comes first and assigns
+            }
         }
       }
     }
