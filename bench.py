@@ -29,7 +29,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
-WORKLOADS = {"cube-2k": 1, "cube-1M": 2, "blobs-4M": 3, "batched-64": 4, "cube-15M": 5}
+WORKLOADS = {"cube-2k": 1, "cube-1M": 2, "blobs-4M": 3, "batched-64": 4, "cube-15M": 5, "sphere-8M": 6}
 
 
 def progress(msg):
@@ -268,7 +268,8 @@ def main():
     ap.add_argument("--precisions", default="fp64,mixed", help="comma list of forms to time: fp64,mixed")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--order", type=int, default=0)
-    ap.add_argument("--cpu-targets", type=int, default=2000)
+    ap.add_argument("--cpu-targets", type=int, default=12000,
+                    help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")

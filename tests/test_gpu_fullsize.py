@@ -6,7 +6,8 @@ size and order, both precision forms).
   * blobs-4M:   4,000,000 clustered beads (2,000 Gaussian blobs), 4 rhs,
                 adaptive tree with W/X lists and overlapping pairs outside U;
   * batched-64: 64 independent systems of 1e3 .. 2e5 beads, 16 rhs, one plan;
-  * cube-15M:   15,000,000 uniform beads, 20 rhs.
+  * cube-15M:   15,000,000 uniform beads, 20 rhs;
+  * sphere-8M:  8,000,000 beads uniform on a sphere surface (adaptive tree).
 """
 import numpy as np
 import pytest
@@ -79,4 +80,15 @@ def test_cube_15M_mixed(orc):
     ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
     err = orc.rel_l2(u, ref)
     log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} rel-L2 = {err:.3e}")
+    assert err <= w.eps
+
+
+def test_sphere_8M_mixed(orc):
+    w = W.config(6, nsample=200)
+    log(f"{w.name} n={w.n} nrhs={w.nrhs} mixed")
+    u, st = _run(w, "mixed")
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
+    err = orc.rel_l2(u, ref)
+    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} "
+        f"W={st['list_len']['W']} O={st['list_len']['O']} rel-L2 = {err:.3e}")
     assert err <= w.eps

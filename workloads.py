@@ -104,8 +104,9 @@ def multi_system(nsys, nmin, nmax, density, a, nrhs, eps=1e-6, seed=0, per_sys_s
 
 
 def config(cid: int, scale: float = 1.0, seed=None, nsample=None):
-    """The five named workloads; `scale` < 1 shrinks the bead count while
-    keeping the bead density (cube sides shrink by scale^(1/3))."""
+    """The named workloads (1-5, and 6: 8M beads on a sphere surface);
+    `scale` < 1 shrinks the bead count while keeping the bead density (cube
+    sides shrink by scale^(1/3))."""
     s = 1000 + cid if seed is None else seed
     c3 = scale ** (1.0 / 3.0)
     if cid == 1:
@@ -127,4 +128,10 @@ def config(cid: int, scale: float = 1.0, seed=None, nsample=None):
         n = max(1, int(round(15_000_000 * scale)))
         return uniform_cube(n, 2000.0 * c3, 0.5, 20, 1e-6, s, 10_000 if nsample is None else nsample,
                             "cube-15M")
+    if cid == 6:
+        # uniform on a sphere surface (the paper's second workload), one bead
+        # per unit area: radius sqrt(n / (4 pi))
+        n = max(1, int(round(8_000_000 * scale)))
+        return sphere_surface(n, float(np.sqrt(n / (4.0 * np.pi))), 0.5, 1, 1e-6, s,
+                              10_000 if nsample is None else nsample, "sphere-8M")
     raise ValueError(f"unknown config {cid}")
