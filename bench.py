@@ -120,9 +120,15 @@ def run(args):
         tm = P.timings()
         ms = (t1 - t0) * 1e3 / args.steps
         progress(f"{w.name} {prec}: {args.steps} timed matvecs, {ms:.2f} ms each")
+        # one more matvec, outside the timed region, with every phase run
+        # alone on the plan stream: isolated per-phase times
+        P.set_timing(2)
+        P.matvec(F, out=U)
+        tms = P.timings()
+        P.set_timing(False)
         nrc = 4 if w.nrhs >= 4 else (2 if w.nrhs >= 2 else 1)
         alg = algorithmic_counts(P, st["order"], nrc)
-        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "alg": alg,
+        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "serial": tms, "alg": alg,
                          "u": U[:, w.sample].cpu().numpy()}
 
     # CPU baseline: the FP64 oracle's direct sum on the sampled targets.
@@ -185,6 +191,7 @@ def run(args):
                    "plan_ms": round(r["stats"]["plan_ms"], 2)},
         "rel_l2_vs_direct": errs.get(best),
         "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
+        "phases_serial_ms": {k: round(v, 4) for k, v in r["serial"]["ms"].items()},
         "forms": {p: {"ms_per_step": round(q["ms"], 4), "value": w.n * w.nrhs / (q["ms"] * 1e-3),
                       "rel_l2_vs_direct": errs.get(p)} for p, q in results.items()},
         "roofline": roof,

@@ -152,9 +152,13 @@ typedef struct {
   int64_t passes;                /* matvec passes (right-hand-side chunks) timed */
 } rpy_timings_t;
 
-/* Enable (1) or disable (0) per-phase timing with HIP events on the plan's
- * stream; enabling resets the accumulators.  Timing adds two events per
- * phase and pass and no synchronisation. */
+/* Per-phase timing with HIP events: 0 off, 1 on (phases keep their normal
+ * concurrency: the near field runs on a second stream beside the far-field
+ * chain, so concurrent phases share the GPU), 2 on with every phase run on
+ * the plan's stream one after another (each phase's time is its own; the
+ * matvec is slower).  Any call resets the accumulators.  Timing adds two
+ * events per phase and pass and no synchronisation.  Other values:
+ * RPY_EINVAL. */
 rpy_status rpy_plan_set_timing(rpy_plan_t* plan, int32_t enable);
 
 /* Waits for the plan's stream, folds all recorded events into *out. */

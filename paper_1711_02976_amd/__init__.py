@@ -162,7 +162,7 @@ def rpy_plan_export(plan):
 
 
 def rpy_plan_set_timing(plan, enable):
-    _check(lib().rpy_plan_set_timing(plan, 1 if enable else 0))
+    _check(lib().rpy_plan_set_timing(plan, int(enable)))
 
 
 def rpy_plan_timings(plan):
@@ -235,7 +235,9 @@ class Plan:
         return rpy_plan_export(self.handle)
 
     def set_timing(self, enable=True):
-        rpy_plan_set_timing(self.handle, enable)
+        """True/1: per-phase events with the normal concurrency; 2: phases
+        run one after another on the plan stream (isolated phase times)."""
+        rpy_plan_set_timing(self.handle, int(enable))
 
     def timings(self):
         return rpy_plan_timings(self.handle)

@@ -134,6 +134,7 @@ struct rpy_plan_s {
   double* sF = nullptr;
   double* u = nullptr;   // near-field velocities, tree order
   double* uf = nullptr;  // far-field velocities, tree order
+  double* Q = nullptr;   // per-bead charges for S->M / S->L, tree order
   int64_t ws_bytes = 0;
   double plan_ms = 0;
   // per-phase timing
@@ -178,11 +179,11 @@ static void fold_events(rpy_plan_t* P) {
 }
 
 static void free_ws(rpy_plan_t* P) {
-  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf};
+  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   P->M = P->L = nullptr;
-  P->sF = P->u = P->uf = nullptr;
+  P->sF = P->u = P->uf = P->Q = nullptr;
   P->ws_nrc = 0;
   P->ws_bytes = 0;
 }
@@ -194,15 +195,18 @@ static int alloc_ws(rpy_plan_t* P, int nrc) {
   const int64_t nbox = std::max(P->B.tree.nbox, 1);
   const int64_t n = std::max<int64_t>(P->B.n, 1);
   size_t ex = sizeof(double2) * nbox * 4 * nrc * T;
-  size_t vb = sizeof(double) * 3 * nrc * n;
+  // Q: per-bead charges plus 64 rows that the S->M/S->L kernels may read past
+  // the last bead (with zero weight); zeroed once so every row is finite
+  size_t vb = sizeof(double) * 3 * nrc * n, qb = sizeof(double) * 4 * nrc * (n + 64);
   if (hipMalloc(&P->M, ex) != hipSuccess || hipMalloc(&P->L, ex) != hipSuccess ||
       hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess ||
-      hipMalloc(&P->uf, vb) != hipSuccess) {
+      hipMalloc(&P->uf, vb) != hipSuccess || hipMalloc(&P->Q, qb) != hipSuccess ||
+      hipMemset(P->Q, 0, qb) != hipSuccess) {
     free_ws(P);
     return -1;
   }
   P->ws_nrc = nrc;
-  P->ws_bytes = 2 * ex + 3 * vb;
+  P->ws_bytes = 2 * ex + 3 * vb + qb;
   return 0;
 }
 
@@ -380,26 +384,29 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream};
-  rpy::Exp e{P->M, P->L};
+  rpy::Exp e{P->M, P->L, P->Q};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
     int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
     const rpy::Built& B = P->B;
     const int nlev = B.depth;
     const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
-    const hipStream_t s0 = P->stream, s1 = P->near ? P->near : P->stream;
+    // timing mode 2 runs the near field on the plan stream too, so that each
+    // phase's events measure that phase alone
+    const bool fork = P->near && P->timing != 2;
+    const hipStream_t s0 = P->stream, s1 = fork ? P->near : P->stream;
     rpy::Launch ln = l;
     ln.s = s1;
     hipError_t he = timed(P, RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
     // near field on s1, after the permute
-    if (he == hipSuccess && P->near) {
+    if (he == hipSuccess && fork) {
       he = hipEventRecord(P->ev_fork, s0);
       if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
     }
     if (he == hipSuccess) he = timed(P, RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, P->sF, P->u, mixed); });
     if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, P->sF, P->u, mixed); });
     if (he == hipSuccess && haveW) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && P->near) he = hipEventRecord(P->ev_join, s1);
+    if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
     // far field on s0
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, s0, [&] { return rpy::run_m2m(l, c, e); });
@@ -411,7 +418,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, c, e, P->uf); });
     // join, then near + far back to caller order
-    if (he == hipSuccess && P->near) he = hipStreamWaitEvent(s0, P->ev_join, 0);
+    if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
     if (he == hipSuccess) he = timed(P, RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
     if (P->timing) P->acc.passes += 1;
     if (he != hipSuccess) {
@@ -489,7 +496,8 @@ rpy_status rpy_plan_set_timing(rpy_plan_t* P, int32_t enable) {
   if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(RPY_EDEVICE, "stream synchronisation failed");
   fold_events(P);
   P->acc = rpy_timings_t{};
-  P->timing = enable ? 1 : 0;
+  if (enable < 0 || enable > 2) return fail(RPY_EINVAL, "timing mode must be 0, 1 or 2");
+  P->timing = enable;
   return RPY_OK;
 }
 

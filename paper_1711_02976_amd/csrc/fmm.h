@@ -17,6 +17,16 @@ namespace rpy {
 struct Exp {
   double2* M;
   double2* L;
+  double* Q;  // per-bead charges [n][4 nrc] for S->M and S->L (written by run_p2m)
+};
+
+// Per wave and pass of the S->M / S->L kernels (p2e.hip): bit k of `start`
+// marks a step that begins a column (order m, the next 5-bit field of
+// mhi:mlo), steps k < nvalid produce a coefficient, the rest pad with zero.
+struct P2EPass {
+  uint32_t start;
+  int32_t nvalid;
+  uint32_t mlo, mhi;
 };
 
 struct Tables {
@@ -36,12 +46,21 @@ struct Tables {
   double* geo;
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
   double* rnm;     // [ncoef(p+2)] 1/((n+m)(n-m)) (0 for n < m+2)
+  // S->M / S->L schedule: per wave (8) and pass (P) a P2EPass, the
+  // coefficient held by each of the 8K slots of each pass (-1: padding) with
+  // its factor 1/((n-m)!(n+m)!), and the diagonal constants (-1)^m (2m-1)!!.
+  P2EPass* p2e_desc;
+  int* p2e_slot;
+  double* p2e_scale;
+  double* p2e_dk;
+  int p2e_K, p2e_P;
   int rot_len;     // sum_n (n+1)^2
   int zt_len;      // sum_l (p-l+1)^2
   int64_t bytes;
 };
 
 int make_tables(int p, Tables* tb, hipStream_t s, Error* err);
+int make_p2e_tables(int p, Tables* tb, Error* err);  // p2e.hip; called by make_tables
 
 // Host helpers (fmm.hip): paper-normalised Y_n^m for 0 <= m <= n <= p at
 // (cos theta, phi); the rotation by +90 degrees about y on degree-n sets,

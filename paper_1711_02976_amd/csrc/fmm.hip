@@ -45,54 +45,6 @@ __device__ inline double2 getc(const double2* C, int n, int m, int nmax) {
   return (m & 1) ? make_double2(-v.x, v.y) : make_double2(v.x, -v.y);
 }
 
-// Column m of the regular harmonics R_n^m(v), n = m..nmax, into H[tri(n)+m].
-__device__ inline void regular_column(double x, double y, double z, int m, int nmax, const double* rnm, double2* H) {
-  double r2 = x * x + y * y + z * z;
-  double2 rmm = make_double2(1.0, 0.0);
-  for (int k = 1; k <= m; ++k) {
-    double f = -0.5 / k;
-    rmm = make_double2(f * (x * rmm.x - y * rmm.y), f * (x * rmm.y + y * rmm.x));
-  }
-  if (m > nmax) return;
-  H[tri(m) + m] = rmm;
-  if (m + 1 > nmax) return;
-  double2 r1 = make_double2(z * rmm.x, z * rmm.y);
-  H[tri(m + 1) + m] = r1;
-  double2 r0 = rmm;
-  for (int n = m + 2; n <= nmax; ++n) {
-    const double inv = rnm[tri(n) + m];
-    double a = (2 * n - 1) * z * inv, b = r2 * inv;
-    double2 rn = make_double2(a * r1.x - b * r0.x, a * r1.y - b * r0.y);
-    H[tri(n) + m] = rn;
-    r0 = r1;
-    r1 = rn;
-  }
-}
-
-// Column m of the irregular harmonics I_n^m(v), n = m..nmax.
-__device__ inline void irregular_column(double x, double y, double z, int m, int nmax, double2* H) {
-  double r2 = x * x + y * y + z * z;
-  double ir2 = 1.0 / r2;
-  double2 imm = make_double2(sqrt(ir2), 0.0);
-  for (int k = 1; k <= m; ++k) {
-    double f = -(2 * k - 1) * ir2;
-    imm = make_double2(f * (x * imm.x - y * imm.y), f * (x * imm.y + y * imm.x));
-  }
-  if (m > nmax) return;
-  H[tri(m) + m] = imm;
-  if (m + 1 > nmax) return;
-  double f1 = (2 * m + 1) * z * ir2;
-  double2 i1 = make_double2(f1 * imm.x, f1 * imm.y);
-  H[tri(m + 1) + m] = i1;
-  double2 i0 = imm;
-  for (int n = m + 2; n <= nmax; ++n) {
-    double a = (2 * n - 1) * z * ir2, b = (double)(n + m - 1) * (n - m - 1) * ir2;
-    double2 in = make_double2(a * i1.x - b * i0.x, a * i1.y - b * i0.y);
-    H[tri(n) + m] = in;
-    i0 = i1;
-    i1 = in;
-  }
-}
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
@@ -360,16 +312,21 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   RPY_HIP(hipMemcpy(tb->geo, geo.data(), sizeof(double) * geo.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->sfac, sf.data(), sizeof(double) * sf.size(), hipMemcpyHostToDevice));
   (void)s;
-  return 0;
+  return make_p2e_tables(p, tb, err);
 }
 
 void free_tables(Tables* tb) {
-  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rnm};
+  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rnm,
+                tb->p2e_desc, tb->p2e_slot, tb->p2e_scale, tb->p2e_dk};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   tb->oct = tb->itab = nullptr;
   tb->rot64 = tb->zt64 = tb->geo = tb->sfac = tb->rnm = nullptr;
   tb->rot32 = tb->zt32 = nullptr;
+  tb->p2e_desc = nullptr;
+  tb->p2e_slot = nullptr;
+  tb->p2e_scale = nullptr;
+  tb->p2e_dk = nullptr;
 }
 
 // ------------------------------------------------------------- permutes ----
@@ -407,85 +364,6 @@ hipError_t unpermute_velocities(const Launch& l, const double* u, const double* 
   if (n == 0) return hipSuccess;
   k_unpermute<<<nblk(n, 256), 256, 0, l.s>>>(u, uf, l.B->perm, n, r0, nrc, out);
   return hipGetLastError();
-}
-
-// ----------------------------------------------------------- S->M, S->L ---
-// One block per box.  Beads are taken CH at a time: their harmonics go to
-// LDS column by column, then thread t accumulates coefficient t of every
-// density.  LOCAL = false: multipole of the box's own beads (S->M, written);
-// LOCAL = true: local expansion from the beads of the box's X list (S->L,
-// added).
-constexpr int P2E_T = 256;
-constexpr int P2E_CH = 16;
-
-template <int ND, bool LOCAL>
-__global__ void __launch_bounds__(P2E_T) k_p2e(int p, const int* ids, Tree t, List X, const double* sx,
-                                               const double* sy, const double* sz, const double* sF, int64_t n,
-                                               const double* __restrict__ rnm, double2* E) {
-  constexpr int NRC = ND / 4;
-  const int T = ncoef(p);
-  const int b = ids ? ids[blockIdx.x] : blockIdx.x;
-  int s0 = 0, s1 = 1;
-  if (LOCAL) {
-    s0 = X.off[b];
-    s1 = X.off[b + 1];
-    if (s0 == s1) return;
-  }
-  extern __shared__ double2 H[];  // P2E_CH * ncoef(p)
-  __shared__ double q[P2E_CH][ND];
-  __shared__ double xi[P2E_CH][3];
-  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
-  double2 acc[ND];
-  for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
-  for (int si = s0; si < s1; ++si) {
-    const int C = LOCAL ? X.ent[si] : b;
-    const int j0 = t.begin[C], j1 = t.end[C];
-    for (int jc = j0; jc < j1; jc += P2E_CH) {
-      const int nb = min(P2E_CH, j1 - jc);
-      __syncthreads();
-      if (threadIdx.x < nb) {
-        int j = jc + threadIdx.x;
-        double dx = sx[j] - cx, dy = sy[j] - cy, dz = sz[j] - cz;
-        xi[threadIdx.x][0] = dx * ih; xi[threadIdx.x][1] = dy * ih; xi[threadIdx.x][2] = dz * ih;
-        for (int r = 0; r < NRC; ++r) {
-          double fx = sF[((int64_t)r * 3 + 0) * n + j], fy = sF[((int64_t)r * 3 + 1) * n + j],
-                 fz = sF[((int64_t)r * 3 + 2) * n + j];
-          q[threadIdx.x][4 * r] = fx; q[threadIdx.x][4 * r + 1] = fy; q[threadIdx.x][4 * r + 2] = fz;
-          q[threadIdx.x][4 * r + 3] = fx * dx + fy * dy + fz * dz;
-        }
-      }
-      __syncthreads();
-      for (int w = threadIdx.x; w < nb * (p + 1); w += P2E_T) {
-        int bj = w / (p + 1), m = w % (p + 1);
-        if (LOCAL) irregular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, H + bj * T);
-        else regular_column(xi[bj][0], xi[bj][1], xi[bj][2], m, p, rnm, H + bj * T);
-      }
-      __syncthreads();
-      if (threadIdx.x < T) {
-        for (int bj = 0; bj < nb; ++bj) {
-          double2 hv = H[bj * T + threadIdx.x];
-          hv.y = -hv.y;  // conjugate
-#pragma unroll
-          for (int d = 0; d < ND; ++d) {
-            acc[d].x = fma(q[bj][d], hv.x, acc[d].x);
-            acc[d].y = fma(q[bj][d], hv.y, acc[d].y);
-          }
-        }
-      }
-    }
-  }
-  if (threadIdx.x < T) {
-    double2* out = E + (int64_t)b * ND * T + threadIdx.x;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      if (LOCAL) {
-        double2 v = out[d * T];
-        out[d * T] = make_double2(v.x + acc[d].x, v.y + acc[d].y);
-      } else {
-        out[d * T] = acc[d];
-      }
-    }
-  }
 }
 
 // ------------------------------------------------------------------ M->M --
@@ -885,24 +763,6 @@ __global__ void __launch_bounds__(NT) k_eval(int p, int pw, const int* leaves, T
     case 4: { constexpr int ND = 16; KERNEL_CALL; break; } \
     default: return hipErrorInvalidValue;                  \
   }
-
-hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e) {
-  const Built* B = l.B;
-  if (B->nleaf == 0) return hipSuccess;
-  const size_t shm = sizeof(double2) * P2E_CH * ncoef(l.p);
-  DISPATCH_ND(nrc, (k_p2e<ND, false><<<B->nleaf, P2E_T, shm, l.s>>>(l.p, B->leaf_ids, B->tree, B->lists[LX], B->sx,
-                                                                     B->sy, B->sz, sF, B->n, l.tb->rnm, e.M)));
-  return hipGetLastError();
-}
-
-hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
-  const Built* B = l.B;
-  if (B->lists[LX].len == 0) return hipSuccess;
-  const size_t shm = sizeof(double2) * P2E_CH * ncoef(l.p);
-  DISPATCH_ND(nrc, (k_p2e<ND, true><<<B->tree.nbox, P2E_T, shm, l.s>>>(l.p, nullptr, B->tree, B->lists[LX], B->sx,
-                                                                        B->sy, B->sz, sF, B->n, l.tb->rnm, e.L)));
-  return hipGetLastError();
-}
 
 hipError_t run_m2m(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;

@@ -1,0 +1,400 @@
+// Particle -> expansion kernels of the four-Laplace FMM (arXiv:1711.02976,
+// Sec. 2): S->M for the leaves and S->L for the X lists of the adaptive tree
+// (Theorem 1).  Both are the contraction
+//
+//   E_n^m[d] = sum_j conj(Y_n^m(r_j - c)) q_j[d]
+//
+// of the bead charges q_j (F_x, F_y, F_z and the fourth charge F.(r - c) per
+// right-hand side) with the regular (S->M) or irregular (S->L) solid
+// harmonics about the expansion centre c, in the box-scaled normalisation of
+// the other far-field kernels.
+//
+// Layout of the work.  A block (8 waves) sweeps the beads of its source
+// leaves in chunks of 64.  Generation: lane = bead, and each wave walks a
+// fixed set of orders m (a balanced bin of whole columns n = m..p), so the
+// degree/order of every step is wave-uniform (a per-pass descriptor says
+// where columns start) and no step reads memory; the harmonics go to LDS
+// as [bead][slot].
+// Accumulation: lane = slot (one coefficient), loop over beads, with the
+// bead charges read by scalar loads from a per-bead charge array; the four
+// (or eight) waves that share a slot group each take a quarter (eighth) of
+// the chunk's beads and their partial sums are added once per box.  A
+// column may run over several passes of K steps per wave; the recurrence
+// state stays in registers between passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fmm.h"
+
+namespace rpy {
+
+namespace {
+
+__device__ inline double2 zmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+constexpr int P2E_WAVES = 8;
+constexpr int P2E_THREADS = 64 * P2E_WAVES;
+constexpr int P2E_CHUNK = 64;  // beads per chunk = lanes per wave
+
+// Charges per bead for the S->M/S->L contraction, [n][4 nrc] (bead-major so a
+// wave reads one bead's charges with a scalar load): F_x, F_y, F_z and
+// F.(r - c_leaf) per right-hand side, c_leaf the centre of the bead's leaf.
+template <int NRC>
+__global__ void __launch_bounds__(256) k_leaf_q(const int* leaves, Tree t, const double* sx, const double* sy,
+                                                const double* sz, const double* sF, int64_t n, double* Q) {
+  constexpr int ND = 4 * NRC;
+  const int b = leaves[blockIdx.x];
+  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b];
+  for (int j = t.begin[b] + threadIdx.x; j < t.end[b]; j += blockDim.x) {
+    const double dx = sx[j] - cx, dy = sy[j] - cy, dz = sz[j] - cz;
+#pragma unroll
+    for (int r = 0; r < NRC; ++r) {
+      const double fx = sF[((int64_t)r * 3 + 0) * n + j], fy = sF[((int64_t)r * 3 + 1) * n + j],
+                   fz = sF[((int64_t)r * 3 + 2) * n + j];
+      double* q = Q + (int64_t)j * ND + 4 * r;
+      q[0] = fx;
+      q[1] = fy;
+      q[2] = fz;
+      q[3] = fx * dx + fy * dy + fz * dz;
+    }
+  }
+}
+
+// The regular harmonics are generated unnormalised, S_n^m = (n-m)!(n+m)! R_n^m,
+// and the irregular ones as they are, so that both obey
+//   h_n = (2n-1) z' h_{n-1} - ((n-1)^2 - m^2) r' h_{n-2},
+//   h_m = (-1)^m (2m-1)!! (x' + i y')^m s'
+// with (x', y', z', r', s') = (x, y, z, r^2, 1) for S_n^m and
+// (x/r^2, y/r^2, z/r^2, 1/r^2, 1/r) for I_n^m (box units about the centre);
+// the two integer coefficients are kept as running FP64 counters, and
+// S_n^m is scaled back to R_n^m per coefficient when the sums are written.
+//
+// K generation steps per wave and pass, P passes: S = 8 K slots per pass,
+// G = S / 64 slot groups, NB = 8 / G bead subsets (partial sums per slot).
+template <int ND, bool LOCAL, int K, int P>
+__global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree t, List X, const double* sx,
+                                                     const double* sy, const double* sz, const double* __restrict__ Q,
+                                                     const P2EPass* __restrict__ desc,
+                                                     const int* __restrict__ slot_coef,
+                                                     const double* __restrict__ slot_scale,
+                                                     const double* __restrict__ dk, double2* E) {
+  constexpr int NRC = ND / 4;
+  constexpr int S = P2E_WAVES * K, G = S / 64, NB = P2E_WAVES / G, BPW = P2E_CHUNK / NB;
+  constexpr int LD = S + 1;  // odd row stride: conflict-free [bead][slot] writes
+  const int T = ncoef(p);
+  const int b = ids ? ids[blockIdx.x] : blockIdx.x;
+  int e0 = 0, e1 = 1;
+  if (LOCAL) {
+    e0 = X.off[b];
+    e1 = X.off[b + 1];
+    if (e0 == e1) return;
+  }
+  extern __shared__ double2 Hs[];  // [64][LD]
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int grp = wv % G, sub = wv / G;
+  const int slot = grp * 64 + lane;
+  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
+  double2 acc[P][ND];
+#pragma unroll
+  for (int ps = 0; ps < P; ++ps)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[ps][d] = make_double2(0.0, 0.0);
+
+  for (int e = e0; e < e1; ++e) {
+    const int C = LOCAL ? X.ent[e] : b;
+    const int j0 = t.begin[C], j1 = t.end[C];
+    // Q holds the fourth charge about the source leaf's centre; about c:
+    // F.(r - c) = F.(r - c_C) + F.(c_C - c)
+    double wx = 0.0, wy = 0.0, wz = 0.0;
+    if (LOCAL) {
+      wx = t.cx[C] - cx;
+      wy = t.cy[C] - cy;
+      wz = t.cz[C] - cz;
+    }
+    for (int jc = j0; jc < j1; jc += P2E_CHUNK) {
+      const int nb = min(P2E_CHUNK, j1 - jc);
+      const int jl = jc + (lane < nb ? lane : 0);  // idle lanes: a valid bead, zero weight
+      const double x = (sx[jl] - cx) * ih, y = (sy[jl] - cy) * ih, z = (sz[jl] - cz) * ih;
+      const double r2 = x * x + y * y + z * z;
+      double zz, rr, ux, uy, sc;
+      if (LOCAL) {
+        rr = 1.0 / r2;
+        zz = z * rr;
+        ux = x * rr;
+        uy = y * rr;
+        sc = sqrt(rr);
+      } else {
+        rr = r2;
+        zz = z;
+        ux = x;
+        uy = y;
+        sc = 1.0;
+      }
+      if (lane >= nb) sc = 0.0;  // every harmonic of an idle lane is zero
+      double2 h0 = make_double2(0.0, 0.0), h1 = h0;
+      double ca = 0.0, cb = 0.0;  // 2n - 1 and (n-1)^2 - m^2 for the next degree n
+#pragma unroll
+      for (int ps = 0; ps < P; ++ps) {
+        const P2EPass d = desc[wv * P + ps];
+        uint64_t ml = ((uint64_t)d.mhi << 32) | d.mlo;
+        double2* hw = Hs + lane * LD + wv * K;  // this lane's row, this wave's slots
+        __syncthreads();                        // the previous accumulation is done with Hs
+        // conj(h) obeys the same recurrence (real coefficients): generate it directly
+        int k = 0;
+        while (k < d.nvalid) {
+          if ((d.start >> k) & 1u) {
+            // a column starts: diagonal harmonic of order m by binary powering
+            const int m = (int)(ml & 31u);
+            ml >>= 5;
+            double2 hv = make_double2(dk[m] * sc, 0.0);
+            double2 bp = make_double2(ux, -uy);
+            for (int ex = m; ex; ex >>= 1) {
+              if (ex & 1) hv = zmul(hv, bp);
+              bp = zmul(bp, bp);
+            }
+            h0 = make_double2(0.0, 0.0);
+            h1 = hv;
+            ca = 2.0 * m + 1.0;
+            cb = 0.0;
+            hw[k] = hv;
+            ++k;
+          }
+          const uint32_t rest = k < 32 ? d.start >> k : 0u;
+          const int ke = rest ? min(k + __builtin_ctz(rest), d.nvalid) : d.nvalid;
+          // two steps per trip, each overwriting the older of (h0, h1)
+          for (; k + 1 < ke; k += 2) {
+            double A = ca * zz, Bc = cb * rr;
+            h0 = make_double2(A * h1.x - Bc * h0.x, A * h1.y - Bc * h0.y);
+            cb += ca;
+            ca += 2.0;
+            hw[k] = h0;
+            A = ca * zz;
+            Bc = cb * rr;
+            h1 = make_double2(A * h0.x - Bc * h1.x, A * h0.y - Bc * h1.y);
+            cb += ca;
+            ca += 2.0;
+            hw[k + 1] = h1;
+          }
+          if (k < ke) {
+            const double A = ca * zz, Bc = cb * rr;
+            const double2 hv = make_double2(A * h1.x - Bc * h0.x, A * h1.y - Bc * h0.y);
+            cb += ca;
+            ca += 2.0;
+            h0 = h1;
+            h1 = hv;
+            hw[k] = hv;
+            ++k;
+          }
+        }
+        for (; k < K; ++k) hw[k] = make_double2(0.0, 0.0);
+        __syncthreads();
+        if (sub * BPW < nb) {
+          // beads past nb have zero harmonics; Q is padded past the last bead
+#pragma unroll
+          for (int i = 0; i < BPW; ++i) {
+            const int bb = sub * BPW + i;
+            const double* q = Q + (int64_t)(jc + bb) * ND;
+            const double2 h = Hs[bb * LD + slot];
+#pragma unroll
+            for (int r = 0; r < NRC; ++r) {
+              const double q0 = q[4 * r], q1 = q[4 * r + 1], q2 = q[4 * r + 2];
+              double q3 = q[4 * r + 3];
+              if (LOCAL) q3 = fma(q0, wx, fma(q1, wy, fma(q2, wz, q3)));
+              const double qq[4] = {q0, q1, q2, q3};
+#pragma unroll
+              for (int dd = 0; dd < 4; ++dd) {
+                acc[ps][4 * r + dd].x = fma(qq[dd], h.x, acc[ps][4 * r + dd].x);
+                acc[ps][4 * r + dd].y = fma(qq[dd], h.y, acc[ps][4 * r + dd].y);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // add the NB partial sums per slot and write the expansion
+  constexpr int DG = ND <= LD / 8 ? ND : LD / 8;  // densities per round: NB * S * DG <= 64 * LD
+  static_assert(ND % DG == 0, "density rounds");
+  double2* R = Hs;
+#pragma unroll
+  for (int ps = 0; ps < P; ++ps) {
+#pragma unroll
+    for (int d0 = 0; d0 < ND; d0 += DG) {
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < DG; ++d) R[(sub * DG + d) * S + slot] = acc[ps][d0 + d];
+      __syncthreads();
+      for (int o = threadIdx.x; o < DG * S; o += P2E_THREADS) {
+        const int d = o / S, s = o - d * S;
+        const int c = slot_coef[ps * S + s];
+        if (c < 0) continue;
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const double2 w = R[(k * DG + d) * S + s];
+          v.x += w.x;
+          v.y += w.y;
+        }
+        double2* out = E + ((int64_t)b * ND + d0 + d) * T + c;
+        if (LOCAL) {
+          const double2 o0 = *out;
+          v.x += o0.x;
+          v.y += o0.y;
+        } else {
+          const double f = slot_scale[ps * S + s];  // S_n^m -> R_n^m
+          v.x *= f;
+          v.y *= f;
+        }
+        *out = v;
+      }
+    }
+  }
+}
+
+template <int ND, bool LOCAL, int K, int P>
+hipError_t launch_p2e(const Launch& l, int grid, const int* ids, const double* Q, double2* E) {
+  const Built* B = l.B;
+  const Tables* tb = l.tb;
+  const size_t shm = sizeof(double2) * P2E_CHUNK * (P2E_WAVES * K + 1);
+  auto kern = k_p2e<ND, LOCAL, K, P>;
+  hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (he != hipSuccess) return he;
+  kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q, tb->p2e_desc,
+                                        tb->p2e_slot, tb->p2e_scale, tb->p2e_dk, E);
+  return hipGetLastError();
+}
+
+template <int ND, bool LOCAL>
+hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double* Q, double2* E) {
+  const int K = l.tb->p2e_K, P = l.tb->p2e_P;
+  if (K == 8 && P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, grid, ids, Q, E);
+  if (K == 8 && P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, grid, ids, Q, E);
+  if (K == 8 && P == 3) return launch_p2e<ND, LOCAL, 8, 3>(l, grid, ids, Q, E);
+  if (K == 16 && P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, grid, ids, Q, E);
+  return hipErrorInvalidValue;
+}
+
+template <bool LOCAL>
+hipError_t launch_p2e_nd(const Launch& l, int nrc, int grid, const int* ids, const double* Q, double2* E) {
+  switch (nrc) {
+    case 1: return launch_p2e_kp<4, LOCAL>(l, grid, ids, Q, E);
+    case 2: return launch_p2e_kp<8, LOCAL>(l, grid, ids, Q, E);
+    case 4: return launch_p2e_kp<16, LOCAL>(l, grid, ids, Q, E);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// First-fit decreasing of the columns m = 0..p (lengths p - m + 1) into 8
+// bins of capacity cap.
+bool pack_columns(int p, int cap, std::vector<std::vector<int>>& bins) {
+  bins.assign(P2E_WAVES, {});
+  std::vector<int> load(P2E_WAVES, 0);
+  for (int m = 0; m <= p; ++m) {
+    const int len = p - m + 1;
+    int w = 0;
+    while (w < P2E_WAVES && load[w] + len > cap) ++w;
+    if (w == P2E_WAVES) return false;
+    bins[w].push_back(m);
+    load[w] += len;
+  }
+  return true;
+}
+
+}  // namespace
+
+int make_p2e_tables(int p, Tables* tb, Error* err) {
+  // (K, P) with the fewest slots (P * 8K) whose column packing fits; on a tie
+  // the smaller K (less LDS per block).
+  static const int opts[][2] = {{8, 1}, {8, 2}, {8, 3}, {16, 2}};
+  int K = 0, P = 0;
+  std::vector<std::vector<int>> bins;
+  for (const auto& o : opts) {
+    std::vector<std::vector<int>> bb;
+    if (!pack_columns(p, o[0] * o[1], bb)) continue;
+    if (K == 0 || o[0] * o[1] < K * P) {
+      K = o[0];
+      P = o[1];
+      bins = bb;
+    }
+  }
+  if (K == 0) {
+    err->code = -1;  // invalid argument
+    err->msg = "expansion order too large for the particle-to-expansion schedule";
+    return -1;
+  }
+  const int L = K * P, S = P2E_WAVES * K;
+  std::vector<P2EPass> desc((size_t)P2E_WAVES * P, P2EPass{0u, 0, 0u, 0u});
+  std::vector<int> slot((size_t)P * S, -1);
+  std::vector<double> scale((size_t)P * S, 0.0), fac(2 * p + 2, 1.0);
+  for (int j = 1; j <= 2 * p + 1; ++j) fac[j] = fac[j - 1] * j;
+  for (int w = 0; w < P2E_WAVES; ++w) {
+    int k = 0;
+    std::vector<int> nst(P, 0);
+    for (int m : bins[w])
+      for (int n = m; n <= p; ++n, ++k) {
+        const int ps = k / K, kk = k % K;
+        P2EPass& d = desc[(size_t)w * P + ps];
+        if (n == m) {
+          d.start |= 1u << kk;
+          const uint64_t ml = ((uint64_t)d.mhi << 32 | d.mlo) | ((uint64_t)m << (5 * nst[ps]++));
+          d.mlo = (uint32_t)ml;
+          d.mhi = (uint32_t)(ml >> 32);
+        }
+        d.nvalid = kk + 1;
+        slot[(size_t)ps * S + w * K + kk] = tri(n) + m;
+        scale[(size_t)ps * S + w * K + kk] = 1.0 / (fac[n - m] * fac[n + m]);
+      }
+    for (int ps = 0; ps < P; ++ps)
+      if (nst[ps] > 12) {
+        err->code = -1;
+        err->msg = "particle-to-expansion schedule: too many columns in one pass";
+        return -1;
+      }
+  }
+  // diagonal constants (-1)^m (2m-1)!!
+  std::vector<double> dk(p + 1);
+  double dd = 1.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) dd *= -(2.0 * m - 1.0);
+    dk[m] = dd;
+  }
+  tb->p2e_K = K;
+  tb->p2e_P = P;
+  RPY_HIP(hipMalloc(&tb->p2e_desc, sizeof(P2EPass) * desc.size()));
+  RPY_HIP(hipMalloc(&tb->p2e_slot, sizeof(int) * slot.size()));
+  RPY_HIP(hipMalloc(&tb->p2e_scale, sizeof(double) * scale.size()));
+  RPY_HIP(hipMalloc(&tb->p2e_dk, sizeof(double) * dk.size()));
+  RPY_HIP(hipMemcpy(tb->p2e_desc, desc.data(), sizeof(P2EPass) * desc.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->p2e_slot, slot.data(), sizeof(int) * slot.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->p2e_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(tb->p2e_dk, dk.data(), sizeof(double) * dk.size(), hipMemcpyHostToDevice));
+  tb->bytes += sizeof(P2EPass) * desc.size() + sizeof(int) * slot.size() + sizeof(double) * (scale.size() + dk.size());
+  return 0;
+}
+
+hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e) {
+  const Built* B = l.B;
+  if (B->nleaf == 0) return hipSuccess;
+  switch (nrc) {
+    case 1: k_leaf_q<1><<<B->nleaf, 256, 0, l.s>>>(B->leaf_ids, B->tree, B->sx, B->sy, B->sz, sF, B->n, e.Q); break;
+    case 2: k_leaf_q<2><<<B->nleaf, 256, 0, l.s>>>(B->leaf_ids, B->tree, B->sx, B->sy, B->sz, sF, B->n, e.Q); break;
+    case 4: k_leaf_q<4><<<B->nleaf, 256, 0, l.s>>>(B->leaf_ids, B->tree, B->sx, B->sy, B->sz, sF, B->n, e.Q); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t he = hipGetLastError();
+  if (he != hipSuccess) return he;
+  return launch_p2e_nd<false>(l, nrc, B->nleaf, B->leaf_ids, e.Q, e.M);
+}
+
+hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
+  (void)sF;  // the charges come from the per-bead array written by run_p2m
+  const Built* B = l.B;
+  if (B->lists[LX].len == 0) return hipSuccess;
+  return launch_p2e_nd<true>(l, nrc, B->tree.nbox, nullptr, e.Q, e.L);
+}
+
+}  // namespace rpy
