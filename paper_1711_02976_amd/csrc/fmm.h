@@ -28,6 +28,15 @@ struct P2EPass {
   int32_t nvalid;
   uint32_t mlo, mhi;
 };
+// A schedule with K steps per wave and pass and P passes (P = 0: none): per
+// wave (8) and pass a P2EPass, and per slot (P x 8K) the coefficient it
+// holds (-1: padding) with its factor 1/((n-m)!(n+m)!).
+struct P2ESched {
+  P2EPass* desc;
+  int* slot;
+  double* scale;
+  int K, P;
+};
 
 struct Tables {
   int p;
@@ -46,14 +55,10 @@ struct Tables {
   double* geo;
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
   double* rnm;     // [ncoef(p+2)] 1/((n+m)(n-m)) (0 for n < m+2)
-  // S->M / S->L schedule: per wave (8) and pass (P) a P2EPass, the
-  // coefficient held by each of the 8K slots of each pass (-1: padding) with
-  // its factor 1/((n-m)!(n+m)!), and the diagonal constants (-1)^m (2m-1)!!.
-  P2EPass* p2e_desc;
-  int* p2e_slot;
-  double* p2e_scale;
+  // S->M / S->L schedules (K = 8 and K = 16 steps per wave and pass) and
+  // the diagonal constants (-1)^m (2m-1)!!.
+  P2ESched p2e[2];
   double* p2e_dk;
-  int p2e_K, p2e_P;
   int rot_len;     // sum_n (n+1)^2
   int zt_len;      // sum_l (p-l+1)^2
   int64_t bytes;

@@ -317,15 +317,19 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
 
 void free_tables(Tables* tb) {
   void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rnm,
-                tb->p2e_desc, tb->p2e_slot, tb->p2e_scale, tb->p2e_dk};
+                tb->p2e[0].desc, tb->p2e[0].slot, tb->p2e[0].scale, tb->p2e[1].desc, tb->p2e[1].slot,
+                tb->p2e[1].scale, tb->p2e_dk};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   tb->oct = tb->itab = nullptr;
   tb->rot64 = tb->zt64 = tb->geo = tb->sfac = tb->rnm = nullptr;
   tb->rot32 = tb->zt32 = nullptr;
-  tb->p2e_desc = nullptr;
-  tb->p2e_slot = nullptr;
-  tb->p2e_scale = nullptr;
+  for (P2ESched& s : tb->p2e) {
+    s.desc = nullptr;
+    s.slot = nullptr;
+    s.scale = nullptr;
+    s.P = 0;
+  }
   tb->p2e_dk = nullptr;
 }
 

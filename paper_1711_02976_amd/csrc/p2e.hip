@@ -255,27 +255,40 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
 }
 
 template <int ND, bool LOCAL, int K, int P>
-hipError_t launch_p2e(const Launch& l, int grid, const int* ids, const double* Q, double2* E) {
+hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* ids, const double* Q, double2* E) {
   const Built* B = l.B;
-  const Tables* tb = l.tb;
   const size_t shm = sizeof(double2) * P2E_CHUNK * (P2E_WAVES * K + 1);
   auto kern = k_p2e<ND, LOCAL, K, P>;
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
-  kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q, tb->p2e_desc,
-                                        tb->p2e_slot, tb->p2e_scale, tb->p2e_dk, E);
+  kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q, sc.desc, sc.slot,
+                                        sc.scale, l.tb->p2e_dk, E);
   return hipGetLastError();
 }
 
+// Schedule choice: 8 steps per wave and pass (66 KB of LDS, two blocks per
+// CU) unless the accumulators of 16 densities over more than two passes
+// would not fit in registers; then 16 steps (132 KB, one block per CU).
 template <int ND, bool LOCAL>
 hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double* Q, double2* E) {
-  const int K = l.tb->p2e_K, P = l.tb->p2e_P;
-  if (K == 8 && P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, grid, ids, Q, E);
-  if (K == 8 && P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, grid, ids, Q, E);
-  if (K == 8 && P == 3) return launch_p2e<ND, LOCAL, 8, 3>(l, grid, ids, Q, E);
-  if (K == 16 && P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, grid, ids, Q, E);
-  return hipErrorInvalidValue;
+  const P2ESched& s8 = l.tb->p2e[0];
+  const P2ESched& s16 = l.tb->p2e[1];
+  if constexpr (ND <= 8) {
+    switch (s8.P) {
+      case 1: return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E);
+      case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
+      case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E);
+      case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (s8.P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E);
+    if (s8.P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
+    if (s16.P == 1) return launch_p2e<ND, LOCAL, 16, 1>(l, s16, grid, ids, Q, E);
+    if (s16.P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, s16, grid, ids, Q, E);
+    return hipErrorInvalidValue;
+  }
 }
 
 template <bool LOCAL>
@@ -306,27 +319,17 @@ bool pack_columns(int p, int cap, std::vector<std::vector<int>>& bins) {
 
 }  // namespace
 
-int make_p2e_tables(int p, Tables* tb, Error* err) {
-  // (K, P) with the fewest slots (P * 8K) whose column packing fits; on a tie
-  // the smaller K (less LDS per block).
-  static const int opts[][2] = {{8, 1}, {8, 2}, {8, 3}, {16, 2}};
-  int K = 0, P = 0;
+// Builds the schedule with K steps per wave and pass and the fewest passes
+// (at most maxp) whose column packing fits; false if none does.
+static int build_sched(int p, int K, int maxp, P2ESched* out, Error* err, int64_t* bytes) {
+  out->K = K;
+  out->P = 0;
   std::vector<std::vector<int>> bins;
-  for (const auto& o : opts) {
-    std::vector<std::vector<int>> bb;
-    if (!pack_columns(p, o[0] * o[1], bb)) continue;
-    if (K == 0 || o[0] * o[1] < K * P) {
-      K = o[0];
-      P = o[1];
-      bins = bb;
-    }
-  }
-  if (K == 0) {
-    err->code = -1;  // invalid argument
-    err->msg = "expansion order too large for the particle-to-expansion schedule";
-    return -1;
-  }
-  const int L = K * P, S = P2E_WAVES * K;
+  int P = 0;
+  for (int q = 1; q <= maxp && P == 0; ++q)
+    if (pack_columns(p, K * q, bins)) P = q;
+  if (P == 0) return 0;
+  const int S = P2E_WAVES * K;
   std::vector<P2EPass> desc((size_t)P2E_WAVES * P, P2EPass{0u, 0, 0u, 0u});
   std::vector<int> slot((size_t)P * S, -1);
   std::vector<double> scale((size_t)P * S, 0.0), fac(2 * p + 2, 1.0);
@@ -339,6 +342,11 @@ int make_p2e_tables(int p, Tables* tb, Error* err) {
         const int ps = k / K, kk = k % K;
         P2EPass& d = desc[(size_t)w * P + ps];
         if (n == m) {
+          if (nst[ps] == 12) {
+            err->code = -1;
+            err->msg = "particle-to-expansion schedule: too many columns in one pass";
+            return -1;
+          }
           d.start |= 1u << kk;
           const uint64_t ml = ((uint64_t)d.mhi << 32 | d.mlo) | ((uint64_t)m << (5 * nst[ps]++));
           d.mlo = (uint32_t)ml;
@@ -348,12 +356,28 @@ int make_p2e_tables(int p, Tables* tb, Error* err) {
         slot[(size_t)ps * S + w * K + kk] = tri(n) + m;
         scale[(size_t)ps * S + w * K + kk] = 1.0 / (fac[n - m] * fac[n + m]);
       }
-    for (int ps = 0; ps < P; ++ps)
-      if (nst[ps] > 12) {
-        err->code = -1;
-        err->msg = "particle-to-expansion schedule: too many columns in one pass";
-        return -1;
-      }
+  }
+  RPY_HIP(hipMalloc(&out->desc, sizeof(P2EPass) * desc.size()));
+  RPY_HIP(hipMalloc(&out->slot, sizeof(int) * slot.size()));
+  RPY_HIP(hipMalloc(&out->scale, sizeof(double) * scale.size()));
+  RPY_HIP(hipMemcpy(out->desc, desc.data(), sizeof(P2EPass) * desc.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(out->slot, slot.data(), sizeof(int) * slot.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(out->scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice));
+  *bytes += sizeof(P2EPass) * desc.size() + (sizeof(int) + sizeof(double)) * slot.size();
+  out->P = P;
+  return 1;
+}
+
+int make_p2e_tables(int p, Tables* tb, Error* err) {
+  int64_t bytes = 0;
+  const int r8 = build_sched(p, 8, 4, &tb->p2e[0], err, &bytes);
+  if (r8 < 0) return -1;
+  const int r16 = build_sched(p, 16, 2, &tb->p2e[1], err, &bytes);
+  if (r16 < 0) return -1;
+  if (r8 == 0 && r16 == 0) {
+    err->code = -1;  // invalid argument
+    err->msg = "expansion order too large for the particle-to-expansion schedule";
+    return -1;
   }
   // diagonal constants (-1)^m (2m-1)!!
   std::vector<double> dk(p + 1);
@@ -362,17 +386,9 @@ int make_p2e_tables(int p, Tables* tb, Error* err) {
     if (m > 0) dd *= -(2.0 * m - 1.0);
     dk[m] = dd;
   }
-  tb->p2e_K = K;
-  tb->p2e_P = P;
-  RPY_HIP(hipMalloc(&tb->p2e_desc, sizeof(P2EPass) * desc.size()));
-  RPY_HIP(hipMalloc(&tb->p2e_slot, sizeof(int) * slot.size()));
-  RPY_HIP(hipMalloc(&tb->p2e_scale, sizeof(double) * scale.size()));
   RPY_HIP(hipMalloc(&tb->p2e_dk, sizeof(double) * dk.size()));
-  RPY_HIP(hipMemcpy(tb->p2e_desc, desc.data(), sizeof(P2EPass) * desc.size(), hipMemcpyHostToDevice));
-  RPY_HIP(hipMemcpy(tb->p2e_slot, slot.data(), sizeof(int) * slot.size(), hipMemcpyHostToDevice));
-  RPY_HIP(hipMemcpy(tb->p2e_scale, scale.data(), sizeof(double) * scale.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->p2e_dk, dk.data(), sizeof(double) * dk.size(), hipMemcpyHostToDevice));
-  tb->bytes += sizeof(P2EPass) * desc.size() + sizeof(int) * slot.size() + sizeof(double) * (scale.size() + dk.size());
+  tb->bytes += bytes + sizeof(double) * dk.size();
   return 0;
 }
 
