@@ -117,6 +117,7 @@ struct rpy_plan_s {
   rpy::Built B;
   rpy::Tables tb{};
   rpy::Tiles tiles{};
+  rpy::EvalPlan ep{};
   int p = 0, leaf_size = 0, max_depth = 14, precision = 0, m2l_mode = 2;
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
@@ -135,6 +136,8 @@ struct rpy_plan_s {
   double* u = nullptr;   // near-field velocities, tree order
   double* uf = nullptr;  // far-field velocities, tree order
   double* Q = nullptr;   // per-bead charges for S->M / S->L, tree order
+  double2* DL = nullptr;  // evaluation sets (local expansions of the leaves)
+  double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
   int64_t ws_bytes = 0;
   double plan_ms = 0;
   // per-phase timing
@@ -179,10 +182,10 @@ static void fold_events(rpy_plan_t* P) {
 }
 
 static void free_ws(rpy_plan_t* P) {
-  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q};
+  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q, P->DL, P->DW};
   for (void* p : ps)
     if (p) (void)hipFree(p);
-  P->M = P->L = nullptr;
+  P->M = P->L = P->DL = P->DW = nullptr;
   P->sF = P->u = P->uf = P->Q = nullptr;
   P->ws_nrc = 0;
   P->ws_bytes = 0;
@@ -198,15 +201,18 @@ static int alloc_ws(rpy_plan_t* P, int nrc) {
   // Q: per-bead charges plus 64 rows that the S->M/S->L kernels may read past
   // the last bead (with zero weight); zeroed once so every row is finite
   size_t vb = sizeof(double) * 3 * nrc * n, qb = sizeof(double) * 4 * nrc * (n + 64);
+  int64_t dwb = 0;
+  const size_t dlb = (size_t)rpy::eval_sets_bytes(&P->B, P->ep, P->p, nrc, &dwb);
   if (hipMalloc(&P->M, ex) != hipSuccess || hipMalloc(&P->L, ex) != hipSuccess ||
       hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess ||
       hipMalloc(&P->uf, vb) != hipSuccess || hipMalloc(&P->Q, qb) != hipSuccess ||
-      hipMemset(P->Q, 0, qb) != hipSuccess) {
+      hipMemset(P->Q, 0, qb) != hipSuccess || hipMalloc(&P->DL, dlb) != hipSuccess ||
+      hipMalloc(&P->DW, (size_t)dwb) != hipSuccess) {
     free_ws(P);
     return -1;
   }
   P->ws_nrc = nrc;
-  P->ws_bytes = 2 * ex + 3 * vb + qb;
+  P->ws_bytes = 2 * ex + 3 * vb + qb + dlb + dwb;
   return 0;
 }
 
@@ -337,6 +343,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
+  if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, &P->ep, P->stream, &err);
   if (rc == 0) {
     // default priority (no priority argument); without it the near field
     // runs on the plan's stream
@@ -384,7 +391,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream};
-  rpy::Exp e{P->M, P->L, P->Q};
+  rpy::Exp e{P->M, P->L, P->Q, P->DL, P->DW};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
     int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
@@ -416,7 +423,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     });
     if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, c, e, P->uf); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
     // join, then near + far back to caller order
     if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
     if (he == hipSuccess) he = timed(P, RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
@@ -523,6 +530,7 @@ void rpy_plan_free(rpy_plan_t* P) {
   rpy::free_tables(&P->tb);
   if (P->tiles.t) (void)hipFree(P->tiles.t);
   if (P->tiles.box) (void)hipFree(P->tiles.box);
+  rpy::free_eval_plan(&P->ep);
   rpy::free_built(&P->B);
   delete P;
 }

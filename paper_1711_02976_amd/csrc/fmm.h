@@ -18,6 +18,8 @@ struct Exp {
   double2* M;
   double2* L;
   double* Q;  // per-bead charges [n][4 nrc] for S->M and S->L (written by run_p2m)
+  double2* DL;  // evaluation sets of the leaves' local expansions (eval.hip)
+  double2* DW;  // evaluation sets of the W-list multipoles that are evaluated
 };
 
 // Per wave and pass of the S->M / S->L kernels (p2e.hip): bit k of `start`
@@ -54,7 +56,7 @@ struct Tables {
   float* zt32;
   double* geo;
   double* sfac;    // [ncoef(p)] sqrt((n-m)!(n+m)!)
-  double* rnm;     // [ncoef(p+2)] 1/((n+m)(n-m)) (0 for n < m+2)
+  double* rscale;  // [ncoef(p)] 1/((n-m)!(n+m)!)
   // S->M / S->L schedules (K = 8 and K = 16 steps per wave and pass) and
   // the diagonal constants (-1)^m (2m-1)!!.
   P2ESched p2e[2];
@@ -93,8 +95,6 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e);       // dense O(p^4)
 hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32);  // rotation, O(p^3)
 hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_l2l(const Launch& l, int nrc, Exp e);
-// Writes the far-field velocities of every bead (assigns; sorted SoA).
-hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u);
 
 // Near field.  `tiles` lists (leaf, first bead, count) work items.
 struct Tiles {
@@ -112,5 +112,23 @@ hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const doubl
 // direct route a few tens of operations per source bead.
 __host__ __device__ constexpr int wdirect_max(int p) { return (p + 1) * (p + 2); }
 hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
+
+// Target evaluation (eval.hip).  tiles: up to 64 beads of one leaf each
+// (.w = leaf ordinal); widx[box] = row of the box's evaluation sets among
+// the nwbig W-list multipoles that are evaluated (wbig lists those boxes),
+// -1 for the others.
+struct EvalPlan {
+  Tiles tiles{};
+  int* widx = nullptr;
+  int* wbig = nullptr;
+  int nwbig = 0;
+};
+int make_eval_plan(const Built* B, int p, EvalPlan* out, hipStream_t s, Error* err);
+void free_eval_plan(EvalPlan* ep);
+// Bytes of the evaluation-set arrays for nrc right-hand sides: returns the
+// leaves' (Exp::DL), stores the W multipoles' (Exp::DW) in *dw_bytes.
+int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int64_t* dw_bytes);
+// Writes the far-field velocities of every bead (assigns; sorted SoA).
+hipError_t run_eval(const Launch& l, const EvalPlan& ep, int nrc, Exp e, double* u);
 
 }  // namespace rpy

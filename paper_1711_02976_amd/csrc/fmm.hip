@@ -46,6 +46,7 @@ __device__ inline double2 getc(const double2* C, int n, int m, int nmax) {
 }
 
 
+
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 // ------------------------------------------------------------ host tables --
@@ -244,10 +245,6 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
         rot[off + mp * K + j++] = D[(size_t)(mp + n) * W + (m + n)] - D[(size_t)(mp + n) * W + (n - m)];
     }
   }
-  // 1/((n+m)(n-m)) for the regular-harmonic recurrence, degrees <= p + 2
-  std::vector<double> rnm(ncoef(p + 2), 0.0);
-  for (int n = 0; n <= p + 2; ++n)
-    for (int m = 0; m + 2 <= n; ++m) rnm[tri(n) + m] = 1.0 / ((double)(n + m) * (n - m));
   std::vector<double> sf(ncoef(p));
   for (int n = 0; n <= p; ++n)
     for (int m = 0; m <= n; ++m) {
@@ -299,10 +296,13 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   RPY_HIP(hipMalloc(&tb->zt32, sizeof(float) * zt32.size()));
   RPY_HIP(hipMalloc(&tb->geo, sizeof(double) * geo.size()));
   RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
-  RPY_HIP(hipMalloc(&tb->rnm, sizeof(double) * rnm.size()));
-  RPY_HIP(hipMemcpy(tb->rnm, rnm.data(), sizeof(double) * rnm.size(), hipMemcpyHostToDevice));
+  std::vector<double> rsc(ncoef(p));
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) rsc[tri(n) + m] = 1.0 / (sf[tri(n) + m] * sf[tri(n) + m]);
+  RPY_HIP(hipMalloc(&tb->rscale, sizeof(double) * rsc.size()));
+  RPY_HIP(hipMemcpy(tb->rscale, rsc.data(), sizeof(double) * rsc.size(), hipMemcpyHostToDevice));
   tb->bytes = sizeof(double2) * (oct.size() + itab.size()) + (sizeof(double) + sizeof(float)) * (rot.size() + zt.size()) +
-              sizeof(double) * (geo.size() + sf.size() + rnm.size());
+              sizeof(double) * (geo.size() + sf.size() + rsc.size());
   RPY_HIP(hipMemcpy(tb->oct, oct.data(), sizeof(double2) * oct.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->itab, itab.data(), sizeof(double2) * itab.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(tb->rot64, rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice));
@@ -316,13 +316,13 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
 }
 
 void free_tables(Tables* tb) {
-  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rnm,
+  void* ps[] = {tb->oct, tb->itab, tb->rot64, tb->rot32, tb->zt64, tb->zt32, tb->geo, tb->sfac, tb->rscale,
                 tb->p2e[0].desc, tb->p2e[0].slot, tb->p2e[0].scale, tb->p2e[1].desc, tb->p2e[1].slot,
                 tb->p2e[1].scale, tb->p2e_dk};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   tb->oct = tb->itab = nullptr;
-  tb->rot64 = tb->zt64 = tb->geo = tb->sfac = tb->rnm = nullptr;
+  tb->rot64 = tb->zt64 = tb->geo = tb->sfac = tb->rscale = nullptr;
   tb->rot32 = tb->zt32 = nullptr;
   for (P2ESched& s : tb->p2e) {
     s.desc = nullptr;
@@ -542,224 +542,6 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, cons
   }
 }
 
-// --------------------------------------------------------- evaluation -----
-// One block per leaf.  For every right-hand side the box's local expansion
-// (and then each W-list multipole, re-centred on this machine) is turned into
-// twelve real-symmetric derived coefficient sets in LDS:
-//   E_i  = C1 L_i + C1 d_i L4 - C2 d_i (d_x L1 + d_y L2 + d_z L3)
-//   G_ik = d_i L_k                                   (i, k in x, y, z)
-// so that eq. (2.8) at a target x reads u_i = E_i(x) - C1 sum_k (x-c)_k G_ik(x);
-// each target then sums the twelve sets against its own harmonics.
-
-// Derivative of a real-symmetric set in coefficient space.  Local (regular)
-// sets: d_z C -> C_{n+1}^m, d_x -> (C_{n+1}^{m-1} - C_{n+1}^{m+1})/2,
-// d_y -> -i (C_{n+1}^{m-1} + C_{n+1}^{m+1})/2.  Multipole (irregular) sets use
-// n-1 in place of n+1 and d_z -> -C_{n-1}^m.
-__device__ inline double2 dcoef(const double2* C, int nmax, int n, int m, int axis, bool mult) {
-  int nn = mult ? n - 1 : n + 1;
-  if (axis == 2) {
-    double2 v = getc(C, nn, m, nmax);
-    return mult ? make_double2(-v.x, -v.y) : v;
-  }
-  double2 a = getc(C, nn, m - 1, nmax), b = getc(C, nn, m + 1, nmax);
-  if (axis == 0) return make_double2(0.5 * (a.x - b.x), 0.5 * (a.y - b.y));
-  return make_double2(0.5 * (a.y + b.y), -0.5 * (a.x + b.x));
-}
-
-// Build the 12 derived sets (E_x,E_y,E_z,G_xx,G_xy,G_xz,G_yx,...) of degree
-// <= nout from the four sets in src (degree <= nin).  scale = 1/h.
-// Builds the 12 evaluation sets of one expansion in LDS:
-//   D[3 + 3i + k] = h^-2 d_i L_k          (k, i = 0..2),
-//   D[i]          = C1 h^-1 L_i + C1 h^-2 d_i L_4 - C2 h^-3 d_i L_C,
-// with L_C = sum_k d_k L_k, so that at a target x (offset v from the centre)
-//   u_i = Re sum_c [D_i - C1 sum_k v_k D_{3+3i+k}]_c h_c(x/h)
-// (eq. 2.8 with Theorem 2, or Theorem 1 for a multipole: mult = true, sets
-// of degree nin + 2).  G4 (3 sets) and LC are scratch.
-__device__ void derived_sets(const double2* src, int nin, int nout, bool mult, double h, double C1, double C2,
-                             double2* D, double2* G4, double2* LC) {
-  const int To = ncoef(nout);
-  const double ih = 1.0 / h, ih2 = ih * ih, ih3 = ih2 * ih;
-  for (int w = threadIdx.x; w < 12 * To; w += blockDim.x) {
-    const int k = w / (3 * To), rem = w - k * 3 * To, i = rem / To, c = rem - i * To;
-    int n = 0;
-    while (tri(n + 1) <= c) ++n;
-    const int m = c - tri(n);
-    const double2 g = dcoef(src + k * ncoef(nin), nin, n, m, i, mult);
-    if (k < 3) D[(3 + 3 * i + k) * To + c] = make_double2(ih2 * g.x, ih2 * g.y);
-    else G4[i * To + c] = g;
-  }
-  __syncthreads();
-  const double h2 = h * h;
-  for (int c = threadIdx.x; c < To; c += blockDim.x) {
-    const double2 a = D[3 * To + c], b = D[7 * To + c], d = D[11 * To + c];
-    LC[c] = make_double2(h2 * (a.x + b.x + d.x), h2 * (a.y + b.y + d.y));
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < 3 * To; w += blockDim.x) {
-    const int i = w / To, c = w - i * To;
-    int n = 0;
-    while (tri(n + 1) <= c) ++n;
-    const int m = c - tri(n);
-    const double2 l = getc(src + i * ncoef(nin), n, m, nin);
-    const double2 g4 = G4[i * To + c];
-    const double2 dc = dcoef(LC, nout, n, m, i, mult);
-    D[i * To + c] = make_double2(C1 * ih * l.x + C1 * ih2 * g4.x - C2 * ih3 * dc.x,
-                                 C1 * ih * l.y + C1 * ih2 * g4.y - C2 * ih3 * dc.y);
-  }
-  __syncthreads();
-}
-
-// Evaluates the 12 sets at BPT targets per thread (x, y, z in box units, v
-// the offset in absolute units) and adds u.  Regular harmonics R_n^m
-// (local expansion) or irregular I_n^m (multipole, MULT) by recurrence in m
-// and then n; each set coefficient read from LDS serves all BPT targets.
-// rnm[tri(n)+m] = 1/((n+m)(n-m)).
-template <bool MULT, int BPT>
-__device__ inline void apply_sets(const double2* D, int nmax, const double* __restrict__ rnm, const double* x,
-                                  const double* y, const double* z, const double (*v)[3], double C1, double (*u)[3]) {
-  const int To = ncoef(nmax);
-  double s[BPT][12];
-  double r2[BPT], ir2[BPT];
-  double2 hmm[BPT];
-#pragma unroll
-  for (int q = 0; q < BPT; ++q) {
-#pragma unroll
-    for (int e = 0; e < 12; ++e) s[q][e] = 0.0;
-    r2[q] = x[q] * x[q] + y[q] * y[q] + z[q] * z[q];
-    ir2[q] = MULT ? 1.0 / r2[q] : 0.0;
-    hmm[q] = make_double2(MULT ? sqrt(ir2[q]) : 1.0, 0.0);
-  }
-  for (int m = 0; m <= nmax; ++m) {
-    const double wm = m ? 2.0 : 1.0;
-    double2 h1[BPT], h2[BPT];
-#pragma unroll
-    for (int q = 0; q < BPT; ++q) {
-      if (m > 0) {
-        const double f = MULT ? -(2 * m - 1) * ir2[q] : -0.5 / m;
-        hmm[q] = make_double2(f * (x[q] * hmm[q].x - y[q] * hmm[q].y), f * (x[q] * hmm[q].y + y[q] * hmm[q].x));
-      }
-      h1[q] = make_double2(0, 0);
-      h2[q] = make_double2(0, 0);
-    }
-    for (int n = m; n <= nmax; ++n) {
-      const int c = tri(n) + m;
-      const double inv = rnm[c];
-      double hx[BPT], hy[BPT];
-#pragma unroll
-      for (int q = 0; q < BPT; ++q) {
-        double2 hv;
-        if (n == m) {
-          hv = hmm[q];
-        } else if (n == m + 1) {
-          const double f = MULT ? (2 * m + 1) * z[q] * ir2[q] : z[q];
-          hv = make_double2(f * hmm[q].x, f * hmm[q].y);
-        } else if (MULT) {
-          const double a = (2 * n - 1) * z[q] * ir2[q], bb = (double)(n + m - 1) * (n - m - 1) * ir2[q];
-          hv = make_double2(a * h1[q].x - bb * h2[q].x, a * h1[q].y - bb * h2[q].y);
-        } else {
-          const double a = (2 * n - 1) * z[q] * inv, bb = r2[q] * inv;
-          hv = make_double2(a * h1[q].x - bb * h2[q].x, a * h1[q].y - bb * h2[q].y);
-        }
-        h2[q] = h1[q];
-        h1[q] = hv;
-        hx[q] = wm * hv.x;
-        hy[q] = wm * hv.y;
-      }
-#pragma unroll
-      for (int e = 0; e < 12; ++e) {
-        const double2 d = D[e * To + c];
-#pragma unroll
-        for (int q = 0; q < BPT; ++q) s[q][e] = fma(d.x, hx[q], fma(-d.y, hy[q], s[q][e]));
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < BPT; ++q)
-    for (int i = 0; i < 3; ++i) {
-      double t = s[q][i];
-      for (int k = 0; k < 3; ++k) t -= C1 * v[q][k] * s[q][3 + 3 * i + k];
-      u[q][i] += t;
-    }
-}
-
-// Target evaluation, one block per leaf: the leaf's local expansion (and each
-// W-list multipole, Theorem 1) is turned into the 12 sets of eq. (2.8) in
-// LDS, then every thread evaluates them at EVB beads.
-constexpr int EVB = 2;
-
-template <int NRC, int NT>
-__global__ void __launch_bounds__(NT) k_eval(int p, int pw, const int* leaves, Tree t, List W, const double* sx,
-                                               const double* sy, const double* sz, int64_t n,
-                                               const double2* M, const double2* L, const double* __restrict__ rnm,
-                                               double C1, double C2, double* u) {
-  constexpr int ND = 4 * NRC;
-  const int b = leaves[blockIdx.x];
-  const int T = ncoef(p), To = ncoef(pw);
-  extern __shared__ double2 sm[];
-  double2* D = sm;                 // 12 * To
-  double2* G4 = D + 12 * To;       // 3 * To
-  double2* LC = G4 + 3 * To;       // To
-  double2* src = LC + To;          // 4 * T
-  const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], h = t.h[b];
-  const int j0 = t.begin[b], j1 = t.end[b];
-  const int w0 = W.off[b], w1 = W.off[b + 1];
-  for (int r = 0; r < NRC; ++r) {
-    for (int e = w0 - 1; e < w1; ++e) {
-      // e = w0 - 1: this leaf's local expansion; then its W-list multipoles
-      // (boxes with few beads are summed directly by the near-field pass)
-      const bool mult = e >= w0;
-      const int C = mult ? W.ent[e] : b;
-      if (mult && t.end[C] - t.begin[C] <= wdirect_max(p)) continue;
-      const double hc = t.h[C], ccx = t.cx[C], ccy = t.cy[C], ccz = t.cz[C];
-      const double wx = ccx - cx, wy = ccy - cy, wz = ccz - cz;
-      __syncthreads();
-      for (int i = threadIdx.x; i < 4 * T; i += NT) {
-        const int d = i / T, c = i - d * T;
-        const double2* E = mult ? M : L;
-        double2 v = E[(int64_t)C * ND * T + (4 * r + d) * T + c];
-        if (mult && d == 3) {
-          // re-centre the fourth density from the W box on this leaf
-          const double w[3] = {wx, wy, wz};
-          for (int k = 0; k < 3; ++k) {
-            const double2 q = M[(int64_t)C * ND * T + (4 * r + k) * T + c];
-            v.x += w[k] * q.x;
-            v.y += w[k] * q.y;
-          }
-        }
-        src[i] = v;
-      }
-      __syncthreads();
-      derived_sets(src, p, mult ? p + 2 : p, mult, hc, C1, C2, D, G4, LC);
-      for (int jb = j0; jb < j1; jb += NT * EVB) {
-        double x[EVB], y[EVB], z[EVB], v[EVB][3], uu[EVB][3];
-#pragma unroll
-        for (int q = 0; q < EVB; ++q) {
-          int j = jb + threadIdx.x + q * NT;
-          if (j >= j1) j = j0;  // idle slot: a valid bead, result not stored
-          v[q][0] = sx[j] - cx;
-          v[q][1] = sy[j] - cy;
-          v[q][2] = sz[j] - cz;
-          x[q] = (sx[j] - ccx) / hc;
-          y[q] = (sy[j] - ccy) / hc;
-          z[q] = (sz[j] - ccz) / hc;
-          uu[q][0] = uu[q][1] = uu[q][2] = 0.0;
-        }
-        if (mult) apply_sets<true, EVB>(D, p + 2, rnm, x, y, z, v, C1, uu);
-        else apply_sets<false, EVB>(D, p, rnm, x, y, z, v, C1, uu);
-#pragma unroll
-        for (int q = 0; q < EVB; ++q) {
-          const int j = jb + threadIdx.x + q * NT;
-          if (j < j1)
-            for (int k = 0; k < 3; ++k) {
-              double* o = u + ((int64_t)r * 3 + k) * n + j;
-              *o = mult ? *o + uu[q][k] : uu[q][k];  // the leaf's own expansion comes first and assigns
-            }
-        }
-      }
-    }
-  }
-}
-
 #define DISPATCH_ND(nrc, KERNEL_CALL)                      \
   switch (nrc) {                                           \
     case 1: { constexpr int ND = 4; KERNEL_CALL; break; }  \
@@ -801,32 +583,5 @@ hipError_t run_l2l(const Launch& l, int nrc, Exp e) {
   return hipSuccess;
 }
 
-hipError_t run_eval(const Launch& l, int nrc, Exp e, double* u) {
-  const Built* B = l.B;
-  if (B->nleaf == 0) return hipSuccess;
-  const int p = l.p;
-  const int pw = B->lists[LW].len > 0 ? p + 2 : p;
-  const double C1 = 1.0 / (8.0 * PI * l.eta), C2 = l.a * l.a / (12.0 * PI * l.eta);
-  const size_t shm = sizeof(double2) * (16 * ncoef(pw) + 4 * ncoef(p));
-  // 128 threads per leaf; 256 when W-list multipoles (degree p + 2 sets, one
-  // block per CU) are evaluated
-#define EVAL_CASE(NR)                                                                                            \
-  case NR:                                                                                                       \
-    if (pw > p)                                                                                                  \
-      k_eval<NR, 256><<<B->nleaf, 256, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy,    \
-                                                    B->sz, B->n, e.M, e.L, l.tb->rnm, C1, C2, u);              \
-    else                                                                                                         \
-      k_eval<NR, 128><<<B->nleaf, 128, shm, l.s>>>(p, pw, B->leaf_ids, B->tree, B->lists[LW], B->sx, B->sy,    \
-                                                    B->sz, B->n, e.M, e.L, l.tb->rnm, C1, C2, u);              \
-    break;
-  switch (nrc) {
-    EVAL_CASE(1)
-    EVAL_CASE(2)
-    EVAL_CASE(4)
-    default: return hipErrorInvalidValue;
-  }
-#undef EVAL_CASE
-  return hipGetLastError();
-}
 
 }  // namespace rpy

@@ -36,7 +36,7 @@ __global__ void k_tile_fill(const int* leaves, int nleaf, Tree t, int tile, cons
   if (i >= nleaf) return;
   int b = leaves[i];
   int o = off[i];
-  for (int s = t.begin[b]; s < t.end[b]; s += tile) out[o++] = make_int4(b, s, min(tile, t.end[b] - s), 0);
+  for (int s = t.begin[b]; s < t.end[b]; s += tile) out[o++] = make_int4(b, s, min(tile, t.end[b] - s), i);
 }
 
 // Bounding box of each tile's beads: lo xyz, hi xyz.
