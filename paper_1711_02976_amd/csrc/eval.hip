@@ -211,7 +211,7 @@ template <int NRC>
 __global__ void __launch_bounds__(64) k_eval_apply(int p, const int4* tiles, Tree t, List W, const int* widx,
                                                    const double* sx, const double* sy, const double* sz, int64_t n,
                                                    const double2* __restrict__ DL, const double2* __restrict__ DW,
-                                                   double C1, double* u) {
+                                                   double C1, double* __restrict__ u) {
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x, lane = threadIdx.x;
   const int j = tl.y + min(lane, tl.z - 1);
@@ -219,20 +219,25 @@ __global__ void __launch_bounds__(64) k_eval_apply(int p, const int4* tiles, Tre
   const int T = ncoef(p), To = ncoef(p + 2);
   const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], h = t.h[b];
   const int w0 = W.off[b], w1 = W.off[b + 1];
+  // all loads before the first store, so that the set arrays can be read
+  // through the scalar cache
+  double vel[NRC][3];
   for (int r = 0; r < NRC; ++r) {
-    double vel[3] = {0.0, 0.0, 0.0};
-    eval_sets<false>(DL + ((int64_t)tl.w * NRC + r) * T * 12, p, px - cx, py - cy, pz - cz, h, C1, vel);
+    vel[r][0] = vel[r][1] = vel[r][2] = 0.0;
+    eval_sets<false>(DL + ((int64_t)tl.w * NRC + r) * T * 12, p, px - cx, py - cy, pz - cz, h, C1, vel[r]);
     for (int e = w0; e < w1; ++e) {
       const int C = W.ent[e];
       const int wi = widx[C];
       if (wi < 0) continue;  // few beads: summed directly with the near field
       eval_sets<true>(DW + ((int64_t)wi * NRC + r) * To * 12, p + 2, px - t.cx[C], py - t.cy[C], pz - t.cz[C],
-                      t.h[C], C1, vel);
+                      t.h[C], C1, vel[r]);
     }
-    if (lane < tl.z)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + tl.y + lane] = vel[k];
   }
+  if (lane < tl.z)
+#pragma unroll
+    for (int r = 0; r < NRC; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + tl.y + lane] = vel[r][k];
 }
 
 // W-list boxes whose multipoles the evaluation uses: flag[C] = 1 for every
