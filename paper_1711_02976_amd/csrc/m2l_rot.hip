@@ -16,8 +16,8 @@
 //   H_l[k][n] = (-1)^{n+l} (n+k)! / (s_k^l s_n^l),  s_n^m = sqrt((n-m)!(n+m)!).
 //
 // GPU organisation.  One block of RW waves per target box; its V-list
-// (source, density) pairs are the columns, taken NC (64, or 32 when LDS is
-// short) at a time into an LDS array X[coefficient][column].  Each batch
+// (source, density) pairs are the columns, taken NC (64; 60 or 32 when LDS
+// is short) at a time into an LDS array X[coefficient][column].  Each batch
 // runs four phases separated by barriers:
 //   0. all threads gather the columns' multipoles into X;
 //   1. per degree n: Phi(pi/2-phi), R, Phi(-theta), S R S;
@@ -61,9 +61,6 @@ struct ColData {
   double* e2x;   // e^{i theta}
   double* e2y;
   double* rinv;  // 1/rho (box units)
-  double* wx;    // source centre - target centre (re-centres the fourth density)
-  double* wy;
-  double* wz;
 };
 
 __host__ __device__ constexpr int rot_block(int n) { return n * (n + 1) * (2 * n + 1) / 6; }  // sum_{j<n} (j+1)^2
@@ -218,13 +215,19 @@ __device__ void second_half(int c, int ld, const ColData& cd, const R* __restric
   rot_apply<N, true, SG, -SG, R>(A, xr, xi, cd.e1x[c], -cd.e1y[c], col, ld);
 }
 
+// Degree (order) cases compiled into a kernel: 0..16, plus 17..21 when the
+// kernel is built for PM = 21.
 #define RPY_DEG_CASES(X) \
-  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) X(21)
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+#define RPY_DEG_CASES_HI(X) X(17) X(18) X(19) X(20) X(21)
 
 }  // namespace
 
-template <int ND, class R>
-__global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, RotSched sched,
+// PM: highest degree compiled in (16 or 21).  MINW: waves per SIMD the
+// register allocation must allow (4 lets two blocks share a CU when their
+// LDS fits).
+template <int ND, class R, int PM, int MINW>
+__global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, List V, RotSched sched,
                                                 const R* __restrict__ rot, const R* __restrict__ zt, int rot_len,
                                                 const double* __restrict__ geo, const double* __restrict__ sf,
                                                 const double2* __restrict__ M, double2* __restrict__ L) {
@@ -251,9 +254,6 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
     cd.e2x = dq; dq += nc;
     cd.e2y = dq; dq += nc;
     cd.rinv = dq; dq += nc;
-    cd.wx = dq; dq += nc;
-    cd.wy = dq; dq += nc;
-    cd.wz = dq; dq += nc;
     cd.src = reinterpret_cast<int*>(dq);
   }
   double2 acc[NACC];
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
     if (tid < nc) {
       const int g = c0 + tid;
       int S = -1;
-      double q0 = 1.0, q1 = 0.0, q2 = 1.0, q3 = 0.0, q4 = 0.5, w0 = 0.0, w1 = 0.0, w2 = 0.0;
+      double q0 = 1.0, q1 = 0.0, q2 = 1.0, q3 = 0.0, q4 = 0.5;
       if (g < ncols) {
         S = V.ent[e0 + g / ND];
         const int o = (t.ax[S] - bx + 3) * 49 + (t.ay[S] - by + 3) * 7 + (t.az[S] - bz + 3);
@@ -279,9 +279,6 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
         q2 = gq[2];
         q3 = gq[3];
         q4 = gq[4];
-        w0 = t.cx[S] - cbx;
-        w1 = t.cy[S] - cby;
-        w2 = t.cz[S] - cbz;
       }
       cd.src[tid] = S;
       cd.e1x[tid] = q0;
@@ -289,9 +286,6 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
       cd.e2x[tid] = q2;
       cd.e2y[tid] = q3;
       cd.rinv[tid] = q4;
-      cd.wx[tid] = w0;
-      cd.wy[tid] = w1;
-      cd.wz[tid] = w2;
     }
     __syncthreads();
     // phase 0: gather the batch's multipoles (coefficient-contiguous reads),
@@ -310,7 +304,7 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
           double2 v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = src[k * T];
-          const double w0 = cd.wx[c], w1 = cd.wy[c], w2 = cd.wz[c];
+          const double w0 = t.cx[S] - cbx, w1 = t.cy[S] - cby, w2 = t.cz[S] - cbz;
           v[3].x += w0 * v[0].x + w1 * v[1].x + w2 * v[2].x;
           v[3].y += w0 * v[0].y + w1 * v[1].y + w2 * v[2].y;
           const double s = sf[f];
@@ -335,8 +329,9 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
         const R* A = rot + rot_block(n);
         switch (n) {
 #define RPY_P1(k) \
-  case k: first_half<k, R>(lane, ld, cd, A, X); break;
+  case k: if (k <= PM) first_half<(k <= PM ? k : 0), R>(lane, ld, cd, A, X); break;
           RPY_DEG_CASES(RPY_P1)
+          RPY_DEG_CASES_HI(RPY_P1)
 #undef RPY_P1
           default: break;
         }
@@ -352,8 +347,9 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
         const int zo = (p + 1) * (p + 2) * (2 * p + 3) / 6 - kk * (kk + 1) * (2 * kk + 1) / 6;
         switch (kk) {
 #define RPY_P2(k) \
-  case k + 1: ztrans<k + 1, R>(l, lane, ld, cd, zt + zo, X); break;
+  case k + 1: if (k <= PM) ztrans<(k <= PM ? k : 0) + 1, R>(l, lane, ld, cd, zt + zo, X); break;
           RPY_DEG_CASES(RPY_P2)
+          RPY_DEG_CASES_HI(RPY_P2)
 #undef RPY_P2
           default: break;
         }
@@ -367,8 +363,9 @@ __global__ void __launch_bounds__(RT) k_m2l_rot(int p, int nc, Tree t, List V, R
         const R* A = rot + rot_block(n);
         switch (n) {
 #define RPY_P3(k) \
-  case k: second_half<k, R>(lane, ld, cd, A, X); break;
+  case k: if (k <= PM) second_half<(k <= PM ? k : 0), R>(lane, ld, cd, A, X); break;
           RPY_DEG_CASES(RPY_P3)
+          RPY_DEG_CASES_HI(RPY_P3)
 #undef RPY_P3
           default: break;
         }
@@ -428,14 +425,14 @@ static RotSched make_sched(int p) {
 }
 
 static size_t rot_smem_bytes(int p, int nc, size_t real) {
-  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * sizeof(double) + sizeof(int));
+  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (5 * sizeof(double) + sizeof(int));
 }
 
-template <class R, int ND>
+template <class R, int ND, int PM, int MINW>
 static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const RotSched& sc, const R* rot,
                             const R* zt) {
   const Built* B = l.B;
-  auto kern = k_m2l_rot<ND, R>;
+  auto kern = k_m2l_rot<ND, R, PM, MINW>;
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
@@ -449,16 +446,25 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   const int p = l.p;
   if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
   if (l.B->tree.nbox == 0) return hipSuccess;
-  // 64 columns per batch, 32 when the LDS (160 KB per CU) cannot hold 64
-  int nc = 64;
+  // 64 columns per batch, 32 when the LDS (160 KB per CU) cannot hold 64.
+  // Up to degree 16 in FP32 with one right-hand side, 60 columns let two
+  // blocks share a CU (registers are then capped for four waves per SIMD).
+  const bool lo = p <= 16, two = lo && sizeof(R) == 4 && nrc == 1;
+  int nc = two ? 60 : 64;
   if (rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc = 32;
   const size_t shm = rot_smem_bytes(p, nc, sizeof(R));
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   const RotSched sc = make_sched(p);
   switch (nrc) {
-    case 1: return launch_nd<R, 4>(l, e, nc, shm, sc, rot, zt);
-    case 2: return launch_nd<R, 8>(l, e, nc, shm, sc, rot, zt);
-    case 4: return launch_nd<R, 16>(l, e, nc, shm, sc, rot, zt);
+    case 1:
+      if constexpr (sizeof(R) == 4)
+        if (two) return launch_nd<R, 4, 16, 4>(l, e, nc, shm, sc, rot, zt);
+      return lo ? launch_nd<R, 4, 16, 1>(l, e, nc, shm, sc, rot, zt) : launch_nd<R, 4, 21, 1>(l, e, nc, shm, sc, rot, zt);
+    case 2:
+      return lo ? launch_nd<R, 8, 16, 1>(l, e, nc, shm, sc, rot, zt) : launch_nd<R, 8, 21, 1>(l, e, nc, shm, sc, rot, zt);
+    case 4:
+      return lo ? launch_nd<R, 16, 16, 1>(l, e, nc, shm, sc, rot, zt)
+                : launch_nd<R, 16, 21, 1>(l, e, nc, shm, sc, rot, zt);
     default: return hipErrorInvalidValue;
   }
 }
