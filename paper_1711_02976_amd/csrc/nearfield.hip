@@ -135,21 +135,23 @@ __device__ inline double rinv_of(double r2) {
 // coincident bead) r^2 is clamped before the reciprocal square root: the far
 // values are then finite and discarded, and the overlap values give the
 // r -> 0 limit A' = c0/c1, B' d = 0.
-// In the mixed form the pair difference is formed in FP64 and rounded, and
-// the pair arithmetic and per-source-leaf sums run in FP32.
+// Positions enter the pair arithmetic relative to the target leaf's centre
+// (differences taken in FP64 and rounded once); in the mixed form the pair
+// arithmetic and per-source-leaf sums run in FP32.
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
                                                PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
+  __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
   const int i = tl.y + (valid ? threadIdx.x : 0);
-  const double xi = sx[i], yi = sy[i], zi = sz[i];
+  const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];
+  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   const int e0 = __builtin_amdgcn_readfirstlane(U.off[b]), e1 = __builtin_amdgcn_readfirstlane(U.off[b + 1]);
@@ -164,10 +166,10 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
+        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
-        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
@@ -176,7 +178,8 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       for (int s0 = 0; s0 < ns4; s0 += 4)
 #pragma unroll
       for (int s = s0; s < s0 + 4; ++s) {
-        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        // padding sources: r^2 overflows to inf in FP32, 1/r = 0, A = B = 0
+        const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
         const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const R rinv = rinv_of(max(r2, k.r2min));
         const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
