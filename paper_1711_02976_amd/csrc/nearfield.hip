@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
                                                    PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                    double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
+  __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
   if (e0 == e1) return;
   const bool valid = (int)threadIdx.x < tl.z;
   const int i = tl.y + (valid ? threadIdx.x : 0);
-  const double xi = sx[i], yi = sy[i], zi = sz[i];
+  const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
+  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   bool any = false;
@@ -244,10 +245,10 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
+        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
-        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
@@ -256,7 +257,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
       for (int s0 = 0; s0 < ns4; s0 += 4)
 #pragma unroll
       for (int s = s0; s < s0 + 4; ++s) {
-        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
         const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const R rinv = rinv_of(max(r2, k.r2min));
         const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
@@ -293,7 +294,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
                                                    PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                    double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  __shared__ double xs[P2P_T], ys[P2P_T], zs[P2P_T];
+  __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
@@ -301,7 +302,8 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
   if (e0 == e1) return;
   const bool valid = (int)threadIdx.x < tl.z;
   const int i = tl.y + (valid ? threadIdx.x : 0);
-  const double xi = sx[i], yi = sy[i], zi = sz[i];
+  const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
+  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   double blo[3], bhi[3];
@@ -328,10 +330,10 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = sx[j]; ys[threadIdx.x] = sy[j]; zs[threadIdx.x] = sz[j];
+        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
-        xs[threadIdx.x] = 1e30; ys[threadIdx.x] = 1e30; zs[threadIdx.x] = 1e30;
+        xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
@@ -340,7 +342,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       for (int s0 = 0; s0 < ns4; s0 += 4)
 #pragma unroll
       for (int s = s0; s < s0 + 4; ++s) {
-        const R dx = (R)(xi - xs[s]), dy = (R)(yi - ys[s]), dz = (R)(zi - zs[s]);
+        const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
         const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const R rinv = rinv_of(max(r2, k.r2min));
         const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
