@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
     for (int r = 0; r < NACC; ++r) {
       const int i = tid + r * RT;
       if (i < ND * T) {
-        const int f = i / ND, d = i % ND;
+        const int d = i / T, f = i - d * T;  // lanes walk a column: one bank per lane
         const C* row = X + (size_t)f * ld + d;
         double sx = 0.0, sy = 0.0;
         for (int j = 0; j < nc; j += ND) {
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   for (int r = 0; r < NACC; ++r) {
     const int i = tid + r * RT;
     if (i < ND * T) {
-      const int f = i / ND, d = i % ND;
+      const int d = i / T, f = i - d * T;
       const double s = sf[f];
       Lb[(size_t)d * T + f] = make_double2(acc[r].x * s, acc[r].y * s);
     }
