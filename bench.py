@@ -209,8 +209,8 @@ def run(args):
 PMC_KERNELS = {  # rocprofv3 kernel-name prefix -> (phase, precision form, source file)
     "rpy::k_p2p<1, true>": ("p2p", "mixed", "nearfield.hip"),
     "rpy::k_p2p<1, false>": ("p2p", "fp64", "nearfield.hip"),
-    "rpy::k_m2l_rot<4, float>": ("m2l", "mixed", "m2l_rot.hip"),
-    "rpy::k_m2l_rot<4, double>": ("m2l", "fp64", "m2l_rot.hip"),
+    "rpy::k_m2l_rot<4, float": ("m2l", "mixed", "m2l_rot.hip"),
+    "rpy::k_m2l_rot<4, double": ("m2l", "fp64", "m2l_rot.hip"),
 }
 
 
@@ -238,7 +238,11 @@ def pmc_summary(args):
     kw = copy_bytes / (1024.0 * mean(cw[("__amd_rocclr_copyBuffer", "WRITE_SIZE")]))
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    for name, (phase, form, src) in PMC_KERNELS.items():
+    for prefix, (phase, form, src) in PMC_KERNELS.items():
+        names = sorted({k[0] for k in f if k[0].startswith(prefix)})
+        if not names:
+            continue
+        name = names[0]
         if (name, "FETCH_SIZE") not in f or (name, "WRITE_SIZE") not in w:
             continue
         fb = mean(f[(name, "FETCH_SIZE")]) * 1024.0 * kf
