@@ -287,6 +287,11 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
 // separated, so r > 0 and the far values are finite.  Pairs at r >= 2a get a
 // zero coefficient (masked, no branch).  With the prefactor taken out:
 //   A' = oc (1 - 9r/(32a)) - 1/r - (2a^2/3)/r^3,  B' = ob/r - (1 - 2a^2/r^2)/r^3.
+// Most pairs of two such leaves are farther apart than 2a, so the staged
+// sources are cut into groups of 16 with bounding boxes, and a wave skips a
+// group whose box is 2a or more from the box of the wave's own targets.
+constexpr int OV_G = 16;
+
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const double* tbox, Tree t, List O,
                                                    double four_a2, const double* sx,
@@ -294,8 +299,10 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
                                                    PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                    double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
+  constexpr int NG = P2P_T / OV_G;
   __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ R fs[NRC * 3][P2P_T];
+  __shared__ R gbox[NG][6];  // per source group: lo xyz, hi xyz
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
   const int e0 = __builtin_amdgcn_readfirstlane(O.off[b]), e1 = __builtin_amdgcn_readfirstlane(O.off[b + 1]);
@@ -304,6 +311,16 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
   const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
+  // bounding box of this wave's targets (idle lanes repeat the tile's first bead)
+  R wlo[3] = {xi, yi, zi}, whi[3] = {xi, yi, zi};
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    for (int o = 1; o < 64; o <<= 1) {
+      wlo[q] = min(wlo[q], __shfl_xor(wlo[q], o));
+      whi[q] = max(whi[q], __shfl_xor(whi[q], o));
+    }
+  // a group is skipped only when its box is clearly 2a away (rounding margin)
+  const R skip2 = (R)(four_a2 * (1.0 + 1e-4));
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   double blo[3], bhi[3];
@@ -337,26 +354,51 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)0;
       }
       __syncthreads();
+      const int ng = (ns + OV_G - 1) / OV_G;
+      if ((int)threadIdx.x < 3 * ng) {
+        // box of the real sources of group g along one axis
+        const int g = threadIdx.x / 3, q = threadIdx.x - 3 * g;
+        const R* col = q == 0 ? xs : (q == 1 ? ys : zs);
+        const int s1 = min(g * OV_G + OV_G, ns);
+        R lo = col[g * OV_G], hi = lo;
+        for (int s = g * OV_G + 1; s < s1; ++s) {
+          lo = min(lo, col[s]);
+          hi = max(hi, col[s]);
+        }
+        gbox[g][q] = lo;
+        gbox[g][3 + q] = hi;
+      }
+      __syncthreads();
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
-      for (int s0 = 0; s0 < ns4; s0 += 4)
+      for (int g = 0; g < ng; ++g) {
+        R g2 = 0;
 #pragma unroll
-      for (int s = s0; s < s0 + 4; ++s) {
-        const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const R rinv = rinv_of(max(r2, k.r2min));
-        const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
-        const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
-        const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
-        const bool ov = r2 < k.four_a2;
-        const R A = ov ? Ao - Af : (R)0, B = ov ? Bo - Bf : (R)0;
+        for (int q = 0; q < 3; ++q) {
+          const R d = max((R)0, max(gbox[g][q] - whi[q], wlo[q] - gbox[g][3 + q]));
+          g2 = fma(d, d, g2);
+        }
+        if (!(g2 < skip2)) continue;  // wave-uniform
+        const int s1 = min(g * OV_G + OV_G, ns4);
+        for (int s0 = g * OV_G; s0 < s1; s0 += 4)
 #pragma unroll
-        for (int r = 0; r < NRC; ++r) {
-          const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
-          const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
-          ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
-          ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
-          ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
+        for (int s = s0; s < s0 + 4; ++s) {
+          const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
+          const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const R rinv = rinv_of(max(r2, k.r2min));
+          const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
+          const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
+          const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
+          const bool ov = r2 < k.four_a2;
+          const R A = ov ? Ao - Af : (R)0, B = ov ? Bo - Bf : (R)0;
+#pragma unroll
+          for (int r = 0; r < NRC; ++r) {
+            const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
+            const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
+            ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
+            ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
+            ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
+          }
         }
       }
       for (int r = 0; r < NRC; ++r)
