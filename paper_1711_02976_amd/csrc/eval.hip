@@ -205,15 +205,22 @@ __device__ inline void eval_sets(const double2* __restrict__ D, int nmax, double
   for (int i = 0; i < 3; ++i) vel[i] += s[i] - C1 * (vx * s[3 + 3 * i] + vy * s[4 + 3 * i] + vz * s[5 + 3 * i]);
 }
 
-// One wave per tile (leaf box, first bead, count <= 64, leaf ordinal).
+// One wave per tile (leaf box, first bead, count <= 64, leaf ordinal),
+// EV_WAVES consecutive tiles per block.
+constexpr int EV_WAVES = 4;
 // Writes (assigns) the far-field velocity of every bead of the tile.
 template <int NRC>
-__global__ void __launch_bounds__(64) k_eval_apply(int p, const int4* tiles, Tree t, List W, const int* widx,
+__global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4* tiles, int ntiles, Tree t, List W,
+                                                             const int* widx,
                                                    const double* sx, const double* sy, const double* sz, int64_t n,
                                                    const double2* __restrict__ DL, const double2* __restrict__ DW,
                                                    double C1, double* __restrict__ u) {
-  const int4 tl = tiles[blockIdx.x];
-  const int b = tl.x, lane = threadIdx.x;
+  // consecutive tiles (mostly of one leaf) share a block, hence a CU and its
+  // scalar cache, and walk the same set coefficients at about the same time
+  const int ti = blockIdx.x * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (ti >= ntiles) return;
+  const int4 tl = tiles[ti];
+  const int b = tl.x, lane = threadIdx.x & 63;
   const int j = tl.y + min(lane, tl.z - 1);
   const double px = sx[j], py = sy[j], pz = sz[j];
   const int T = ncoef(p), To = ncoef(p + 2);
@@ -273,7 +280,8 @@ hipError_t launch_eval(const Launch& l, const EvalPlan& ep, Exp e, double* u) {
   he = hipGetLastError();
   if (he != hipSuccess) return he;
   if (ep.tiles.n > 0)
-    k_eval_apply<NRC><<<ep.tiles.n, 64, 0, l.s>>>(p, ep.tiles.t, B->tree, B->lists[LW], ep.widx, B->sx, B->sy, B->sz,
+    k_eval_apply<NRC><<<(ep.tiles.n + EV_WAVES - 1) / EV_WAVES, 64 * EV_WAVES, 0, l.s>>>(
+        p, ep.tiles.t, ep.tiles.n, B->tree, B->lists[LW], ep.widx, B->sx, B->sy, B->sz,
                                                   B->n, e.DL, e.DW, C1, u);
   return hipGetLastError();
 }
