@@ -144,8 +144,11 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
                                                PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
-  __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
-  __shared__ R fs[NRC * 3][P2P_T];
+  using V4 = typename std::conditional<MIXED, float4, double4>::type;
+  __shared__ alignas(32) R xs[P2P_T];
+  __shared__ alignas(32) R ys[P2P_T];
+  __shared__ alignas(32) R zs[P2P_T];
+  __shared__ alignas(32) R fs[NRC * 3][P2P_T];
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
@@ -175,29 +178,46 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       __syncthreads();
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
-      for (int s0 = 0; s0 < ns4; s0 += 4)
-#pragma unroll
-      for (int s = s0; s < s0 + 4; ++s) {
+      // four sources per trip, read as vectors; one wave-wide test for the
+      // overlap branch per trip
+      for (int s0 = 0; s0 < ns4; s0 += 4) {
+        const V4 X4 = *reinterpret_cast<const V4*>(xs + s0), Y4 = *reinterpret_cast<const V4*>(ys + s0),
+                 Z4 = *reinterpret_cast<const V4*>(zs + s0);
         // padding sources: r^2 overflows to inf in FP32, 1/r = 0, A = B = 0
-        const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const R rinv = rinv_of(max(r2, k.r2min));
-        const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
-        R A = fma(k.a3, ri3, rinv);
-        R B = ri3 * fma(-k.a2, ri2, (R)1);
-        const bool ov = r2 < k.four_a2;
-        if (__builtin_expect(__any(ov), 0)) {
-          const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
-          A = ov ? Ao : A;
-          B = ov ? Bo : B;
+        const R dx[4] = {xi - X4.x, xi - X4.y, xi - X4.z, xi - X4.w};
+        const R dy[4] = {yi - Y4.x, yi - Y4.y, yi - Y4.z, yi - Y4.w};
+        const R dz[4] = {zi - Z4.x, zi - Z4.y, zi - Z4.z, zi - Z4.w};
+        R r2[4], rinv[4], A[4], B[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          r2[q] = fma(dx[q], dx[q], fma(dy[q], dy[q], dz[q] * dz[q]));
+          rinv[q] = rinv_of(max(r2[q], k.r2min));
+          const R ri2 = rinv[q] * rinv[q], ri3 = ri2 * rinv[q];
+          A[q] = fma(k.a3, ri3, rinv[q]);
+          B[q] = ri3 * fma(-k.a2, ri2, (R)1);
+        }
+        const R r2lo = min(min(r2[0], r2[1]), min(r2[2], r2[3]));
+        if (__builtin_expect(__any(r2lo < k.four_a2), 0)) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const bool ov = r2[q] < k.four_a2;
+            const R Ao = fma(-k.ock9, r2[q] * rinv[q], k.oc), Bo = k.ob * rinv[q];
+            A[q] = ov ? Ao : A[q];
+            B[q] = ov ? Bo : B[q];
+          }
         }
 #pragma unroll
         for (int r = 0; r < NRC; ++r) {
-          const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
-          const R sdf = B * fma(dx, fx, fma(dy, fy, dz * fz));
-          ar[r][0] = fma(A, fx, fma(sdf, dx, ar[r][0]));
-          ar[r][1] = fma(A, fy, fma(sdf, dy, ar[r][1]));
-          ar[r][2] = fma(A, fz, fma(sdf, dz, ar[r][2]));
+          const V4 FX = *reinterpret_cast<const V4*>(&fs[3 * r][s0]), FY = *reinterpret_cast<const V4*>(&fs[3 * r + 1][s0]),
+                   FZ = *reinterpret_cast<const V4*>(&fs[3 * r + 2][s0]);
+          const R fx[4] = {FX.x, FX.y, FX.z, FX.w}, fy[4] = {FY.x, FY.y, FY.z, FY.w}, fz[4] = {FZ.x, FZ.y, FZ.z, FZ.w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const R sdf = B[q] * fma(dx[q], fx[q], fma(dy[q], fy[q], dz[q] * fz[q]));
+            ar[r][0] = fma(A[q], fx[q], fma(sdf, dx[q], ar[r][0]));
+            ar[r][1] = fma(A[q], fy[q], fma(sdf, dy[q], ar[r][1]));
+            ar[r][2] = fma(A[q], fz[q], fma(sdf, dz[q], ar[r][2]));
+          }
         }
       }
       for (int r = 0; r < NRC; ++r)
