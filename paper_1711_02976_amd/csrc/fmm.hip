@@ -417,11 +417,21 @@ __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const doubl
     }
     __syncthreads();
     if (threadIdx.x < T) {
+      // four independent partial sums keep several LDS reads in flight
+      double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
       for (int k = 0; k <= n; ++k) {
         const int j = n - k;
         const int lmin = max(-k, m - j), lmax = min(k, m + j);
-        for (int l = lmin; l <= lmax; ++l) cfmac(acc, Mc[fidx(k, l)], Rt[fidx(j, m - l)]);
+        const int mk = fidx(k, 0), rj = fidx(j, m);  // rj - l >= j*j for l <= lmax
+        int l = lmin;
+        for (; l + 3 <= lmax; l += 4) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) cfmac(a4[q], Mc[mk + l + q], Rt[rj - (l + q)]);
+        }
+        for (; l <= lmax; ++l) cfmac(a4[0], Mc[mk + l], Rt[rj - l]);
       }
+      acc.x += (a4[0].x + a4[1].x) + (a4[2].x + a4[3].x);
+      acc.y += (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y);
     }
   }
   if (threadIdx.x < T) M[(int64_t)b * ND * T + d * T + threadIdx.x] = acc;
@@ -463,12 +473,20 @@ __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const doubl
   int k = 0;
   while (tri(k + 1) <= (int)threadIdx.x) ++k;
   const int l = threadIdx.x - tri(k);
-  double2 acc = make_double2(0, 0);
+  // four independent partial sums keep several LDS reads in flight
+  double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
   for (int n = k; n <= p; ++n) {
     const int j = n - k;
     const int mmin = max(-n, l - j), mmax = min(n, l + j);
-    for (int m = mmin; m <= mmax; ++m) cfma(acc, Lp[fidx(n, m)], Rt[fidx(j, m - l)]);
+    const int ln = fidx(n, 0), rj = fidx(j, -l);  // rj + m >= j*j for m >= mmin
+    int m = mmin;
+    for (; m + 3 <= mmax; m += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cfma(a4[q], Lp[ln + m + q], Rt[rj + m + q]);
+    }
+    for (; m <= mmax; ++m) cfma(a4[0], Lp[ln + m], Rt[rj + m]);
   }
+  double2 acc = make_double2((a4[0].x + a4[1].x) + (a4[2].x + a4[3].x), (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y));
   const double sc = ldexp(1.0, -(k + 1));
   double2* out = L + (int64_t)b * ND * T + d * T + threadIdx.x;
   const double2 v = *out;
