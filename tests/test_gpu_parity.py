@@ -110,6 +110,23 @@ def test_fmm_fp64_matches_oracle_fmm(orc, case):
     assert err <= 1e-12
 
 
+# (order, rhs) pairs that reach every particle-to-expansion schedule: 8 steps
+# per wave and pass over 1..4 passes (one or two right-hand sides per pass)
+# and, with four right-hand sides per pass, 8 steps over 1..2 passes or 16
+# steps over 2; the tree has W and X lists.
+@pytest.mark.parametrize("p,nrhs", [(1, 3), (7, 4), (14, 3), (15, 4), (18, 2), (19, 1), (21, 4)],
+                         ids=lambda v: str(v))
+def test_schedules_match_oracle_fmm(orc, p, nrhs):
+    w = W.clustered(1500, 8, 10.0, 0.8, 0.05, nrhs, seed=80 + p)
+    log(f"schedule parity n={w.n} nrhs={nrhs} p={p} s=20")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=20)
+    assert st["list_len"]["X"] > 0 and st["list_len"]["W"] > 0
+    ref = orc.fmm(w.pos, w.forces, w.a, w.eta, p, 20)
+    err = orc.rel_l2(u, ref)
+    log(f"  rel-L2 vs oracle FMM = {err:.3e}")
+    assert err <= 1e-12
+
+
 @pytest.mark.parametrize("eps", [1e-3, 1e-6])
 def test_fmm_fp64_accuracy_vs_direct(orc, eps):
     w = W.uniform_cube(20_000, 2.0, 0.01, nrhs=1, seed=71)
