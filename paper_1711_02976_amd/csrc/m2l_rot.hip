@@ -61,6 +61,9 @@ struct ColData {
   double* e2x;   // e^{i theta}
   double* e2y;
   double* rinv;  // 1/rho (box units)
+  double* wx;    // source centre - target centre (re-centres the fourth density)
+  double* wy;
+  double* wz;
 };
 
 __host__ __device__ constexpr int rot_block(int n) { return n * (n + 1) * (2 * n + 1) / 6; }  // sum_{j<n} (j+1)^2
@@ -254,6 +257,9 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
     cd.e2x = dq; dq += nc;
     cd.e2y = dq; dq += nc;
     cd.rinv = dq; dq += nc;
+    cd.wx = dq; dq += nc;
+    cd.wy = dq; dq += nc;
+    cd.wz = dq; dq += nc;
     cd.src = reinterpret_cast<int*>(dq);
   }
   double2 acc[NACC];
@@ -269,7 +275,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
     if (tid < nc) {
       const int g = c0 + tid;
       int S = -1;
-      double q0 = 1.0, q1 = 0.0, q2 = 1.0, q3 = 0.0, q4 = 0.5;
+      double q0 = 1.0, q1 = 0.0, q2 = 1.0, q3 = 0.0, q4 = 0.5, w0 = 0.0, w1 = 0.0, w2 = 0.0;
       if (g < ncols) {
         S = V.ent[e0 + g / ND];
         const int o = (t.ax[S] - bx + 3) * 49 + (t.ay[S] - by + 3) * 7 + (t.az[S] - bz + 3);
@@ -279,6 +285,9 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
         q2 = gq[2];
         q3 = gq[3];
         q4 = gq[4];
+        w0 = t.cx[S] - cbx;
+        w1 = t.cy[S] - cby;
+        w2 = t.cz[S] - cbz;
       }
       cd.src[tid] = S;
       cd.e1x[tid] = q0;
@@ -286,6 +295,9 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
       cd.e2x[tid] = q2;
       cd.e2y[tid] = q3;
       cd.rinv[tid] = q4;
+      cd.wx[tid] = w0;
+      cd.wy[tid] = w1;
+      cd.wz[tid] = w2;
     }
     __syncthreads();
     // phase 0: gather the batch's multipoles (coefficient-contiguous reads),
@@ -304,7 +316,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
           double2 v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = src[k * T];
-          const double w0 = t.cx[S] - cbx, w1 = t.cy[S] - cby, w2 = t.cz[S] - cbz;
+          const double w0 = cd.wx[c], w1 = cd.wy[c], w2 = cd.wz[c];
           v[3].x += w0 * v[0].x + w1 * v[1].x + w2 * v[2].x;
           v[3].y += w0 * v[0].y + w1 * v[1].y + w2 * v[2].y;
           const double s = sf[f];
@@ -425,7 +437,7 @@ static RotSched make_sched(int p) {
 }
 
 static size_t rot_smem_bytes(int p, int nc, size_t real) {
-  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (5 * sizeof(double) + sizeof(int));
+  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * sizeof(double) + sizeof(int));
 }
 
 template <class R, int ND, int PM, int MINW>
