@@ -102,6 +102,9 @@ struct Built {
   int nleaf = 0;
   int* leaf_ids = nullptr;      // [nleaf]
   List lists[5]{};
+  // block -> target box of the rotation M->L (make_m2l_map), -1: no box
+  int* m2l_map = nullptr;
+  int m2l_grid = 0;
   int64_t bytes = 0;
 };
 

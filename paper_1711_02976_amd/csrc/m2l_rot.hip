@@ -15,7 +15,8 @@
 //   L'_k^l = rho^-(k+1) sum_n H_l[k][n] rho^-n M'_n^l,
 //   H_l[k][n] = (-1)^{n+l} (n+k)! / (s_k^l s_n^l),  s_n^m = sqrt((n-m)!(n+m)!).
 //
-// GPU organisation.  One block of RW waves per target box; its V-list
+// GPU organisation.  One block of RW waves per target box (the block-to-box
+// map balances the V-list work over the XCDs, see make_m2l_map); its V-list
 // (source, density) pairs are the columns, taken NC (64; 60 or 32 when LDS
 // is short) at a time into an LDS array X[coefficient][column].  Each batch
 // runs four phases separated by barriers:
@@ -30,6 +31,9 @@
 // and each lane's coefficients of one degree stay in registers.  Degrees and
 // orders are assigned to waves by a host-side longest-first schedule.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "fmm.h"
 
@@ -233,7 +237,8 @@ template <int ND, class R, int PM, int MINW>
 __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, List V, RotSched sched,
                                                 const R* __restrict__ rot, const R* __restrict__ zt, int rot_len,
                                                 const double* __restrict__ geo, const double* __restrict__ sf,
-                                                const double2* __restrict__ M, double2* __restrict__ L) {
+                                                const double2* __restrict__ M, double2* __restrict__ L,
+                                                const int* __restrict__ bmap) {
   using C = typename Cx<R>::T;
   constexpr int NACC = (ND * ncoef(MAX_ORDER) + RT - 1) / RT;
   extern __shared__ double2 smem[];
@@ -241,13 +246,8 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   const int ld = nc + 1;  // padded row: column-wise and row-wise LDS accesses both avoid bank conflicts
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // contiguous runs of target boxes per XCD (blocks are dealt to the 8 XCDs
-  // round-robin), so that neighbouring targets share sources in one L2
-  int b;
-  {
-    const int G = gridDim.x, q = G / 8, r = G % 8, x = blockIdx.x % 8;
-    b = x * q + min(x, r) + blockIdx.x / 8;
-  }
+  const int b = bmap[blockIdx.x];
+  if (b < 0) return;  // whole block, before any barrier
   C* X = reinterpret_cast<C*>(smem);
   ColData cd;
   {
@@ -448,8 +448,9 @@ static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const Ro
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
-  kern<<<B->tree.nbox, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
-                                       l.tb->sfac, e.M, e.L);
+  if (!B->m2l_map || B->m2l_grid < B->tree.nbox) return hipErrorInvalidValue;
+  kern<<<B->m2l_grid, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
+                                       l.tb->sfac, e.M, e.L, B->m2l_map);
   return hipGetLastError();
 }
 
@@ -479,6 +480,50 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
                 : launch_nd<R, 16, 21, 1>(l, e, nc, shm, sc, rot, zt);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Blocks are dealt to the 8 XCDs round-robin (block i to XCD i mod 8), and
+// each XCD has its own L2.  Every XCD gets one contiguous run of target
+// boxes, so that neighbouring targets share their V-list sources in one L2,
+// and the runs are cut where the modelled work (V entries, plus the part
+// batch and the store of L per box) splits evenly: with clustered beads the
+// V lists are far from uniform along the box order, and equal box counts
+// per XCD left some XCDs with twice the mean work.  Block 8k + x takes the
+// k-th box of run x; blocks past the end of a shorter run take none.
+int make_m2l_map(Built* B, hipStream_t s, Error* err) {
+  const int nbox = B->tree.nbox;
+  if (B->m2l_map) {
+    (void)hipFree(B->m2l_map);
+    B->m2l_map = nullptr;
+  }
+  B->m2l_grid = 0;
+  if (nbox == 0) return 0;
+  std::vector<int> off(nbox + 1);
+  RPY_HIP(hipMemcpyAsync(off.data(), B->lists[LV].off, sizeof(int) * (nbox + 1), hipMemcpyDeviceToHost, s));
+  RPY_HIP(hipStreamSynchronize(s));
+  std::vector<double> pre(nbox + 1, 0.0);
+  for (int b = 0; b < nbox; ++b) {
+    const int v = off[b + 1] - off[b];
+    pre[b + 1] = pre[b] + v + (v > 0 ? 1.0 : 0.0) + 0.25;
+  }
+  int cut[9];
+  cut[0] = 0;
+  cut[8] = nbox;
+  for (int x = 1; x < 8; ++x) {
+    const double goal = pre[nbox] * x / 8.0;
+    cut[x] = (int)(std::lower_bound(pre.begin(), pre.end(), goal) - pre.begin());
+    cut[x] = std::min(std::max(cut[x], cut[x - 1]), nbox);
+  }
+  int K = 0;
+  for (int x = 0; x < 8; ++x) K = std::max(K, cut[x + 1] - cut[x]);
+  std::vector<int> map((size_t)8 * K, -1);
+  for (int x = 0; x < 8; ++x)
+    for (int k = 0; k < cut[x + 1] - cut[x]; ++k) map[(size_t)8 * k + x] = cut[x] + k;
+  RPY_HIP(hipMalloc(&B->m2l_map, sizeof(int) * map.size()));
+  RPY_HIP(hipMemcpy(B->m2l_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+  B->m2l_grid = 8 * K;
+  B->bytes += (int64_t)sizeof(int) * map.size();
+  return 0;
 }
 
 hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32) {
