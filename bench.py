@@ -101,7 +101,7 @@ def run(args):
     for prec in args.precisions:
         torch.cuda.synchronize()
         P = R.Plan(pos, w.a, w.eta, w.eps, precision=prec, leaf_size=args.leaf_size, order=args.order,
-                   max_depth=w.max_depth, counts=counts, m2l=args.m2l)
+                   max_depth=w.max_depth, counts=counts, m2l=args.m2l, nrhs=F.shape[0])
         st = P.stats()
         progress(f"{w.name} {prec}: plan {st['plan_ms']:.1f} ms, p={st['order']} s={st['leaf_size']} "
                  f"boxes={st['nbox']} depth={st['depth']}")

@@ -62,6 +62,12 @@ typedef struct {
                             (rotation), 1 = dense O(p^4) translation,
                             2 = rotation to the z axis, O(p^3) */
   void* stream;          /* hipStream_t for all work; NULL = null stream */
+  int32_t nrhs;          /* right-hand sides per rpy_matvec call that the
+                            library's leaf-size choice is tuned for (passes of
+                            4 make the near field cheaper per right-hand side,
+                            so larger leaves pay); 0 = 1.  Any nrhs may still
+                            be passed to rpy_matvec.  Callers built against a
+                            struct_size that ends at `stream` get 0. */
 } rpy_options;
 
 typedef struct rpy_plan_s rpy_plan_t;

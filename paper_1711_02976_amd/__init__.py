@@ -27,7 +27,7 @@ LIST_NAMES = ("U", "V", "W", "X", "O")
 class rpy_options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("precision", C.c_int32), ("leaf_size", C.c_int32),
                 ("order", C.c_int32), ("max_depth", C.c_int32), ("m2l_mode", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("nrhs", C.c_int32)]
 
 
 class rpy_plan_stats_t(C.Structure):
@@ -98,7 +98,7 @@ def _check(status):
 M2L_MODES = {"auto": 0, "dense": 1, "rotation": 2}
 
 
-def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=None, m2l="auto"):
+def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=None, m2l="auto", nrhs=0):
     o = rpy_options()
     lib().rpy_default_options(C.byref(o))
     o.m2l_mode = M2L_MODES[m2l] if isinstance(m2l, str) else int(m2l)
@@ -107,6 +107,7 @@ def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=
     o.order = int(order)
     o.max_depth = int(max_depth)
     o.stream = stream
+    o.nrhs = int(nrhs)
     return o
 
 
@@ -187,7 +188,7 @@ class Plan:
     """
 
     def __init__(self, positions, a, eta=1.0, eps=1e-6, precision="fp64", leaf_size=0, order=0,
-                 max_depth=0, counts=None, stream=None, m2l="auto"):
+                 max_depth=0, counts=None, stream=None, m2l="auto", nrhs=0):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a float64 CUDA tensor")
@@ -199,7 +200,8 @@ class Plan:
             stream = torch.cuda.current_stream(pos.device).cuda_stream
         self.device = pos.device
         self.stream = stream
-        self.options = make_options(prec, leaf_size, order, max_depth, C.c_void_p(stream) if stream else None, m2l)
+        self.options = make_options(prec, leaf_size, order, max_depth, C.c_void_p(stream) if stream else None, m2l,
+                                    nrhs)
         self.n = int(pos.shape[0])
         self.counts = [self.n] if counts is None else [int(c) for c in counts]
         if sum(self.counts) != self.n:

@@ -46,12 +46,19 @@ int order_for_eps(double eps, bool adaptive) {
 }
 
 // ---- leaf-size choice ------------------------------------------------------
-// Modelled time of one matvec (one right-hand side) on a built tree, from its
-// interaction counts and per-unit kernel times measured on MI355X for this
-// library at p = 16 (1M-bead cube): P2P (and overlap-correction) per ordered bead pair, M2L per
-// (V pair, density), per-box upward/downward work per density, and the
-// adaptive W/X terms per (bead, box).  Also returns the range of refinement
-// limits that produce this same tree.
+// Modelled time of one matvec with nrhs right-hand sides on a built tree, from
+// its interaction counts and per-unit kernel times measured on MI355X for this
+// library (uniform cube, sphere surface, Gaussian blobs and batched systems,
+// p = 16 and 21):
+//   * P2P and the direct W sums per ordered bead pair, with targets padded to
+//     whole 128-bead tiles; a pass of 4 right-hand sides costs about 2.3x a
+//     pass of one;
+//   * per density (4 per right-hand side): M2L per V pair (O(p^3)), upward
+//     and downward translations per box (O(p^4)), S->M and evaluation sets
+//     per leaf, S->L per (bead, X box) and W-multipole evaluation per
+//     (target bead, W box) (O(p^2)).
+// The overlap correction is not modelled: trial trees have no O list.  Also
+// returns the range of refinement limits that produce this same tree.
 struct TreeCost {
   double ns = 0;
   int same_lo = 0;     // largest leaf that a larger limit could not split
@@ -59,7 +66,8 @@ struct TreeCost {
   bool adaptive = false;
 };
 
-static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, int max_depth, TreeCost* out) {
+static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, int max_depth, int nrhs,
+                      TreeCost* out) {
   const rpy::Tree& t = B.tree;
   const int nbox = t.nbox;
   std::vector<int> beg(nbox), end(nbox), child(nbox), lev(nbox);
@@ -71,40 +79,51 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const rpy::List& U = B.lists[rpy::LU];
   const rpy::List& W = B.lists[rpy::LW];
   const rpy::List& X = B.lists[rpy::LX];
-  const rpy::List& O = B.lists[rpy::LO];
-  std::vector<int> uo(nbox + 1), ue(U.len), wo(nbox + 1), xo(nbox + 1), xe(X.len), oo(nbox + 1), oe(O.len);
-  if (!get(uo, U.off, nbox + 1) || !get(ue, U.ent, U.len) || !get(wo, W.off, nbox + 1) || !get(xo, X.off, nbox + 1) ||
-      !get(xe, X.ent, X.len) || !get(oo, O.off, nbox + 1) || !get(oe, O.ent, O.len))
+  std::vector<int> uo(nbox + 1), ue(U.len), wo(nbox + 1), we(W.len), xo(nbox + 1), xe(X.len);
+  if (!get(uo, U.off, nbox + 1) || !get(ue, U.ent, U.len) || !get(wo, W.off, nbox + 1) || !get(we, W.ent, W.len) ||
+      !get(xo, X.off, nbox + 1) || !get(xe, X.ent, X.len))
     return -4;
   const bool adaptive = W.len > 0 || X.len > 0;
   const int p = order ? order : order_for_eps(eps, adaptive);
-  double pairs = 0, wterm = 0, xterm = 0, opairs = 0;
+  const int wmax = rpy::wdirect_max(p);
+  double pairs = 0, weval = 0, xpairs = 0, nleaf = 0;
   int lo = 0, hi = 0x7fffffff;
   for (int b = 0; b < nbox; ++b) {
     const int nb = end[b] - beg[b];
     if (child[b] < 0) {
       if (lev[b] < max_depth) lo = std::max(lo, nb);
+      nleaf += 1;
+      const double padded = 128.0 * ((nb + 127) / 128);
       double src = 0;
       for (int k = uo[b]; k < uo[b + 1]; ++k) src += end[ue[k]] - beg[ue[k]];
-      pairs += (double)nb * src;
-      wterm += (double)nb * (wo[b + 1] - wo[b]);
-      double osrc = 0;
-      for (int k = oo[b]; k < oo[b + 1]; ++k) osrc += end[oe[k]] - beg[oe[k]];
-      opairs += (double)nb * osrc;
+      for (int k = wo[b]; k < wo[b + 1]; ++k) {
+        const int nc = end[we[k]] - beg[we[k]];
+        if (nc > wmax) weval += nb;
+        else src += nc;
+      }
+      pairs += padded * src;
     } else {
       hi = std::min(hi, nb);
     }
-    for (int k = xo[b]; k < xo[b + 1]; ++k) xterm += end[xe[k]] - beg[xe[k]];
+    for (int k = xo[b]; k < xo[b + 1]; ++k) xpairs += end[xe[k]] - beg[xe[k]];
   }
-  const double S = (p + 1.0) * (p + 2.0) * (2.0 * p + 3.0) / 6.0, S16 = 17.0 * 18.0 * 35.0 / 6.0;
-  const double T = (p + 1.0) * (p + 2.0) / 2.0, T16 = 153.0;
-  const double c_pair = mixed ? 0.84 : 1.55;          // ns per ordered pair
-  const double c_v = (mixed ? 1400.0 : 1900.0) * S / S16;  // ns per (V pair, density)
-  const double c_box = 45.0 * T / T16;                // ns per (box, density)
-  const double c_wx = 3.0 * T / T16;                  // ns per (bead, W or X box, density)
-  // bead pairs of O-list leaves: the overlap correction visits them at about
-  // the P2P rate (an upper bound: tiles farther than 2a are skipped)
-  out->ns = (pairs + opairs) * c_pair + 4.0 * (B.lists[rpy::LV].len * c_v + nbox * c_box + (wterm + xterm) * c_wx);
+  const double S = (p + 1.0) * (p + 2.0) * (2.0 * p + 3.0) / 6.0, T = (p + 1.0) * (p + 2.0) / 2.0;
+  const double S16 = 1785.0, S21 = 3795.0, T21 = 253.0;
+  // ns per unit (one density unless stated)
+  const double c_pair = mixed ? 0.53e-3 : 0.98e-3;  // per padded pair, one right-hand side
+  // the FP32 rotation M2L up to p = 16 fits two blocks per CU; the FP64 one
+  // above p = 16 takes 32 columns per batch
+  double c_v = p > 16 ? 2.55 * S / S21 : 0.94 * S / S16;
+  if (!mixed) c_v *= p > 16 ? 2.15 : 1.65;
+  const double c_box = 30.0 * (T / T21) * (T / T21);
+  const double c_leaf = 27.0 * T / T21;
+  const double c_x = 0.075 * T / T21, c_w = 0.09 * T / T21;
+  const double far = B.lists[rpy::LV].len * c_v + nbox * c_box + nleaf * c_leaf + xpairs * c_x + weval * c_w;
+  // passes of 4 right-hand sides, then 2 and 1, as rpy_matvec runs them
+  const int r = std::max(nrhs, 1);
+  const int n4 = r / 4, n2 = (r % 4) / 2, n1 = r % 2;
+  const double near_passes = n4 * 2.3 + n2 * 1.5 + n1;
+  out->ns = pairs * c_pair * near_passes + 4.0 * r * far;
   out->same_lo = lo;
   out->same_hi = hi;
   out->adaptive = adaptive;
@@ -261,7 +280,9 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (opt) {
     if (opt->struct_size < offsetof(rpy_options, stream) + sizeof(void*))
       return fail(RPY_EINVAL, "options.struct_size too small");
-    std::memcpy(&o, opt, sizeof(rpy_options));
+    // fields past the caller's struct_size keep their defaults
+    std::memcpy(&o, opt, std::min<size_t>(opt->struct_size, sizeof(rpy_options)));
+    o.struct_size = sizeof(rpy_options);
   }
   if (o.precision != RPY_PREC_FP64 && o.precision != RPY_PREC_MIXED)
     return fail(RPY_EINVAL, "unknown precision");
@@ -269,6 +290,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.leaf_size < 0) return fail(RPY_EINVAL, "leaf_size must be >= 0");
   if (o.max_depth == 0) o.max_depth = 14;
   if (o.max_depth < 1 || o.max_depth > 21) return fail(RPY_EINVAL, "max_depth must be 1..21");
+  if (o.nrhs < 0) return fail(RPY_EINVAL, "nrhs must be >= 0");
   if (o.m2l_mode < 0 || o.m2l_mode > 2) return fail(RPY_EINVAL, "m2l_mode must be 0, 1 or 2");
 
   rpy_plan_t* P = new rpy_plan_t();
@@ -312,7 +334,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       ba.skip_o = true;
       rc = rpy::build_tree(ba, &Bc, &err);
       TreeCost tc;
-      if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, &tc);
+      if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, o.nrhs, &tc);
       if (rc != 0) {
         rpy::free_built(&Bc);
         break;

@@ -52,5 +52,17 @@ def test_host_validation_without_gpu():
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
     o = R.make_options(max_depth=30)
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    o = R.make_options(nrhs=-1)
+    assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    assert b"nrhs" in L.rpy_last_error()
+    # a caller whose struct ends at `stream` (struct_size = offset of nrhs):
+    # the field past it is not read, so its garbage value is not rejected
+    o = R.make_options(order=99, nrhs=-7)
+    o.struct_size = R.rpy_options.nrhs.offset
+    assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    assert b"nrhs" not in L.rpy_last_error()
+    o.struct_size = R.rpy_options.stream.offset
+    assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    assert b"struct_size" in L.rpy_last_error()
     L.rpy_plan_free(None)  # NULL-safe
     assert L.rpy_status_string(R.RPY_ENONFINITE) == b"non-finite position"

@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 def _run(w, precision, counts=None):
     import paper_1711_02976_amd as R
     torch = torch_cuda()
-    P = R.Plan(to_dev(w.pos), w.a, w.eta, w.eps, precision=precision, max_depth=w.max_depth, counts=counts)
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, w.eps, precision=precision, max_depth=w.max_depth, counts=counts,
+               nrhs=w.forces.shape[0])
     try:
         F = to_dev(w.forces)
         U = P.matvec(F)
