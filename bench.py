@@ -5,7 +5,9 @@
 
 A step is one full matvec (tree reused): permute, near field (P2P + overlap
 correction), S->M, M->M, M->L, S->L, L->L, target evaluation (eq. 2.8) and
-un-permute, over device-resident forces.  Prints one JSON line with the
+un-permute, over device-resident forces.  After the timed region each form
+also draws Brownian displacement directions D^{1/2} z once (rpy_sqrt_matvec,
+z = the force vectors), reported under "brownian".  Prints one JSON line with the
 metric, the live roofline of the dominant kernel (HIP events around each
 phase inside the timed region) and the FP64 CPU oracle timed on a bounded
 sample of the same workload (which also gates the accuracy).
@@ -126,9 +128,23 @@ def run(args):
         P.matvec(F, out=U)
         tms = P.timings()
         P.set_timing(False)
+        # Brownian displacement directions D^{1/2} z by the Lanczos recurrence
+        # (rpy_sqrt_matvec), z = the standard-normal force vectors; skipped
+        # when the iteration cap would take more than about 20 s
+        brown = None
+        if args.brownian_tol > 0 and ms * args.brownian_iters <= 20e3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = P.sqrt_matvec(F, tol=args.brownian_tol, max_iter=args.brownian_iters)
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - t0) * 1e3
+            brown = {"tol": args.brownian_tol, "max_iter": args.brownian_iters, "nrhs": w.nrhs, **info,
+                     "ms": round(bms, 3), "ms_per_iteration": round(bms / max(info["iterations"], 1), 4)}
+            progress(f"{w.name} {prec}: sqrt_matvec {info['iterations']} steps, {bms:.1f} ms, "
+                     f"converged={info['converged']}")
         nrc = 4 if w.nrhs >= 4 else (2 if w.nrhs >= 2 else 1)
         alg = algorithmic_counts(P, st["order"], nrc)
-        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "serial": tms, "alg": alg,
+        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "serial": tms, "alg": alg, "brownian": brown,
                          "u": U[:, w.sample].cpu().numpy()}
 
     # CPU baseline: the FP64 oracle's direct sum on the sampled targets.
@@ -193,7 +209,7 @@ def run(args):
         "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "phases_serial_ms": {k: round(v, 4) for k, v in r["serial"]["ms"].items()},
         "forms": {p: {"ms_per_step": round(q["ms"], 4), "value": w.n * w.nrhs / (q["ms"] * 1e-3),
-                      "rel_l2_vs_direct": errs.get(p)} for p, q in results.items()},
+                      "rel_l2_vs_direct": errs.get(p), "brownian": q["brownian"]} for p, q in results.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -278,6 +294,9 @@ def main():
     ap.add_argument("--workload", default="cube-1M", choices=sorted(WORKLOADS))
     ap.add_argument("--precisions", default="fp64,mixed", help="comma list of forms to time: fp64,mixed")
     ap.add_argument("--leaf-size", type=int, default=0)
+    ap.add_argument("--brownian-tol", type=float, default=1e-3,
+                    help="after the timed matvecs, one rpy_sqrt_matvec at this tolerance (0: skip)")
+    ap.add_argument("--brownian-iters", type=int, default=60, help="iteration cap of that call")
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--cpu-targets", type=int, default=12000,
                     help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate)")

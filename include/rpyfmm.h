@@ -120,6 +120,41 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
  * stream reaches this call's end. */
 rpy_status rpy_matvec(rpy_plan_t* plan, int32_t nrhs, const double* forces, double* velocities);
 
+/* Brownian displacement vectors (Sec. 1, the Ermak-McCammon step): the
+ * random displacements have covariance 2 D dt, so each is sqrt(2 dt) D^{1/2} z
+ * for a standard normal z.  This computes y = D^{1/2} z, D the plan's
+ * mobility (kB T = 1), by the Lanczos approximation from the Krylov space
+ * {D^k z} (Sec. 1: D^{1/2} z approximated from the vectors D^k z), using only
+ * rpy_matvec:
+ *   beta_0 = |z|, v_0 = z / beta_0; per step k: w = D v_k, orthogonalised
+ *   against v_0..v_k twice (classical Gram-Schmidt), alpha_k the v_k
+ *   component, beta_{k+1} = |w|, v_{k+1} = w / beta_{k+1};
+ *   y_k = beta_0 V_k T_k^{1/2} e_1, T_k the tridiagonal (alpha, beta) matrix,
+ *   its square root from its eigen-decomposition (negative Ritz values,
+ *   possible only through far-field error, are taken as 0).
+ * No preconditioner is applied.  A right-hand side stops when
+ * |y_k - y_{k-1}| <= tol |y_k| (the basis is orthonormal, so this is read off
+ * the coefficients) or when beta_{k+1} vanishes; all right-hand sides share
+ * the matvecs, nrhs at a time.
+ *   z         device [nrhs][n][3] FP64, caller bead order; read only.
+ *   y         device [nrhs][n][3] FP64; overwritten.  y may not alias z.
+ *   tol       relative change at which to stop, in (0, 1).
+ *   max_iter  most matvecs per right-hand side, 1..100.
+ *   info      nullable host struct, filled on return.
+ * Synchronous: it waits on the plan's stream after every step (a few
+ * doubles cross to the host per step).  The plan keeps a workspace of
+ * (max_iter + 2) nrhs 3n doubles after the first call (RPY_ENOMEM if it
+ * cannot).  Not converging within max_iter is not an error: info says so. */
+typedef struct {
+  int32_t iterations;  /* matvecs applied (steps of the recurrence) */
+  int32_t converged;   /* 1 if every right-hand side met tol */
+  double rel_change;   /* largest last relative change over the right-hand sides */
+  double min_ritz;     /* smallest Ritz value at the last step over the right-hand sides */
+} rpy_sqrt_info_t;
+
+rpy_status rpy_sqrt_matvec(rpy_plan_t* plan, int32_t nrhs, const double* z, double* y, double tol,
+                           int32_t max_iter, rpy_sqrt_info_t* info);
+
 /* Sizes and settings of a plan (host struct). */
 rpy_status rpy_plan_stats(const rpy_plan_t* plan, rpy_plan_stats_t* out);
 

@@ -62,6 +62,7 @@ def lib():
                               C.c_int, C.c_int, _dp, C.c_int]
         L.orc_fmm.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
+        L.orc_rpy_dense.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
         _lib = L
     return _lib
 
@@ -99,6 +100,34 @@ def rpy_direct(pos, forces, a, eta, targets=None, nthreads=0):
     out = np.zeros((nrhs, nt, 3))
     lib().orc_rpy_direct(n, pos, nrhs, F, a, eta, nt, tp, out, nthreads)
     return out[0] if squeeze else out
+
+
+def rpy_dense(pos, a, eta):
+    """Dense 3n x 3n RPY mobility matrix D (Sec. 1, RPY block equations)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    out = np.zeros((3 * n, 3 * n))
+    lib().orc_rpy_dense(n, pos, a, eta, out)
+    return out
+
+
+def rpy_sqrt(pos, z, a, eta):
+    """Brownian displacement directions y = D^{1/2} z (Sec. 1: the random
+    displacements of the Ermak-McCammon step have covariance 2 D dt), with
+    D^{1/2} = Q diag(sqrt(lambda)) Q^T from numpy's symmetric eigensolver on
+    the dense D.  z [nrhs, n, 3] or [n, 3]; returns the same shape.  Raises
+    if D is not positive definite (the RPY tensor is, for any positions)."""
+    Z = _f64(z)
+    squeeze = Z.ndim == 2
+    if squeeze:
+        Z = Z[None]
+    n = Z.shape[1]
+    lam, Q = np.linalg.eigh(rpy_dense(pos, a, eta))
+    if lam.min() <= 0.0:
+        raise ValueError(f"mobility matrix not positive definite (smallest eigenvalue {lam.min():.3e})")
+    Y = (Q * np.sqrt(lam)) @ (Q.T @ Z.reshape(Z.shape[0], 3 * n).T)
+    Y = Y.T.reshape(Z.shape)
+    return Y[0] if squeeze else Y
 
 
 def far_four_laplace(pos, forces, a, eta, centers=None, nthreads=0):

@@ -18,6 +18,9 @@
  *       (Sec. 4.2, "threshold") and the adaptive-FMM interaction lists
  *       U, V, W, X (+ O for overlapping pairs outside U), by brute force over
  *       boxes from their definitions.
+ *   O5  orc_rpy_dense                    -- the dense 3N x 3N mobility matrix D
+ *       (Sec. 1), whose symmetric square root the Python wrapper applies to
+ *       give Brownian displacements D^{1/2} z (Sec. 1, Ermak-McCammon step).
  *   O4  orc_fmm                          -- the four-Laplace adaptive FMM with
  *       expansions in the paper's normalisation (Sec. 2, multipole/local
  *       expansion forms and Y_n^m), derivatives at targets by Theorem 1 (M)
@@ -123,6 +126,23 @@ void orc_rpy_direct(int64_t n, const double* pos, int nrhs, const double* F, dou
       for (int k = 0; k < 3; ++k) out[((size_t)r * nt + ti) * 3 + k] = s[k] + c[k];
     }
   }
+}
+
+/* ------------------------------------------------------------------ O5 --- */
+
+/* D[3i + k][3j + l] = M(r_i - r_j)[k][l] for all bead pairs, self blocks
+ * included (Sec. 1).  out holds (3n)^2 doubles, row-major. */
+void orc_rpy_dense(int64_t n, const double* pos, double a, double eta, double* out) {
+  const int64_t L = 3 * n;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1], pos[3 * i + 2] - pos[3 * j + 2]};
+      double M[9];
+      orc_rpy_block(d, a, eta, M);
+      for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) out[(3 * i + k) * L + 3 * j + l] = M[3 * k + l];
+    }
 }
 
 /* ------------------------------------------------------------------ O2 --- */

@@ -44,6 +44,11 @@ class rpy_timings_t(C.Structure):
     _fields_ = [("ms", C.c_double * len(PHASES)), ("launches", C.c_int64 * len(PHASES)), ("passes", C.c_int64)]
 
 
+class rpy_sqrt_info_t(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_change", C.c_double),
+                ("min_ritz", C.c_double)]
+
+
 class RpyError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
@@ -52,7 +57,7 @@ class RpyError(RuntimeError):
 
 _lib = None
 
-EXPORTED = ("rpy_default_options", "rpy_plan", "rpy_plan_batched", "rpy_matvec", "rpy_plan_stats",
+EXPORTED = ("rpy_default_options", "rpy_plan", "rpy_plan_batched", "rpy_matvec", "rpy_sqrt_matvec", "rpy_plan_stats",
             "rpy_plan_export", "rpy_plan_set_timing", "rpy_plan_timings", "rpy_plan_free",
             "rpy_status_string", "rpy_last_error")
 
@@ -73,6 +78,9 @@ def lib():
         L.rpy_plan_batched.restype = C.c_int
         L.rpy_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.rpy_matvec.restype = C.c_int
+        L.rpy_sqrt_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                                      C.POINTER(rpy_sqrt_info_t)]
+        L.rpy_sqrt_matvec.restype = C.c_int
         L.rpy_plan_stats.argtypes = [C.c_void_p, C.POINTER(rpy_plan_stats_t)]
         L.rpy_plan_stats.restype = C.c_int
         L.rpy_plan_export.argtypes = [C.c_void_p] + [C.c_void_p] * 5
@@ -131,6 +139,13 @@ def rpy_plan_batched(counts, positions_ptr, a, eta, eps, options=None):
 
 def rpy_matvec(plan, nrhs, forces_ptr, velocities_ptr):
     _check(lib().rpy_matvec(plan, int(nrhs), forces_ptr, velocities_ptr))
+
+
+def rpy_sqrt_matvec(plan, nrhs, z_ptr, y_ptr, tol, max_iter):
+    info = rpy_sqrt_info_t()
+    _check(lib().rpy_sqrt_matvec(plan, int(nrhs), z_ptr, y_ptr, float(tol), int(max_iter), C.byref(info)))
+    return {"iterations": info.iterations, "converged": bool(info.converged), "rel_change": info.rel_change,
+            "min_ritz": info.min_ritz}
 
 
 def rpy_plan_stats(plan):
@@ -229,6 +244,24 @@ class Plan:
         with torch.cuda.device(self.device):
             rpy_matvec(self.handle, F.shape[0], F.data_ptr(), out.data_ptr())
         return out[0] if squeeze else out
+
+    def sqrt_matvec(self, z, tol=1e-6, max_iter=50, out=None):
+        """y = D^{1/2} z (Lanczos, rpy_sqrt_matvec).  z: float64 CUDA tensor
+        [nrhs, n, 3] or [n, 3].  Returns (y, info)."""
+        import torch
+        if not (z.is_cuda and z.dtype == torch.float64):
+            raise TypeError("z must be a float64 CUDA tensor")
+        Z = z.contiguous()
+        squeeze = Z.dim() == 2
+        if squeeze:
+            Z = Z.unsqueeze(0)
+        if Z.shape[1:] != (self.n, 3):
+            raise ValueError(f"z must have shape [nrhs, {self.n}, 3]")
+        if out is None:
+            out = torch.empty_like(Z)
+        with torch.cuda.device(self.device):
+            info = rpy_sqrt_matvec(self.handle, Z.shape[0], Z.data_ptr(), out.data_ptr(), tol, max_iter)
+        return (out[0] if squeeze else out), info
 
     def stats(self):
         return rpy_plan_stats(self.handle)

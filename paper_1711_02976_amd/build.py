@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librpyfmm.so")
-SOURCES = ["tree.hip", "fmm.hip", "p2e.hip", "eval.hip", "m2l_rot.hip", "nearfield.hip", "api.hip"]
+SOURCES = ["tree.hip", "fmm.hip", "p2e.hip", "eval.hip", "m2l_rot.hip", "nearfield.hip", "krylov.hip", "api.hip"]
 ARCH = os.environ.get("RPYFMM_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -158,6 +158,9 @@ struct rpy_plan_s {
   double2* DL = nullptr;  // evaluation sets (local expansions of the leaves)
   double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
   int64_t ws_bytes = 0;
+  // Krylov workspace (rpy_sqrt_matvec), grown on demand
+  double* kbuf = nullptr;
+  int64_t kbuf_doubles = 0;
   double plan_ms = 0;
   // per-phase timing
   int timing = 0;
@@ -460,6 +463,179 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   return RPY_OK;
 }
 
+rpy_status rpy_sqrt_matvec(rpy_plan_t* P, int32_t nrhs, const double* z, double* y, double tol, int32_t max_iter,
+                           rpy_sqrt_info_t* info) {
+  if (info) *info = rpy_sqrt_info_t{0, 0, 0.0, 0.0};
+  if (!P) return fail(RPY_EINVAL, "plan is NULL");
+  if (P->sticky) return fail(RPY_EDEVICE, "plan is in an error state from an earlier HIP failure");
+  if (nrhs < 1 || nrhs > 65535) return fail(RPY_EINVAL, "nrhs must be 1..65535");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(RPY_EINVAL, "tol must be in (0, 1)");
+  if (max_iter < 1 || max_iter > 100) return fail(RPY_EINVAL, "max_iter must be 1..100");
+  if (P->B.n == 0) {
+    if (info) info->converged = 1;
+    return RPY_OK;
+  }
+  if (!z || !y) return fail(RPY_EINVAL, "z or y is NULL");
+  if (z == y) return fail(RPY_EINVAL, "y may not alias z");
+  const int64_t L = 3 * P->B.n;
+  const int kcap = max_iter + 1;
+  const int64_t set = (int64_t)nrhs * L;
+  const int64_t npart = rpy::krylov_part_doubles(L, kcap, nrhs);
+  // basis [kcap][nrhs][L], w [nrhs][L], partial sums, 3 coefficient blocks [nrhs][kcap], scales [nrhs]
+  const int64_t need = kcap * set + set + npart + 3 * (int64_t)nrhs * kcap + nrhs;
+  hipStream_t st = P->stream;
+  if (P->kbuf_doubles < need) {
+    if (P->kbuf) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(P->kbuf);
+    }
+    P->kbuf = nullptr;
+    P->kbuf_doubles = 0;
+    if (hipMalloc(&P->kbuf, sizeof(double) * need) != hipSuccess) {
+      (void)hipGetLastError();
+      P->kbuf = nullptr;
+      return fail(RPY_ENOMEM, "cannot allocate the Krylov workspace");
+    }
+    P->kbuf_doubles = need;
+  }
+  double* V = P->kbuf;
+  double* W = V + kcap * set;
+  double* part = W + set;
+  double* cA = part + npart;
+  double* cB = cA + (int64_t)nrhs * kcap;
+  double* cF = cB + (int64_t)nrhs * kcap;
+  double* sc = cF + (int64_t)nrhs * kcap;
+  auto dev = [&](hipError_t he) {
+    if (he != hipSuccess) {
+      (void)hipGetLastError();
+      P->sticky = 1;
+      return fail(RPY_EDEVICE, std::string("Krylov step failed: ") + hipGetErrorString(he));
+    }
+    return RPY_OK;
+  };
+  std::vector<double> hA((size_t)nrhs * kcap), hB((size_t)nrhs * kcap), hs(nrhs);
+  auto fetch = [&](const double* d, std::vector<double>& h) {
+    hipError_t he = hipMemcpyAsync(h.data(), d, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    return he;
+  };
+  // beta_0 = |z|, v_0 = z / beta_0
+  rpy_status rs = dev(rpy::krylov_mdot(z, 0, 1, z, L, nrhs, kcap, part, cA, st));
+  if (rs == RPY_OK) rs = dev(fetch(cA, hA));
+  if (rs != RPY_OK) return rs;
+  std::vector<double> beta0(nrhs);
+  for (int r = 0; r < nrhs; ++r) {
+    beta0[r] = std::sqrt(std::max(hA[(size_t)r * kcap], 0.0));
+    hs[r] = beta0[r] > 0.0 ? 1.0 / beta0[r] : 0.0;
+  }
+  rs = dev(hipMemcpyAsync(sc, hs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+  if (rs == RPY_OK) rs = dev(rpy::krylov_comb(nullptr, 0, 0, kcap, cA, 1.0, z, 1.0, sc, L, nrhs, V, st));
+  if (rs != RPY_OK) return rs;
+
+  // per right-hand side: tridiagonal entries, coefficients of y in the basis
+  std::vector<std::vector<double>> alpha(nrhs), beta(nrhs), f(nrhs);
+  std::vector<int> done(nrhs, 0);
+  std::vector<double> change(nrhs, 0.0), ritz(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    if (beta0[r] == 0.0) done[r] = 1;  // y = 0
+  int steps = 0, used = 1;
+  for (int k = 0; k < max_iter; ++k) {
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) all = all && done[r];
+    if (all) break;
+    const double* vk = V + k * set;
+    rs = rpy_matvec(P, nrhs, vk, W);
+    if (rs != RPY_OK) return rs;
+    steps = k + 1;
+    // two passes of classical Gram-Schmidt against v_0..v_k
+    rs = dev(rpy::krylov_mdot(V, set, k + 1, W, L, nrhs, kcap, part, cA, st));
+    if (rs == RPY_OK) rs = dev(rpy::krylov_comb(V, set, k + 1, kcap, cA, -1.0, W, 1.0, nullptr, L, nrhs, W, st));
+    if (rs == RPY_OK) rs = dev(rpy::krylov_mdot(V, set, k + 1, W, L, nrhs, kcap, part, cB, st));
+    if (rs == RPY_OK) rs = dev(rpy::krylov_comb(V, set, k + 1, kcap, cB, -1.0, W, 1.0, nullptr, L, nrhs, W, st));
+    if (rs == RPY_OK) rs = dev(fetch(cA, hA));
+    if (rs == RPY_OK) rs = dev(fetch(cB, hB));
+    // |w|^2 into cF's first column
+    if (rs == RPY_OK) rs = dev(rpy::krylov_mdot(W, 0, 1, W, L, nrhs, kcap, part, cF, st));
+    std::vector<double> hn((size_t)nrhs * kcap);
+    if (rs == RPY_OK) rs = dev(fetch(cF, hn));
+    if (rs != RPY_OK) return rs;
+    for (int r = 0; r < nrhs; ++r) {
+      if (done[r]) continue;
+      const double a = hA[(size_t)r * kcap + k] + hB[(size_t)r * kcap + k];
+      const double b = std::sqrt(std::max(hn[(size_t)r * kcap], 0.0));
+      alpha[r].push_back(a);
+      beta[r].push_back(b);
+      // T_k = tridiag(beta_1..beta_k; alpha_0..alpha_k; beta_1..beta_k)
+      const int m = k + 1;
+      std::vector<double> T((size_t)m * m, 0.0), lam, Q;
+      for (int i = 0; i < m; ++i) {
+        T[(size_t)i * m + i] = alpha[r][i];
+        if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[r][i];
+      }
+      rpy::sym_eig(m, T, lam, Q);
+      // y = beta_0 V Q sqrt(Lambda) Q^T e_1
+      std::vector<double> g(m, 0.0);
+      double lmin = lam[0], lmax = 0.0;
+      for (int q = 0; q < m; ++q) {
+        lmin = std::min(lmin, lam[q]);
+        lmax = std::max(lmax, std::fabs(lam[q]));
+        const double w = std::sqrt(std::max(lam[q], 0.0)) * Q[q];  // Q[0][q] = e_1 . column q
+        for (int i = 0; i < m; ++i) g[i] += Q[(size_t)i * m + q] * w;
+      }
+      double dn = 0.0, gn = 0.0;
+      for (int i = 0; i < m; ++i) {
+        g[i] *= beta0[r];
+        const double prev = i < (int)f[r].size() ? f[r][i] : 0.0;
+        dn += (g[i] - prev) * (g[i] - prev);
+        gn += g[i] * g[i];
+      }
+      change[r] = k == 0 ? 1.0 : (gn > 0.0 ? std::sqrt(dn / gn) : 0.0);
+      ritz[r] = lmin;
+      f[r] = g;
+      used = std::max(used, m);
+      // converged, or the Krylov space is exhausted (D v_k lies in the span)
+      if ((k > 0 && change[r] <= tol) || b <= 1e-14 * std::max(lmax, 1e-300)) done[r] = 1;
+    }
+    bool fin = true;
+    for (int r = 0; r < nrhs; ++r) fin = fin && done[r];
+    if (fin || k + 1 == max_iter) break;
+    // v_{k+1} = w / beta_{k+1} (zero for the right-hand sides that are done)
+    for (int r = 0; r < nrhs; ++r) {
+      const double b = beta[r].empty() ? 0.0 : beta[r].back();
+      hs[r] = (!done[r] && b > 0.0) ? 1.0 / b : 0.0;
+    }
+    rs = dev(hipMemcpyAsync(sc, hs.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    if (rs == RPY_OK) rs = dev(rpy::krylov_comb(nullptr, 0, 0, kcap, cA, 1.0, W, 1.0, sc, L, nrhs, V + (k + 1) * set, st));
+    if (rs == RPY_OK) rs = dev(hipStreamSynchronize(st));  // hs is reused next step
+    if (rs != RPY_OK) return rs;
+  }
+  // y = sum_j f_j v_j
+  std::vector<double> hf((size_t)nrhs * kcap, 0.0);
+  for (int r = 0; r < nrhs; ++r)
+    for (size_t i = 0; i < f[r].size(); ++i) hf[(size_t)r * kcap + i] = f[r][i];
+  rs = dev(hipMemcpyAsync(cF, hf.data(), sizeof(double) * hf.size(), hipMemcpyHostToDevice, st));
+  if (rs == RPY_OK) rs = dev(rpy::krylov_comb(V, set, used, kcap, cF, 1.0, nullptr, 0.0, nullptr, L, nrhs, y, st));
+  if (rs == RPY_OK) rs = dev(hipStreamSynchronize(st));
+  if (rs != RPY_OK) return rs;
+  if (info) {
+    info->iterations = steps;
+    int conv = 1;
+    double ch = 0.0, rm = 0.0;
+    bool first = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (beta0[r] == 0.0) continue;
+      conv = conv && done[r];
+      ch = std::max(ch, change[r]);
+      rm = first ? ritz[r] : std::min(rm, ritz[r]);
+      first = false;
+    }
+    info->converged = conv;
+    info->rel_change = ch;
+    info->min_ritz = rm;
+  }
+  return RPY_OK;
+}
+
 rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   if (!P || !out) return fail(RPY_EINVAL, "NULL argument");
   std::memset(out, 0, sizeof(*out));
@@ -550,6 +726,7 @@ void rpy_plan_free(rpy_plan_t* P) {
   if (P->near) (void)hipStreamDestroy(P->near);
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   free_ws(P);
+  if (P->kbuf) (void)hipFree(P->kbuf);
   rpy::free_tables(&P->tb);
   if (P->tiles.t) (void)hipFree(P->tiles.t);
   if (P->tiles.box) (void)hipFree(P->tiles.box);

@@ -133,4 +133,18 @@ int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int6
 // Writes the far-field velocities of every bead (assigns; sorted SoA).
 hipError_t run_eval(const Launch& l, const EvalPlan& ep, int nrc, Exp e, double* u);
 
+// Krylov building blocks (krylov.hip).  Vector sets are [nrhs][L]; the j-th
+// of a family of sets starts at V + j * vstride.  krylov_mdot writes
+// out[r * kcap + j] = V_j[r] . w[r] for j < k (deterministic order; part
+// holds krylov_part_doubles(L, kcap, nrhs) doubles).  krylov_comb writes
+// out[r] = s[r] * (a w[r] + sgn sum_{j<k} coef[r * kcap + j] V_j[r]) (s may
+// be null = 1, w may be null, out may alias w).
+int64_t krylov_part_doubles(int64_t L, int kcap, int nrhs);
+hipError_t krylov_mdot(const double* V, int64_t vstride, int k, const double* w, int64_t L, int nrhs, int kcap,
+                       double* part, double* out, hipStream_t st);
+hipError_t krylov_comb(const double* V, int64_t vstride, int k, int kcap, const double* coef, double sgn,
+                       const double* w, double a, const double* s, int64_t L, int nrhs, double* out, hipStream_t st);
+// Eigen-decomposition of a small symmetric matrix (host, Jacobi rotations).
+void sym_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Q);
+
 }  // namespace rpy

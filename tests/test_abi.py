@@ -47,6 +47,10 @@ def test_host_validation_without_gpu():
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 0.5, None) == R.RPY_EINVAL
     assert L.rpy_plan(C.byref(h), -1, C.c_void_p(8), 0.5, 1.0, 1e-6, None) == R.RPY_EINVAL
     assert L.rpy_matvec(None, 1, None, None) == R.RPY_EINVAL
+    info = R.rpy_sqrt_info_t()
+    info.iterations = 77
+    assert L.rpy_sqrt_matvec(None, 1, None, None, 1e-6, 10, C.byref(info)) == R.RPY_EINVAL
+    assert info.iterations == 0 and b"plan" in L.rpy_last_error()
     assert b"plan" in L.rpy_last_error()
     o = R.make_options(order=99)
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
