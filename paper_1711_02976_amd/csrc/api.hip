@@ -567,12 +567,8 @@ rpy_status rpy_sqrt_matvec(rpy_plan_t* P, int32_t nrhs, const double* z, double*
       beta[r].push_back(b);
       // T_k = tridiag(beta_1..beta_k; alpha_0..alpha_k; beta_1..beta_k)
       const int m = k + 1;
-      std::vector<double> T((size_t)m * m, 0.0), lam, Q;
-      for (int i = 0; i < m; ++i) {
-        T[(size_t)i * m + i] = alpha[r][i];
-        if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = beta[r][i];
-      }
-      rpy::sym_eig(m, T, lam, Q);
+      std::vector<double> lam, Q;
+      rpy::tridiag_eig(m, alpha[r], beta[r], lam, Q);
       // y = beta_0 V Q sqrt(Lambda) Q^T e_1
       std::vector<double> g(m, 0.0);
       double lmin = lam[0], lmax = 0.0;

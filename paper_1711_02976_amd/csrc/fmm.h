@@ -144,7 +144,9 @@ hipError_t krylov_mdot(const double* V, int64_t vstride, int k, const double* w,
                        double* part, double* out, hipStream_t st);
 hipError_t krylov_comb(const double* V, int64_t vstride, int k, int kcap, const double* coef, double sgn,
                        const double* w, double a, const double* s, int64_t L, int nrhs, double* out, hipStream_t st);
-// Eigen-decomposition of a small symmetric matrix (host, Jacobi rotations).
-void sym_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Q);
+// Eigen-decomposition of a symmetric tridiagonal matrix (host, implicit QL):
+// diagonal d[0..m), off-diagonal e[0..m-1); Q column q = eigenvector q.
+void tridiag_eig(int m, const std::vector<double>& d, const std::vector<double>& e, std::vector<double>& lam,
+                 std::vector<double>& Q);
 
 }  // namespace rpy

@@ -98,48 +98,64 @@ hipError_t krylov_comb(const double* V, int64_t vstride, int k, int kcap, const 
 }
 
 // Eigenvalues lam[m] and orthonormal eigenvectors Q (column q in Q[i * m + q])
-// of a symmetric m x m matrix A (row-major; destroyed), by cyclic Jacobi
-// rotations until the off-diagonal part is negligible.
-void sym_eig(int m, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& Q) {
+// of the symmetric tridiagonal matrix with diagonal d[0..m) and
+// off-diagonal e[0..m-1) (e[i] couples i and i + 1), by the implicit QL
+// method: each sweep applies a Wilkinson-shifted QL step to the unreduced
+// block [l, k] as a chain of plane rotations from the bottom up, and the
+// rotations are accumulated into Q.  O(m^2) per eigenvalue.
+void tridiag_eig(int m, const std::vector<double>& d, const std::vector<double>& e, std::vector<double>& lam,
+                 std::vector<double>& Q) {
+  lam.assign(d.begin(), d.begin() + m);
+  std::vector<double> off(m, 0.0);
+  for (int i = 0; i + 1 < m; ++i) off[i] = e[i];
   Q.assign((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) Q[(size_t)i * m + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < m; ++i)
-      for (int j = 0; j < m; ++j) {
-        const double v = A[(size_t)i * m + j] * A[(size_t)i * m + j];
-        tot += v;
-        if (i != j) off += v;
+  for (int l = 0; l < m; ++l) {
+    for (int it = 0; it < 64; ++it) {
+      // first negligible coupling at or below l: the block [l, k] is unreduced
+      int k = l;
+      for (; k + 1 < m; ++k) {
+        const double dd = std::fabs(lam[k]) + std::fabs(lam[k + 1]);
+        if (std::fabs(off[k]) <= 1e-16 * dd) break;
       }
-    if (off <= 1e-32 * tot || off == 0.0) break;
-    for (int p = 0; p < m - 1; ++p)
-      for (int q = p + 1; q < m; ++q) {
-        const double apq = A[(size_t)p * m + q];
-        if (apq == 0.0) continue;
-        const double app = A[(size_t)p * m + p], aqq = A[(size_t)q * m + q];
-        // rotation angle that zeroes A[p][q]: tan(2 phi) = 2 apq / (aqq - app)
-        const double th = (aqq - app) / (2.0 * apq);
-        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < m; ++k) {
-          const double akp = A[(size_t)k * m + p], akq = A[(size_t)k * m + q];
-          A[(size_t)k * m + p] = c * akp - s * akq;
-          A[(size_t)k * m + q] = s * akp + c * akq;
+      if (k == l) break;
+      // Wilkinson shift from the leading 2x2 of the block
+      double g = (lam[l + 1] - lam[l]) / (2.0 * off[l]);
+      double r = std::hypot(g, 1.0);
+      g = lam[k] - lam[l] + off[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = k - 1;
+      bool split = false;
+      for (; i >= l; --i) {
+        const double f = s * off[i], b = c * off[i];
+        r = std::hypot(f, g);
+        off[i + 1] = r;
+        if (r == 0.0) {  // the rotation underflowed: the block splits here
+          lam[i + 1] -= p;
+          off[k] = 0.0;
+          split = true;
+          break;
         }
-        for (int k = 0; k < m; ++k) {
-          const double apk = A[(size_t)p * m + k], aqk = A[(size_t)q * m + k];
-          A[(size_t)p * m + k] = c * apk - s * aqk;
-          A[(size_t)q * m + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < m; ++k) {
-          const double qkp = Q[(size_t)k * m + p], qkq = Q[(size_t)k * m + q];
-          Q[(size_t)k * m + p] = c * qkp - s * qkq;
-          Q[(size_t)k * m + q] = s * qkp + c * qkq;
+        s = f / r;
+        c = g / r;
+        g = lam[i + 1] - p;
+        r = (lam[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        lam[i + 1] = g + p;
+        g = c * r - b;
+        for (int q = 0; q < m; ++q) {
+          double* row = &Q[(size_t)q * m];
+          const double t = row[i + 1];
+          row[i + 1] = s * row[i] + c * t;
+          row[i] = c * row[i] - s * t;
         }
       }
+      if (split) continue;
+      lam[l] -= p;
+      off[l] = g;
+      off[k] = 0.0;
+    }
   }
-  lam.resize(m);
-  for (int i = 0; i < m; ++i) lam[i] = A[(size_t)i * m + i];
 }
 
 }  // namespace rpy
