@@ -442,13 +442,13 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
     // far field on s0
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev, s0, [&] { return rpy::run_m2m(l, c, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, s0, [&] {
       if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
       return rpy::run_m2l_rot(l, c, e, mixed);
     });
     if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 1 ? nlev - 1 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
+    if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
     // join, then near + far back to caller order
     if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);

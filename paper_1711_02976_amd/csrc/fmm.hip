@@ -571,7 +571,10 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, cons
 hipError_t run_m2m(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
   const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
-  for (int lev = B->depth - 1; lev >= 0; --lev) {
+  // parents down to level 2 only: multipoles at levels 0 and 1 are never
+  // read (V lists start at level 2, and W-list boxes are descendants of a
+  // leaf's colleagues, so they sit at level 2 or deeper)
+  for (int lev = B->depth - 1; lev >= 2; --lev) {
     const int ls = B->level_start[lev], le = B->level_start[lev + 1];
     DISPATCH_ND(nrc, (k_m2m<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
     hipError_t err = hipGetLastError();
@@ -592,7 +595,9 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e) {
 hipError_t run_l2l(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
   const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
-  for (int lev = 2; lev <= B->depth; ++lev) {
+  // children from level 3: local expansions at levels 0 and 1 are zero (no
+  // V or X entries there), so level 2 keeps what M->L and S->L wrote
+  for (int lev = 3; lev <= B->depth; ++lev) {
     const int ls = B->level_start[lev], le = B->level_start[lev + 1];
     DISPATCH_ND(nrc, (k_l2l<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
     hipError_t err = hipGetLastError();
