@@ -308,9 +308,9 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
 // zero coefficient (masked, no branch).  With the prefactor taken out:
 //   A' = oc (1 - 9r/(32a)) - 1/r - (2a^2/3)/r^3,  B' = ob/r - (1 - 2a^2/r^2)/r^3.
 // Most pairs of two such leaves are farther apart than 2a, so the staged
-// sources are cut into groups of 16 with bounding boxes, and a wave skips a
-// group whose box is 2a or more from the box of the wave's own targets.
-constexpr int OV_G = 16;
+// sources are cut into groups of OV_G with bounding boxes, and a wave skips a
+// group whose box is 2a or more from every one of the wave's targets.
+constexpr int OV_G = 8;
 
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const double* tbox, Tree t, List O,
@@ -331,15 +331,8 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
   const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
-  // bounding box of this wave's targets (idle lanes repeat the tile's first bead)
-  R wlo[3] = {xi, yi, zi}, whi[3] = {xi, yi, zi};
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-    for (int o = 1; o < 64; o <<= 1) {
-      wlo[q] = min(wlo[q], __shfl_xor(wlo[q], o));
-      whi[q] = max(whi[q], __shfl_xor(whi[q], o));
-    }
-  // a group is skipped only when its box is clearly 2a away (rounding margin)
+  // a group is skipped only when its box is clearly 2a away (rounding margin);
+  // idle lanes repeat the tile's first bead, so they add no extra groups
   const R skip2 = (R)(four_a2 * (1.0 + 1e-4));
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
@@ -392,13 +385,13 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
       for (int g = 0; g < ng; ++g) {
-        R g2 = 0;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const R d = max((R)0, max(gbox[g][q] - whi[q], wlo[q] - gbox[g][3 + q]));
-          g2 = fma(d, d, g2);
-        }
-        if (!(g2 < skip2)) continue;  // wave-uniform
+        // distance from this lane's target to the group's box; the wave
+        // skips the group when no lane comes within 2a of it
+        const R gx = max((R)0, max(gbox[g][0] - xi, xi - gbox[g][3]));
+        const R gy = max((R)0, max(gbox[g][1] - yi, yi - gbox[g][4]));
+        const R gz = max((R)0, max(gbox[g][2] - zi, zi - gbox[g][5]));
+        const R g2 = fma(gx, gx, fma(gy, gy, gz * gz));
+        if (!__any(g2 < skip2)) continue;  // wave-uniform
         const int s1 = min(g * OV_G + OV_G, ns4);
         for (int s0 = g * OV_G; s0 < s1; s0 += 4)
 #pragma unroll

@@ -3,6 +3,8 @@ direct sum of the oracle (each sampled target summed over every source of
 its system), in the configuration the benchmark uses (library-chosen leaf
 size and order, both precision forms).
 
+  * cube-1M:    1,000,000 uniform beads, one rhs, at both accuracy settings
+                (eps 1e-3 and 1e-6), on 10,000 sampled targets;
   * blobs-4M:   4,000,000 clustered beads (2,000 Gaussian blobs), 4 rhs,
                 adaptive tree with W/X lists and overlapping pairs outside U;
   * batched-64: 64 independent systems of 1e3 .. 2e5 beads, 16 rhs, one plan;
@@ -72,6 +74,23 @@ def test_batched_64(orc, precision):
     log(f"  p={st['order']} s={st['leaf_size']} nbox={st['nbox']} rel-L2 = {err:.3e}")
     assert st["nsys"] == 64
     assert err <= w.eps
+
+
+_cube_ref = {}
+
+
+@pytest.mark.parametrize("precision,eps", [("fp64", 1e-3), ("mixed", 1e-3), ("fp64", 1e-6), ("mixed", 1e-6)])
+def test_cube_1M(orc, precision, eps):
+    import dataclasses
+    w = dataclasses.replace(W.config(2), eps=eps)  # 10,000 sampled targets
+    log(f"{w.name} n={w.n} eps={eps} {precision}")
+    u, st = _run(w, precision)
+    if "ref" not in _cube_ref:
+        _cube_ref["ref"] = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
+    err = orc.rel_l2(u, _cube_ref["ref"])
+    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} rel-L2 = {err:.3e}")
+    assert len(w.sample) == 10_000
+    assert err <= eps
 
 
 def test_cube_15M_mixed(orc):
