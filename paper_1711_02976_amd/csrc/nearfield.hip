@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
 // Most pairs of two such leaves are farther apart than 2a, so the staged
 // sources are cut into groups of OV_G with bounding boxes, and a wave skips a
 // group whose box is 2a or more from every one of the wave's targets.
-constexpr int OV_G = 8;
+constexpr int OV_G = 4;
 
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const double* tbox, Tree t, List O,

@@ -92,6 +92,9 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
     if (e0 == e1) return;
   }
   extern __shared__ double2 Hs[];  // [64][LD]
+  // S->L: the chunk's charges with the fourth one re-centred on this machine,
+  // computed once per bead instead of once per (bead, slot)
+  __shared__ double Qs[LOCAL ? P2E_CHUNK * ND : 1];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int grp = wv % G, sub = wv / G;
@@ -142,6 +145,16 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
         uint64_t ml = ((uint64_t)d.mhi << 32) | d.mlo;
         double2* hw = Hs + lane * LD + wv * K;  // this lane's row, this wave's slots
         __syncthreads();                        // the previous accumulation is done with Hs
+        if (LOCAL && ps == 0 && (int)threadIdx.x < P2E_CHUNK * NRC) {
+          const int bb = threadIdx.x % P2E_CHUNK, r = threadIdx.x / P2E_CHUNK;
+          const double* q = Q + (int64_t)(jc + bb) * ND + 4 * r;
+          const double q0 = q[0], q1 = q[1], q2 = q[2];
+          double* o = Qs + bb * ND + 4 * r;
+          o[0] = q0;
+          o[1] = q1;
+          o[2] = q2;
+          o[3] = fma(q0, wx, fma(q1, wy, fma(q2, wz, q[3])));
+        }
         // conj(h) obeys the same recurrence (real coefficients): generate it directly
         int k = 0;
         while (k < d.nvalid) {
@@ -196,14 +209,11 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
 #pragma unroll
           for (int i = 0; i < BPW; ++i) {
             const int bb = sub * BPW + i;
-            const double* q = Q + (int64_t)(jc + bb) * ND;
+            const double* q = LOCAL ? Qs + bb * ND : Q + (int64_t)(jc + bb) * ND;
             const double2 h = Hs[bb * LD + slot];
 #pragma unroll
             for (int r = 0; r < NRC; ++r) {
-              const double q0 = q[4 * r], q1 = q[4 * r + 1], q2 = q[4 * r + 2];
-              double q3 = q[4 * r + 3];
-              if (LOCAL) q3 = fma(q0, wx, fma(q1, wy, fma(q2, wz, q3)));
-              const double qq[4] = {q0, q1, q2, q3};
+              const double qq[4] = {q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]};
 #pragma unroll
               for (int dd = 0; dd < 4; ++dd) {
                 acc[ps][4 * r + dd].x = fma(qq[dd], h.x, acc[ps][4 * r + dd].x);
