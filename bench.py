@@ -92,6 +92,9 @@ def run(args):
     import workloads as W
 
     w = W.config(WORKLOADS[args.workload], nsample=args.cpu_targets)
+    if args.eps:
+        import dataclasses
+        w = dataclasses.replace(w, eps=args.eps)
     progress(f"{w.name}: {w.n} beads, {w.nrhs} rhs generated")
     dev = torch.device("cuda:0")
     pos = torch.as_tensor(w.pos, device=dev)
@@ -298,6 +301,8 @@ def main():
                     help="after the timed matvecs, one rpy_sqrt_matvec at this tolerance (0: skip)")
     ap.add_argument("--brownian-iters", type=int, default=60, help="iteration cap of that call")
     ap.add_argument("--order", type=int, default=0)
+    ap.add_argument("--eps", type=float, default=0.0,
+                    help="accuracy target in place of the workload's (e.g. 1e-9, the 9-digit setting)")
     ap.add_argument("--cpu-targets", type=int, default=12000,
                     help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")

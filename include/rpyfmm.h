@@ -56,7 +56,8 @@ typedef struct {
                             "threshold"); 0 = chosen by the library: trees
                             are built for limits 64 * 1.5^k and the one with
                             the lowest modelled matvec time is kept */
-  int32_t order;         /* expansion order p; 0 = chosen from eps */
+  int32_t order;         /* expansion order p, 0..27; 0 = chosen from eps.
+                            Above 21 each pass carries one right-hand side */
   int32_t max_depth;     /* deepest tree level, 1..21; 0 = 14 */
   int32_t m2l_mode;      /* multipole-to-local operator: 0 = library choice
                             (rotation), 1 = dense O(p^4) translation,
@@ -96,7 +97,9 @@ void rpy_default_options(rpy_options* opt);
  *   a, eta     bead radius and solvent viscosity, both > 0.
  *   eps        requested relative L2 accuracy of the far field, in
  *              [1e-12, 1e-1]; selects the expansion order when
- *              opt->order == 0 (Sec. 4.3 uses 3, 6 and 9 digits).
+ *              opt->order == 0 (Sec. 4.3 uses 3, 6 and 9 digits; below
+ *              1e-8 the order is the highest built, 27, which reaches
+ *              about 3e-9 on uniform beads).
  *   opt        nullable; NULL means rpy_default_options.
  * Builds, on the GPU: the bounding cube and 63-bit Morton keys, a stable
  * radix sort, the adaptive octree (refine while more than leaf_size beads,

@@ -30,11 +30,14 @@ rpy_status fail(rpy_status s, const std::string& msg) {
 // worse separation ratio: measured on a uniform cube, p = 7 gives 2.2e-4 and
 // p = 16 gives 4.0e-7; on 20k beads in Gaussian blobs p = 12, 16, 20 give
 // 3.2e-5, 2.6e-6 and 2.8e-7, and on 4M beads in 2,000 blobs (depth 11-13)
-// p = 20 gives 1.0e-6 and p = 21 gives 6.8e-7.
+// p = 20 gives 1.0e-6 and p = 21 gives 6.8e-7.  Below 1e-8 (the paper's
+// 9-digit setting) the order is the highest built, 27: on 20k beads in a
+// uniform cube p = 21, 24, 27 give 3.3e-8, 9.0e-9, 2.6e-9, and on 20k
+// clustered beads (adaptive tree) 1.3e-7, 3.1e-8, 7.5e-9.
 int order_for_eps(double eps, bool adaptive) {
   static const double tol[] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7,
-                               3e-8, 1e-8, 1e-9};
-  static const int ord[] = {2, 3, 4, 6, 7, 8, 10, 11, 13, 14, 16, 17, 19, 20, 21, 21};
+                               3e-8, 1e-8};
+  static const int ord[] = {2, 3, 4, 6, 7, 8, 10, 11, 13, 14, 16, 17, 19, 20, 21};
   int p = rpy::MAX_ORDER;
   for (int i = 0; i < (int)(sizeof(tol) / sizeof(tol[0])); ++i)
     if (eps >= tol[i]) {
@@ -289,7 +292,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   }
   if (o.precision != RPY_PREC_FP64 && o.precision != RPY_PREC_MIXED)
     return fail(RPY_EINVAL, "unknown precision");
-  if (o.order < 0 || o.order > rpy::MAX_ORDER) return fail(RPY_EINVAL, "order must be 0..21");
+  if (o.order < 0 || o.order > rpy::MAX_ORDER) return fail(RPY_EINVAL, "order must be 0..27");
   if (o.leaf_size < 0) return fail(RPY_EINVAL, "leaf_size must be >= 0");
   if (o.max_depth == 0) o.max_depth = 14;
   if (o.max_depth < 1 || o.max_depth > 21) return fail(RPY_EINVAL, "max_depth must be 1..21");
@@ -414,6 +417,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   // right-hand sides per pass: 4, 2 or 1, limited by device memory
   const int64_t T = rpy::ncoef(P->p);
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+  if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream};

@@ -10,7 +10,8 @@ namespace rpy {
 
 constexpr int KBITS = 21;            // quantisation bits per axis (63-bit Morton key)
 constexpr int NSLOT = 27;            // colleague slots: offsets in {-1,0,1}^3
-constexpr int MAX_ORDER = 21;        // (p+1)(p+2)/2 <= 253 coefficients per expansion
+constexpr int MAX_ORDER = 27;        // (p+1)(p+2)/2 <= 406 coefficients per expansion
+constexpr int MAX_ORDER_MULTI = 21;  // highest order at which a pass carries 2 or 4 right-hand sides
 constexpr int STACK = 192;           // private DFS stack of the list kernels
 
 __host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }

@@ -387,11 +387,16 @@ __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const doubl
   extern __shared__ double2 sm[];
   double2* Rt = sm;        // F1
   double2* Mc = sm + F1;   // F1
-  double2 acc = make_double2(0, 0);
-  int n = 0, m = 0;
-  if (threadIdx.x < T) {
-    while (tri(n + 1) <= (int)threadIdx.x) ++n;
-    m = threadIdx.x - tri(n);
+  // outputs threadIdx.x and threadIdx.x + TR_T (T exceeds TR_T above order 21)
+  double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+  int nq[2] = {0, 0}, mq[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = threadIdx.x + q * TR_T;
+    if (c < T) {
+      while (tri(nq[q] + 1) <= c) ++nq[q];
+      mq[q] = c - tri(nq[q]);
+    }
   }
   const int dd = d & 3, base = d - dd;
   for (int C = t.child[b]; C < t.child[b] + nc; ++C) {
@@ -416,7 +421,9 @@ __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const doubl
       Mc[f] = make_double2(v.x * sc, v.y * sc);
     }
     __syncthreads();
-    if (threadIdx.x < T) {
+    for (int q = 0; q < 2; ++q) {
+      if (threadIdx.x + q * TR_T >= T) break;
+      const int n = nq[q], m = mq[q];
       // four independent partial sums keep several LDS reads in flight
       double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
       for (int k = 0; k <= n; ++k) {
@@ -426,15 +433,17 @@ __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const doubl
         int l = lmin;
         for (; l + 3 <= lmax; l += 4) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) cfmac(a4[q], Mc[mk + l + q], Rt[rj - (l + q)]);
+          for (int u = 0; u < 4; ++u) cfmac(a4[u], Mc[mk + l + u], Rt[rj - (l + u)]);
         }
         for (; l <= lmax; ++l) cfmac(a4[0], Mc[mk + l], Rt[rj - l]);
       }
-      acc.x += (a4[0].x + a4[1].x) + (a4[2].x + a4[3].x);
-      acc.y += (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y);
+      acc[q].x += (a4[0].x + a4[1].x) + (a4[2].x + a4[3].x);
+      acc[q].y += (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y);
     }
   }
-  if (threadIdx.x < T) M[(int64_t)b * ND * T + d * T + threadIdx.x] = acc;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (threadIdx.x + q * TR_T < T) M[(int64_t)b * ND * T + d * T + threadIdx.x + q * TR_T] = acc[q];
 }
 
 // ------------------------------------------------------------------ L->L --
@@ -469,28 +478,31 @@ __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const doubl
     Lp[f] = v;
   }
   __syncthreads();
-  if (threadIdx.x >= T) return;
-  int k = 0;
-  while (tri(k + 1) <= (int)threadIdx.x) ++k;
-  const int l = threadIdx.x - tri(k);
-  // four independent partial sums keep several LDS reads in flight
-  double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-  for (int n = k; n <= p; ++n) {
-    const int j = n - k;
-    const int mmin = max(-n, l - j), mmax = min(n, l + j);
-    const int ln = fidx(n, 0), rj = fidx(j, -l);  // rj + m >= j*j for m >= mmin
-    int m = mmin;
-    for (; m + 3 <= mmax; m += 4) {
+  // outputs threadIdx.x and threadIdx.x + TR_T (T exceeds TR_T above order 21)
+  for (int c = threadIdx.x; c < T; c += TR_T) {
+    int k = 0;
+    while (tri(k + 1) <= c) ++k;
+    const int l = c - tri(k);
+    // four independent partial sums keep several LDS reads in flight
+    double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    for (int n = k; n <= p; ++n) {
+      const int j = n - k;
+      const int mmin = max(-n, l - j), mmax = min(n, l + j);
+      const int ln = fidx(n, 0), rj = fidx(j, -l);  // rj + m >= j*j for m >= mmin
+      int m = mmin;
+      for (; m + 3 <= mmax; m += 4) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cfma(a4[q], Lp[ln + m + q], Rt[rj + m + q]);
+        for (int q = 0; q < 4; ++q) cfma(a4[q], Lp[ln + m + q], Rt[rj + m + q]);
+      }
+      for (; m <= mmax; ++m) cfma(a4[0], Lp[ln + m], Rt[rj + m]);
     }
-    for (; m <= mmax; ++m) cfma(a4[0], Lp[ln + m], Rt[rj + m]);
+    const double2 acc =
+        make_double2((a4[0].x + a4[1].x) + (a4[2].x + a4[3].x), (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y));
+    const double sc = ldexp(1.0, -(k + 1));
+    double2* out = L + (int64_t)b * ND * T + d * T + c;
+    const double2 v = *out;
+    *out = make_double2(v.x + sc * acc.x, v.y + sc * acc.y);
   }
-  double2 acc = make_double2((a4[0].x + a4[1].x) + (a4[2].x + a4[3].x), (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y));
-  const double sc = ldexp(1.0, -(k + 1));
-  double2* out = L + (int64_t)b * ND * T + d * T + threadIdx.x;
-  const double2 v = *out;
-  *out = make_double2(v.x + sc * acc.x, v.y + sc * acc.y);
 }
 
 // ----------------------------------------------------------- M->L (V) -----
@@ -500,17 +512,18 @@ __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const doubl
 constexpr int M2L_T = 256;
 
 template <int ND>
-__global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, const double2* itab,
+__global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, int c0, Tree t, List V, const double2* itab,
                                                      const double2* M, double2* L) {
-  const int b = blockIdx.x;
+  // outputs c0 .. c0 + M2L_T - 1 (a second launch covers T > M2L_T)
+  const int b = blockIdx.x, c = c0 + threadIdx.x;
   const int T = ncoef(p), F1 = (p + 1) * (p + 1), F2 = (2 * p + 1) * (2 * p + 1);
   extern __shared__ double2 sm[];
   double2* It = sm;            // F2
   double2* Ms = sm + F2;       // ND * F1
   int k = 0, l = 0;
-  if (threadIdx.x < T) {
-    while (tri(k + 1) <= (int)threadIdx.x) ++k;
-    l = threadIdx.x - tri(k);
+  if (c < T) {
+    while (tri(k + 1) <= c) ++k;
+    l = c - tri(k);
   }
   double2 acc[ND];
   for (int d = 0; d < ND; ++d) acc[d] = make_double2(0, 0);
@@ -541,7 +554,7 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, cons
       Ms[d * F1 + f] = v;
     }
     __syncthreads();
-    if (threadIdx.x < T) {
+    if (c < T) {
       for (int n = 0; n <= p; ++n) {
         const int base_i = (n + k) * (n + k) + (n + k) - l;
         const int base_m = n * n + n;
@@ -553,9 +566,9 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, Tree t, List V, cons
       }
     }
   }
-  if (threadIdx.x < T) {
+  if (c < T) {
     const double sg = (l & 1) ? -1.0 : 1.0;
-    double2* out = L + (int64_t)b * ND * T + threadIdx.x;
+    double2* out = L + (int64_t)b * ND * T + c;
     for (int d = 0; d < ND; ++d) out[d * T] = make_double2(sg * acc[d].x, sg * acc[d].y);
   }
 }
@@ -587,8 +600,20 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
   const int p = l.p;
   size_t shm = sizeof(double2) * ((2 * p + 1) * (2 * p + 1) + 4 * nrc * (p + 1) * (p + 1));
-  DISPATCH_ND(nrc, (k_m2l_dense<ND><<<B->tree.nbox, M2L_T, shm, l.s>>>(p, B->tree, B->lists[LV], l.tb->itab, e.M,
-                                                                       e.L)));
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  auto go = [&](auto kern) {
+    hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (he != hipSuccess) return he;
+    for (int c0 = 0; c0 < ncoef(p); c0 += M2L_T)
+      kern<<<B->tree.nbox, M2L_T, shm, l.s>>>(p, c0, B->tree, B->lists[LV], l.tb->itab, e.M, e.L);
+    return hipSuccess;
+  };
+  hipError_t he = hipErrorInvalidValue;
+  if (nrc == 1) he = go(k_m2l_dense<4>);
+  else if (nrc == 2) he = go(k_m2l_dense<8>);
+  else if (nrc == 4) he = go(k_m2l_dense<16>);
+  if (he != hipSuccess) return he;
   return hipGetLastError();
 }
 

@@ -223,14 +223,15 @@ __device__ void second_half(int c, int ld, const ColData& cd, const R* __restric
 }
 
 // Degree (order) cases compiled into a kernel: 0..16, plus 17..21 when the
-// kernel is built for PM = 21.
+// kernel is built for PM = 21, plus 22..27 for PM = 27.
 #define RPY_DEG_CASES(X) \
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 #define RPY_DEG_CASES_HI(X) X(17) X(18) X(19) X(20) X(21)
+#define RPY_DEG_CASES_HI2(X) X(22) X(23) X(24) X(25) X(26) X(27)
 
 }  // namespace
 
-// PM: highest degree compiled in (16 or 21).  MINW: waves per SIMD the
+// PM: highest degree compiled in (16, 21 or 27).  MINW: waves per SIMD the
 // register allocation must allow (4 lets two blocks share a CU when their
 // LDS fits).
 template <int ND, class R, int PM, int MINW>
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
                                                 const double2* __restrict__ M, double2* __restrict__ L,
                                                 const int* __restrict__ bmap) {
   using C = typename Cx<R>::T;
-  constexpr int NACC = (ND * ncoef(MAX_ORDER) + RT - 1) / RT;
+  constexpr int NACC = (ND * ncoef(PM) + RT - 1) / RT;
   extern __shared__ double2 smem[];
   const int T = ncoef(p);
   const int ld = nc + 1;  // padded row: column-wise and row-wise LDS accesses both avoid bank conflicts
@@ -344,6 +345,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   case k: if (k <= PM) first_half<(k <= PM ? k : 0), R>(lane, ld, cd, A, X); break;
           RPY_DEG_CASES(RPY_P1)
           RPY_DEG_CASES_HI(RPY_P1)
+          RPY_DEG_CASES_HI2(RPY_P1)
 #undef RPY_P1
           default: break;
         }
@@ -362,6 +364,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   case k + 1: if (k <= PM) ztrans<(k <= PM ? k : 0) + 1, R>(l, lane, ld, cd, zt + zo, X); break;
           RPY_DEG_CASES(RPY_P2)
           RPY_DEG_CASES_HI(RPY_P2)
+          RPY_DEG_CASES_HI2(RPY_P2)
 #undef RPY_P2
           default: break;
         }
@@ -378,6 +381,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   case k: if (k <= PM) second_half<(k <= PM ? k : 0), R>(lane, ld, cd, A, X); break;
           RPY_DEG_CASES(RPY_P3)
           RPY_DEG_CASES_HI(RPY_P3)
+          RPY_DEG_CASES_HI2(RPY_P3)
 #undef RPY_P3
           default: break;
         }
@@ -459,15 +463,17 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   const int p = l.p;
   if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
   if (l.B->tree.nbox == 0) return hipSuccess;
-  // 64 columns per batch, 32 when the LDS (160 KB per CU) cannot hold 64.
-  // Up to degree 16 in FP32 with one right-hand side, 60 columns let two
-  // blocks share a CU (registers are then capped for four waves per SIMD).
+  // 64 columns per batch, halved while the LDS (160 KB per CU) cannot hold
+  // them.  Up to degree 16 in FP32 with one right-hand side, 60 columns let
+  // two blocks share a CU (registers are then capped for four waves per SIMD).
   const bool lo = p <= 16, two = lo && sizeof(R) == 4 && nrc == 1;
   int nc = two ? 60 : 64;
-  if (rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc = 32;
+  while (nc > 8 && rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc /= 2;
   const size_t shm = rot_smem_bytes(p, nc, sizeof(R));
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   const RotSched sc = make_sched(p);
+  // orders above 21 (the 9-digit setting) run one right-hand side per pass
+  if (p > MAX_ORDER_MULTI) return nrc == 1 ? launch_nd<R, 4, 27, 1>(l, e, nc, shm, sc, rot, zt) : hipErrorInvalidValue;
   switch (nrc) {
     case 1:
       if constexpr (sizeof(R) == 4)

@@ -290,8 +290,18 @@ hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double
       case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
       case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E);
       case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E);
-      default: return hipErrorInvalidValue;
+      default: break;
     }
+    // orders above 21 run one right-hand side per pass: up to 7 passes
+    if constexpr (ND == 4) {
+      switch (s8.P) {
+        case 5: return launch_p2e<ND, LOCAL, 8, 5>(l, s8, grid, ids, Q, E);
+        case 6: return launch_p2e<ND, LOCAL, 8, 6>(l, s8, grid, ids, Q, E);
+        case 7: return launch_p2e<ND, LOCAL, 8, 7>(l, s8, grid, ids, Q, E);
+        default: break;
+      }
+    }
+    return hipErrorInvalidValue;
   } else {
     if (s8.P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E);
     if (s8.P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
@@ -380,7 +390,7 @@ static int build_sched(int p, int K, int maxp, P2ESched* out, Error* err, int64_
 
 int make_p2e_tables(int p, Tables* tb, Error* err) {
   int64_t bytes = 0;
-  const int r8 = build_sched(p, 8, 4, &tb->p2e[0], err, &bytes);
+  const int r8 = build_sched(p, 8, 7, &tb->p2e[0], err, &bytes);
   if (r8 < 0) return -1;
   const int r16 = build_sched(p, 16, 2, &tb->p2e[1], err, &bytes);
   if (r16 < 0) return -1;

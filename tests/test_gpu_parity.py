@@ -113,8 +113,9 @@ def test_fmm_fp64_matches_oracle_fmm(orc, case):
 # (order, rhs) pairs that reach every particle-to-expansion schedule: 8 steps
 # per wave and pass over 1..4 passes (one or two right-hand sides per pass)
 # and, with four right-hand sides per pass, 8 steps over 1..2 passes or 16
-# steps over 2; the tree has W and X lists.
-@pytest.mark.parametrize("p,nrhs", [(1, 3), (7, 4), (14, 3), (15, 4), (18, 2), (19, 1), (21, 4)],
+# steps over 2; above order 21 (the 9-digit setting) one right-hand side per
+# pass over 5..7 passes; the tree has W and X lists.
+@pytest.mark.parametrize("p,nrhs", [(1, 3), (7, 4), (14, 3), (15, 4), (18, 2), (19, 1), (21, 4), (24, 2), (27, 3)],
                          ids=lambda v: str(v))
 def test_schedules_match_oracle_fmm(orc, p, nrhs):
     w = W.clustered(1500, 8, 10.0, 0.8, 0.05, nrhs, seed=80 + p)
@@ -136,6 +137,24 @@ def test_fmm_fp64_accuracy_vs_direct(orc, eps):
     err = orc.rel_l2(u, ref)
     log(f"  p={st['order']} rel-L2 vs direct = {err:.3e}")
     assert err <= eps
+
+
+def test_nine_digit_setting_vs_direct(orc):
+    # eps below 1e-8 selects the highest order built (27): the paper's 9-digit
+    # setting, FP64, on uniform beads (level-uniform tree) and clustered beads
+    # (adaptive tree, W and X lists)
+    w = W.uniform_cube(20_000, 2.0, 0.01, nrhs=1, seed=71)
+    log("9-digit setting n=20000 uniform eps=1e-9")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-9, leaf_size=60)
+    err = orc.rel_l2(u, orc.rpy_direct(w.pos, w.forces, w.a, w.eta))
+    log(f"  p={st['order']} rel-L2 vs direct = {err:.3e}")
+    assert st["order"] == 27 and err <= 3.5e-9
+    w = W.clustered(20_000, 30, 30.0, 1.0, 0.5, 2, seed=72)
+    log("9-digit setting n=20000 clustered eps=1e-9, 2 rhs")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-9, leaf_size=40)
+    err = orc.rel_l2(u, orc.rpy_direct(w.pos, w.forces, w.a, w.eta))
+    log(f"  p={st['order']} W={st['list_len']['W']} rel-L2 vs direct = {err:.3e}")
+    assert st["order"] == 27 and st["list_len"]["W"] > 0 and err <= 1e-8
 
 
 def test_clustered_accuracy_vs_direct(orc):
@@ -212,7 +231,7 @@ def test_fullsize_cube_1M_sampled(orc):
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("p", [4, 13, 21])
+@pytest.mark.parametrize("p", [4, 13, 21, 27])
 def test_m2l_rotation_matches_dense(orc, p):
     """The rotation-based M->L and the dense O(p^4) M->L compute the same
     truncated operator; both match the oracle FMM."""
