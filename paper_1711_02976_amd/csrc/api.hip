@@ -373,6 +373,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
   if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, &P->ep, P->stream, &err);
   if (rc == 0) rc = rpy::make_m2l_map(&P->B, P->stream, &err);
+  if (rc == 0) rc = rpy::make_p2l_work(&P->B, P->stream, &err);
   if (rc == 0) {
     // default priority (no priority argument); without it the near field
     // runs on the plan's stream

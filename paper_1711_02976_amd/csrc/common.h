@@ -106,6 +106,11 @@ struct Built {
   // block -> target box of the rotation M->L (make_m2l_map), -1: no box
   int* m2l_map = nullptr;
   int m2l_grid = 0;
+  // S->L work items (make_p2l_work): (box, first X entry, end X entry,
+  // shared) and the range of 64-bead chunks taken from each entry
+  int4* xwork = nullptr;
+  int2* xchunks = nullptr;
+  int nxwork = 0;
   int64_t bytes = 0;
 };
 

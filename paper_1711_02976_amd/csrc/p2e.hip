@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_leaf_q(const int* leaves, Tree t, const
 // K generation steps per wave and pass, P passes: S = 8 K slots per pass,
 // G = S / 64 slot groups, NB = 8 / G bead subsets (partial sums per slot).
 template <int ND, bool LOCAL, int K, int P>
-__global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree t, List X, const double* sx,
+__global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, const int4* __restrict__ xwork,
+                                                     const int2* __restrict__ xchunks, Tree t, List X, const double* sx,
                                                      const double* sy, const double* sz, const double* __restrict__ Q,
                                                      const P2EPass* __restrict__ desc,
                                                      const int* __restrict__ slot_coef,
@@ -84,12 +85,22 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
   constexpr int S = P2E_WAVES * K, G = S / 64, NB = P2E_WAVES / G, BPW = P2E_CHUNK / NB;
   constexpr int LD = S + 1;  // odd row stride: conflict-free [bead][slot] writes
   const int T = ncoef(p);
-  const int b = ids ? ids[blockIdx.x] : blockIdx.x;
-  int e0 = 0, e1 = 1;
+  // S->M: one leaf per block.  S->L: one work item per block, a run of the
+  // box's X entries and a range of 64-bead chunks of each; a box whose X
+  // work was split over several items adds its share atomically
+  int b, e0 = 0, e1 = 1, clo = 0, chi = 0x7fffffff;
+  bool shared = false;
   if (LOCAL) {
-    e0 = X.off[b];
-    e1 = X.off[b + 1];
-    if (e0 == e1) return;
+    const int4 wk = xwork[blockIdx.x];
+    const int2 ch = xchunks[blockIdx.x];
+    b = wk.x;
+    e0 = wk.y;
+    e1 = wk.z;
+    shared = wk.w != 0;
+    clo = ch.x;
+    chi = ch.y;
+  } else {
+    b = ids ? ids[blockIdx.x] : blockIdx.x;
   }
   extern __shared__ double2 Hs[];  // [64][LD]
   // S->L: the chunk's charges with the fourth one re-centred on this machine,
@@ -108,7 +119,11 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
 
   for (int e = e0; e < e1; ++e) {
     const int C = LOCAL ? X.ent[e] : b;
-    const int j0 = t.begin[C], j1 = t.end[C];
+    int j0 = t.begin[C], j1 = t.end[C];
+    if (LOCAL) {
+      j1 = (int)min((int64_t)j1, (int64_t)j0 + (int64_t)chi * P2E_CHUNK);
+      j0 += clo * P2E_CHUNK;
+    }
     // Q holds the fourth charge about the source leaf's centre; about c:
     // F.(r - c) = F.(r - c_C) + F.(c_C - c)
     double wx = 0.0, wy = 0.0, wz = 0.0;
@@ -249,6 +264,11 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
           v.y += w.y;
         }
         double2* out = E + ((int64_t)b * ND + d0 + d) * T + c;
+        if (LOCAL && shared) {
+          atomicAdd(&out->x, v.x);
+          atomicAdd(&out->y, v.y);
+          continue;
+        }
         if (LOCAL) {
           const double2 o0 = *out;
           v.x += o0.x;
@@ -267,13 +287,14 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, Tree
 template <int ND, bool LOCAL, int K, int P>
 hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* ids, const double* Q, double2* E) {
   const Built* B = l.B;
+  if (grid == 0) return hipSuccess;
   const size_t shm = sizeof(double2) * P2E_CHUNK * (P2E_WAVES * K + 1);
   auto kern = k_p2e<ND, LOCAL, K, P>;
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
-  kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q, sc.desc, sc.slot,
-                                        sc.scale, l.tb->p2e_dk, E);
+  kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->xwork, B->xchunks, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q,
+                                        sc.desc, sc.slot, sc.scale, l.tb->p2e_dk, E);
   return hipGetLastError();
 }
 
@@ -388,6 +409,63 @@ static int build_sched(int p, int K, int maxp, P2ESched* out, Error* err, int64_
   return 1;
 }
 
+// S->L work items.  A box's X entries are cut into runs of at most `cap`
+// 64-bead chunks, and an entry longer than that into chunk ranges, so that
+// no block carries much more than its share: on 64 systems at leaf 1640 one
+// box held 344 chunks against 17 per CU on average, and its block set the
+// kernel's length.  cap = max(16, total / 2048).
+int make_p2l_work(Built* B, hipStream_t s, Error* err) {
+  if (B->xwork) (void)hipFree(B->xwork);
+  if (B->xchunks) (void)hipFree(B->xchunks);
+  B->xwork = nullptr;
+  B->xchunks = nullptr;
+  B->nxwork = 0;
+  const List& X = B->lists[LX];
+  const int nbox = B->tree.nbox;
+  if (X.len == 0 || nbox == 0) return 0;
+  std::vector<int> off(nbox + 1), ent(X.len), beg(nbox), end(nbox);
+  RPY_HIP(hipMemcpyAsync(off.data(), X.off, sizeof(int) * (nbox + 1), hipMemcpyDeviceToHost, s));
+  RPY_HIP(hipMemcpyAsync(ent.data(), X.ent, sizeof(int) * X.len, hipMemcpyDeviceToHost, s));
+  RPY_HIP(hipMemcpyAsync(beg.data(), B->tree.begin, sizeof(int) * nbox, hipMemcpyDeviceToHost, s));
+  RPY_HIP(hipMemcpyAsync(end.data(), B->tree.end, sizeof(int) * nbox, hipMemcpyDeviceToHost, s));
+  RPY_HIP(hipStreamSynchronize(s));
+  auto chunks = [&](int e) { return (end[ent[e]] - beg[ent[e]] + P2E_CHUNK - 1) / P2E_CHUNK; };
+  int64_t total = 0;
+  for (int64_t e = 0; e < X.len; ++e) total += chunks((int)e);
+  const int cap = (int)std::max<int64_t>(16, total / 2048);
+  std::vector<int4> work;
+  std::vector<int2> rng;
+  for (int b = 0; b < nbox; ++b) {
+    const size_t first = work.size();
+    int e = off[b];
+    while (e < off[b + 1]) {
+      const int c = chunks(e);
+      if (c > cap) {  // one long entry: chunk ranges of it
+        for (int lo = 0; lo < c; lo += cap) {
+          work.push_back(make_int4(b, e, e + 1, 0));
+          rng.push_back(make_int2(lo, std::min(c, lo + cap)));
+        }
+        ++e;
+        continue;
+      }
+      int e1 = e, sum = 0;
+      while (e1 < off[b + 1] && chunks(e1) <= cap && sum + chunks(e1) <= cap) sum += chunks(e1++);
+      work.push_back(make_int4(b, e, e1, 0));
+      rng.push_back(make_int2(0, 0x7fffffff));
+      e = e1;
+    }
+    if (work.size() - first > 1)
+      for (size_t i = first; i < work.size(); ++i) work[i].w = 1;
+  }
+  B->nxwork = (int)work.size();
+  RPY_HIP(hipMalloc(&B->xwork, sizeof(int4) * work.size()));
+  RPY_HIP(hipMalloc(&B->xchunks, sizeof(int2) * rng.size()));
+  RPY_HIP(hipMemcpy(B->xwork, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
+  RPY_HIP(hipMemcpy(B->xchunks, rng.data(), sizeof(int2) * rng.size(), hipMemcpyHostToDevice));
+  B->bytes += (int64_t)(sizeof(int4) + sizeof(int2)) * work.size();
+  return 0;
+}
+
 int make_p2e_tables(int p, Tables* tb, Error* err) {
   int64_t bytes = 0;
   const int r8 = build_sched(p, 8, 7, &tb->p2e[0], err, &bytes);
@@ -430,7 +508,8 @@ hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
   (void)sF;  // the charges come from the per-bead array written by run_p2m
   const Built* B = l.B;
   if (B->lists[LX].len == 0) return hipSuccess;
-  return launch_p2e_nd<true>(l, nrc, B->tree.nbox, nullptr, e.Q, e.L);
+  if (!B->xwork && B->nxwork > 0) return hipErrorInvalidValue;
+  return launch_p2e_nd<true>(l, nrc, B->nxwork, nullptr, e.Q, e.L);
 }
 
 }  // namespace rpy

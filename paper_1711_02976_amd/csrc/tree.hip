@@ -598,7 +598,7 @@ void free_built(Built* b) {
   void* ps[] = {b->keys, b->perm, b->sx, b->sy, b->sz, b->d_lo, b->d_side, b->d_sys_begin,
                 b->tree.level, b->tree.sys, b->tree.ax, b->tree.ay, b->tree.az, b->tree.begin,
                 b->tree.end, b->tree.parent, b->tree.child, b->tree.nchild, b->tree.cx, b->tree.cy,
-                b->tree.cz, b->tree.h, b->colleague, b->leaf_ids, b->m2l_map};
+                b->tree.cz, b->tree.h, b->colleague, b->leaf_ids, b->m2l_map, b->xwork, b->xchunks};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& L : b->lists) {
