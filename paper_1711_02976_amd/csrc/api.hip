@@ -64,6 +64,7 @@ int order_for_eps(double eps, bool adaptive) {
 // returns the range of refinement limits that produce this same tree.
 struct TreeCost {
   double ns = 0;
+  double near_ns = 0;  // the P2P and direct-W part of ns
   int same_lo = 0;     // largest leaf that a larger limit could not split
   int same_hi = 0;     // smallest count among split boxes: limits below it keep every split
   bool adaptive = false;
@@ -126,7 +127,8 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const int r = std::max(nrhs, 1);
   const int n4 = r / 4, n2 = (r % 4) / 2, n1 = r % 2;
   const double near_passes = n4 * 2.3 + n2 * 1.5 + n1;
-  out->ns = pairs * c_pair * near_passes + 4.0 * r * far;
+  out->near_ns = pairs * c_pair * near_passes;
+  out->ns = out->near_ns + 4.0 * r * far;
   out->same_lo = lo;
   out->same_hi = hi;
   out->adaptive = adaptive;
@@ -323,8 +325,10 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     // Refinement limit chosen by the cost model over a ladder of limits
     // (64 * 1.5^k) up to the largest system; limits that provably give the
     // tree already built are skipped, so only distinct trees are built.  The
-    // whole ladder is searched: partly refined (adaptive) trees in between
-    // need a higher order, so the modelled time is not unimodal in the limit.
+    // modelled time is not unimodal in the limit (partly refined trees in
+    // between need a higher order), so the ladder is climbed until a tree's
+    // near field alone, which only grows as the tree coarsens, costs more
+    // than the best whole matvec.
     // Trial trees are built without the O list: the overlapping bead pairs
     // are fixed by the geometry, not by the tree, and dense clusters with
     // small leaves make that list very long.  The chosen tree is rebuilt
@@ -358,6 +362,9 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
         rpy::free_built(&Bc);
       }
       if (cand >= nmax || tc.same_hi > nmax) break;  // one leaf per system from here on
+      // coarser trees only add near-field pairs: once this tree's near field
+      // alone costs more than the best whole matvec, no larger limit can win
+      if (tc.near_ns > best) break;
       do sl *= 1.5;
       while ((int64_t)sl < tc.same_hi);
     }
