@@ -110,7 +110,7 @@ struct PairK {
   R oc;       // c0/c1
   R ock9;     // (c0/c1) 9/(32a)
   R ob;       // (c0/c1) 3/(32a)
-  R r2min;    // clamp of r^2 before the reciprocal square root (coincident beads)
+  R r2min;    // floor added to r^2 before the reciprocal square root (coincident beads)
 };
 
 template <class R>
@@ -132,7 +132,8 @@ __device__ inline double rinv_of(double r2) {
 // The overlap formula is evaluated only when some lane of the wave has a
 // source closer than 2a (a wave-uniform branch), since such pairs are rare
 // apart from each target's own bead.  For r = 0 (the bead itself, or a
-// coincident bead) r^2 is clamped before the reciprocal square root: the far
+// coincident bead) r^2 carries a floor of 1e-30 (added in the first FMA; it
+// changes no r^2 above 1e-23) before the reciprocal square root: the far
 // values are then finite and discarded, and the overlap values give the
 // r -> 0 limit A' = c0/c1, B' d = 0.
 // Positions enter the pair arithmetic relative to the target leaf's centre
@@ -190,8 +191,9 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
         R r2[4], rinv[4], A[4], B[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          r2[q] = fma(dx[q], dx[q], fma(dy[q], dy[q], dz[q] * dz[q]));
-          rinv[q] = rinv_of(max(r2[q], k.r2min));
+          // r^2 + r2min: the floor rides in the first FMA instead of a max
+          r2[q] = fma(dx[q], dx[q], fma(dy[q], dy[q], fma(dz[q], dz[q], k.r2min)));
+          rinv[q] = rinv_of(r2[q]);
           const R ri2 = rinv[q] * rinv[q], ri3 = ri2 * rinv[q];
           A[q] = fma(k.a3, ri3, rinv[q]);
           B[q] = ri3 * fma(-k.a2, ri2, (R)1);
@@ -278,8 +280,8 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
 #pragma unroll
       for (int s = s0; s < s0 + 4; ++s) {
         const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-        const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const R rinv = rinv_of(max(r2, k.r2min));
+        const R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, k.r2min)));
+        const R rinv = rinv_of(r2);
         const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
         const R A = fma(k.a3, ri3, rinv), B = ri3 * fma(-k.a2, ri2, (R)1);
 #pragma unroll
@@ -397,8 +399,8 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
 #pragma unroll
         for (int s = s0; s < s0 + 4; ++s) {
           const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
-          const R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          const R rinv = rinv_of(max(r2, k.r2min));
+          const R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, k.r2min)));
+          const R rinv = rinv_of(r2);
           const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
           const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
           const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
