@@ -203,7 +203,8 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const bool ov = r2[q] < k.four_a2;
-            const R Ao = fma(-k.ock9, r2[q] * rinv[q], k.oc), Bo = k.ob * rinv[q];
+            // r from r^2 without the floor: exactly 0 for the bead itself
+            const R Ao = fma(-k.ock9, (r2[q] - k.r2min) * rinv[q], k.oc), Bo = k.ob * rinv[q];
             A[q] = ov ? Ao : A[q];
             B[q] = ov ? Bo : B[q];
           }
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
           const R rinv = rinv_of(r2);
           const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
           const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
-          const R Ao = fma(-k.ock9, r2 * rinv, k.oc), Bo = k.ob * rinv;
+          const R Ao = fma(-k.ock9, (r2 - k.r2min) * rinv, k.oc), Bo = k.ob * rinv;
           const bool ov = r2 < k.four_a2;
           const R A = ov ? Ao - Af : (R)0, B = ov ? Bo - Bf : (R)0;
 #pragma unroll

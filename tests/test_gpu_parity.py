@@ -139,6 +139,23 @@ def test_fmm_fp64_accuracy_vs_direct(orc, eps):
     assert err <= eps
 
 
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_si_units_small_beads(orc, precision, bound):
+    # SI-like units (a = 1 nm, positions over 20 nm, water viscosity): the
+    # pair kernels' 1e-30 floor on r^2 must not leak into the self term or
+    # the overlap branch; one leaf, so the matvec is the exact pair sum
+    g = np.random.default_rng(17)
+    n, a, eta = 300, 1e-9, 1e-3
+    pos = g.uniform(0.0, 2e-8, size=(n, 3))
+    F = g.standard_normal((1, n, 3)) * 1e-12
+    log(f"SI units n={n} a={a} {precision}")
+    u, st = gpu_matvec(pos, F, a, eta, 1e-6, leaf_size=1000, precision=precision)
+    ref = orc.rpy_direct(pos, F, a, eta)
+    err = orc.rel_l2(u, ref)
+    log(f"  rel-L2 vs direct = {err:.3e}")
+    assert err <= bound
+
+
 def test_nine_digit_setting_vs_direct(orc):
     # eps below 1e-8 selects the highest order built (27): the paper's 9-digit
     # setting, FP64, on uniform beads (level-uniform tree) and clustered beads
