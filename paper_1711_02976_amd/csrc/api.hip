@@ -151,6 +151,10 @@ struct rpy_plan_s {
   // combined on `stream`.
   hipStream_t near = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // M->L of the deepest level (sources need only S->M) runs on a third
+  // stream while the upward pass continues on `stream`
+  hipStream_t far2 = nullptr;
+  hipEvent_t ev_p2m = nullptr, ev_m2l0 = nullptr;
   int sticky = 0;
   // matvec workspace, sized for `ws_nrc` right-hand sides per pass
   int ws_nrc = 0;
@@ -394,6 +398,16 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       P->near = nullptr;
       P->ev_fork = P->ev_join = nullptr;
     }
+    if (hipStreamCreateWithFlags(&P->far2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_p2m, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_m2l0, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (P->far2) (void)hipStreamDestroy(P->far2);
+      if (P->ev_p2m) (void)hipEventDestroy(P->ev_p2m);
+      if (P->ev_m2l0) (void)hipEventDestroy(P->ev_m2l0);
+      P->far2 = nullptr;
+      P->ev_p2m = P->ev_m2l0 = nullptr;
+    }
   }
 
   if (rc != 0) {
@@ -454,11 +468,24 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
     if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
     // far field on s0
     if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
+    // the deepest level's M->L needs only S->M: on a third stream, beside
+    // the upward pass (it writes L of other boxes than the second part)
+    const bool split = fork && P->far2 && P->m2l_mode != 1;
+    if (split) {
+      rpy::Launch l2 = l;
+      l2.s = P->far2;
+      he = hipEventRecord(P->ev_p2m, s0);
+      if (he == hipSuccess) he = hipStreamWaitEvent(P->far2, P->ev_p2m, 0);
+      if (he == hipSuccess)
+        he = timed(P, RPY_PH_M2L, 1, P->far2, [&] { return rpy::run_m2l_rot(l2, c, e, mixed, 0); });
+      if (he == hipSuccess) he = hipEventRecord(P->ev_m2l0, P->far2);
+    }
     if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, s0, [&] {
       if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
-      return rpy::run_m2l_rot(l, c, e, mixed);
+      return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
     });
+    if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
     if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
     if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
@@ -728,7 +755,11 @@ void rpy_plan_free(rpy_plan_t* P) {
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
   if (P->near) (void)hipStreamSynchronize(P->near);
+  if (P->far2) (void)hipStreamSynchronize(P->far2);
   fold_events(P);
+  if (P->far2) (void)hipStreamDestroy(P->far2);
+  if (P->ev_p2m) (void)hipEventDestroy(P->ev_p2m);
+  if (P->ev_m2l0) (void)hipEventDestroy(P->ev_m2l0);
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->near) (void)hipStreamDestroy(P->near);

@@ -103,9 +103,11 @@ struct Built {
   int nleaf = 0;
   int* leaf_ids = nullptr;      // [nleaf]
   List lists[5]{};
-  // block -> target box of the rotation M->L (make_m2l_map), -1: no box
+  // block -> target box of the rotation M->L (make_m2l_map), -1: no box;
+  // blocks [m2l_part[0], m2l_part[1]) take the deepest level's boxes, whose
+  // sources need only S->M, blocks [m2l_part[1], m2l_part[2]) the others
   int* m2l_map = nullptr;
-  int m2l_grid = 0;
+  int m2l_part[3] = {0, 0, 0};
   // S->L work items (make_p2l_work): (box, first X entry, end X entry,
   // shared) and the range of 64-bead chunks taken from each entry
   int4* xwork = nullptr;

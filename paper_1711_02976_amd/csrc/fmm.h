@@ -92,8 +92,10 @@ hipError_t unpermute_velocities(const Launch& l, const double* u, const double* 
 hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e);
 hipError_t run_m2m(const Launch& l, int nrc, Exp e);
 hipError_t run_m2l(const Launch& l, int nrc, Exp e);       // dense O(p^4)
-hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32);  // rotation, O(p^3)
-// Fills B->m2l_map / m2l_grid, which run_m2l_rot needs (m2l_rot.hip).
+// rotation, O(p^3); part 0: target boxes of the deepest level, 1: the
+// others, -1: all
+hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32, int part = -1);
+// Fills B->m2l_map / m2l_part, which run_m2l_rot needs (m2l_rot.hip).
 int make_m2l_map(Built* B, hipStream_t s, Error* err);
 // Fills B->xwork / xchunks / nxwork, which run_p2l needs (p2e.hip).
 int make_p2l_work(Built* B, hipStream_t s, Error* err);

@@ -446,20 +446,22 @@ static size_t rot_smem_bytes(int p, int nc, size_t real) {
 
 template <class R, int ND, int PM, int MINW>
 static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const RotSched& sc, const R* rot,
-                            const R* zt) {
+                            const R* zt, int part) {
   const Built* B = l.B;
   auto kern = k_m2l_rot<ND, R, PM, MINW>;
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
-  if (!B->m2l_map || B->m2l_grid < B->tree.nbox) return hipErrorInvalidValue;
-  kern<<<B->m2l_grid, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
-                                       l.tb->sfac, e.M, e.L, B->m2l_map);
+  if (!B->m2l_map || B->m2l_part[2] < B->tree.nbox) return hipErrorInvalidValue;
+  const int b0 = part == 1 ? B->m2l_part[1] : 0, b1 = part == 0 ? B->m2l_part[1] : B->m2l_part[2];
+  if (b1 <= b0) return hipSuccess;
+  kern<<<b1 - b0, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
+                                   l.tb->sfac, e.M, e.L, B->m2l_map + b0);
   return hipGetLastError();
 }
 
 template <class R>
-static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, const R* zt) {
+static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, const R* zt, int part) {
   const int p = l.p;
   if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
   if (l.B->tree.nbox == 0) return hipSuccess;
@@ -473,17 +475,17 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   if (shm > 160 * 1024) return hipErrorInvalidValue;
   const RotSched sc = make_sched(p);
   // orders above 21 (the 9-digit setting) run one right-hand side per pass
-  if (p > MAX_ORDER_MULTI) return nrc == 1 ? launch_nd<R, 4, 27, 1>(l, e, nc, shm, sc, rot, zt) : hipErrorInvalidValue;
+  if (p > MAX_ORDER_MULTI) return nrc == 1 ? launch_nd<R, 4, 27, 1>(l, e, nc, shm, sc, rot, zt, part) : hipErrorInvalidValue;
   switch (nrc) {
     case 1:
       if constexpr (sizeof(R) == 4)
-        if (two) return launch_nd<R, 4, 16, 4>(l, e, nc, shm, sc, rot, zt);
-      return lo ? launch_nd<R, 4, 16, 1>(l, e, nc, shm, sc, rot, zt) : launch_nd<R, 4, 21, 1>(l, e, nc, shm, sc, rot, zt);
+        if (two) return launch_nd<R, 4, 16, 4>(l, e, nc, shm, sc, rot, zt, part);
+      return lo ? launch_nd<R, 4, 16, 1>(l, e, nc, shm, sc, rot, zt, part) : launch_nd<R, 4, 21, 1>(l, e, nc, shm, sc, rot, zt, part);
     case 2:
-      return lo ? launch_nd<R, 8, 16, 1>(l, e, nc, shm, sc, rot, zt) : launch_nd<R, 8, 21, 1>(l, e, nc, shm, sc, rot, zt);
+      return lo ? launch_nd<R, 8, 16, 1>(l, e, nc, shm, sc, rot, zt, part) : launch_nd<R, 8, 21, 1>(l, e, nc, shm, sc, rot, zt, part);
     case 4:
-      return lo ? launch_nd<R, 16, 16, 1>(l, e, nc, shm, sc, rot, zt)
-                : launch_nd<R, 16, 21, 1>(l, e, nc, shm, sc, rot, zt);
+      return lo ? launch_nd<R, 16, 16, 1>(l, e, nc, shm, sc, rot, zt, part)
+                : launch_nd<R, 16, 21, 1>(l, e, nc, shm, sc, rot, zt, part);
     default: return hipErrorInvalidValue;
   }
 }
@@ -496,45 +498,59 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
 // V lists are far from uniform along the box order, and equal box counts
 // per XCD left some XCDs with twice the mean work.  Block 8k + x takes the
 // k-th box of run x; blocks past the end of a shorter run take none.
+// Map of the boxes [r0, r1) appended to map (8 K entries).
+static void append_map(const std::vector<int>& off, int r0, int r1, std::vector<int>& map) {
+  if (r1 <= r0) return;
+  const int nb = r1 - r0;
+  std::vector<double> pre(nb + 1, 0.0);
+  for (int i = 0; i < nb; ++i) {
+    const int v = off[r0 + i + 1] - off[r0 + i];
+    pre[i + 1] = pre[i] + v + (v > 0 ? 1.0 : 0.0) + 0.25;
+  }
+  int cut[9];
+  cut[0] = 0;
+  cut[8] = nb;
+  for (int x = 1; x < 8; ++x) {
+    const double goal = pre[nb] * x / 8.0;
+    cut[x] = (int)(std::lower_bound(pre.begin(), pre.end(), goal) - pre.begin());
+    cut[x] = std::min(std::max(cut[x], cut[x - 1]), nb);
+  }
+  int K = 0;
+  for (int x = 0; x < 8; ++x) K = std::max(K, cut[x + 1] - cut[x]);
+  const size_t base = map.size();
+  map.resize(base + (size_t)8 * K, -1);
+  for (int x = 0; x < 8; ++x)
+    for (int k = 0; k < cut[x + 1] - cut[x]; ++k) map[base + (size_t)8 * k + x] = r0 + cut[x] + k;
+}
+
 int make_m2l_map(Built* B, hipStream_t s, Error* err) {
   const int nbox = B->tree.nbox;
   if (B->m2l_map) {
     (void)hipFree(B->m2l_map);
     B->m2l_map = nullptr;
   }
-  B->m2l_grid = 0;
+  B->m2l_part[0] = B->m2l_part[1] = B->m2l_part[2] = 0;
   if (nbox == 0) return 0;
   std::vector<int> off(nbox + 1);
   RPY_HIP(hipMemcpyAsync(off.data(), B->lists[LV].off, sizeof(int) * (nbox + 1), hipMemcpyDeviceToHost, s));
   RPY_HIP(hipStreamSynchronize(s));
-  std::vector<double> pre(nbox + 1, 0.0);
-  for (int b = 0; b < nbox; ++b) {
-    const int v = off[b + 1] - off[b];
-    pre[b + 1] = pre[b] + v + (v > 0 ? 1.0 : 0.0) + 0.25;
-  }
-  int cut[9];
-  cut[0] = 0;
-  cut[8] = nbox;
-  for (int x = 1; x < 8; ++x) {
-    const double goal = pre[nbox] * x / 8.0;
-    cut[x] = (int)(std::lower_bound(pre.begin(), pre.end(), goal) - pre.begin());
-    cut[x] = std::min(std::max(cut[x], cut[x - 1]), nbox);
-  }
-  int K = 0;
-  for (int x = 0; x < 8; ++x) K = std::max(K, cut[x + 1] - cut[x]);
-  std::vector<int> map((size_t)8 * K, -1);
-  for (int x = 0; x < 8; ++x)
-    for (int k = 0; k < cut[x + 1] - cut[x]; ++k) map[(size_t)8 * k + x] = cut[x] + k;
+  // boxes are numbered by level: the deepest level is the last range
+  const int deep = B->level_start.empty() ? 0 : B->level_start[B->depth];
+  std::vector<int> map;
+  append_map(off, deep, nbox, map);
+  B->m2l_part[1] = (int)map.size();
+  append_map(off, 0, deep, map);
+  B->m2l_part[2] = (int)map.size();
+  if (map.empty()) return 0;
   RPY_HIP(hipMalloc(&B->m2l_map, sizeof(int) * map.size()));
   RPY_HIP(hipMemcpy(B->m2l_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
-  B->m2l_grid = 8 * K;
   B->bytes += (int64_t)sizeof(int) * map.size();
   return 0;
 }
 
-hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32) {
-  return fp32 ? launch_rot<float>(l, nrc, e, l.tb->rot32, l.tb->zt32)
-              : launch_rot<double>(l, nrc, e, l.tb->rot64, l.tb->zt64);
+hipError_t run_m2l_rot(const Launch& l, int nrc, Exp e, int fp32, int part) {
+  return fp32 ? launch_rot<float>(l, nrc, e, l.tb->rot32, l.tb->zt32, part)
+              : launch_rot<double>(l, nrc, e, l.tb->rot64, l.tb->zt64, part);
 }
 
 }  // namespace rpy
