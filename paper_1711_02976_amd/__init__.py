@@ -6,8 +6,15 @@ fails loudly if the library has not been built (``python -m
 paper_1711_02976_amd.build``) -- there is no CPU fallback.
 
 Functions mirror the C entry points (``rpy_plan``, ``rpy_plan_batched``,
-``rpy_matvec``, ``rpy_plan_stats``, ``rpy_plan_export``, ``rpy_plan_free``);
-``Plan`` wraps them for torch tensors.
+``rpy_matvec``, ``rpy_sqrt_matvec``, ``rpy_plan_stats``, ``rpy_plan_export``,
+``rpy_plan_free``); ``Plan`` wraps them for torch tensors::
+
+    import torch, paper_1711_02976_amd as R
+    pos = torch.rand(100_000, 3, dtype=torch.float64, device="cuda") * 50
+    P = R.Plan(pos, a=0.5, eta=1.0, eps=1e-6, precision="mixed", nrhs=1)
+    u = P.matvec(torch.randn(1, 100_000, 3, dtype=torch.float64, device="cuda"))
+    y, info = P.sqrt_matvec(torch.randn_like(u), tol=1e-3)   # D^{1/2} z
+    P.free()
 """
 from __future__ import annotations
 
