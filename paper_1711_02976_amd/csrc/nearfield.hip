@@ -153,6 +153,7 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   const int4 tl = tiles[blockIdx.x];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
+  const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];
   const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
@@ -180,8 +181,9 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
       // four sources per trip, read as vectors; one wave-wide test for the
-      // overlap branch per trip
-      for (int s0 = 0; s0 < ns4; s0 += 4) {
+      // overlap branch per trip.  A wave with no target of the tile (the
+      // second wave of a tile of 64 beads or fewer) stages and syncs only.
+      for (int s0 = 0; s0 < (wlive ? ns4 : 0); s0 += 4) {
         const V4 X4 = *reinterpret_cast<const V4*>(xs + s0), Y4 = *reinterpret_cast<const V4*>(ys + s0),
                  Z4 = *reinterpret_cast<const V4*>(zs + s0);
         // padding sources: r^2 overflows to inf in FP32, 1/r = 0, A = B = 0
@@ -251,6 +253,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
   const int e0 = __builtin_amdgcn_readfirstlane(W.off[b]), e1 = __builtin_amdgcn_readfirstlane(W.off[b + 1]);
   if (e0 == e1) return;
   const bool valid = (int)threadIdx.x < tl.z;
+  const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
   const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
@@ -277,7 +280,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
       __syncthreads();
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
-      for (int s0 = 0; s0 < ns4; s0 += 4)
+      for (int s0 = 0; s0 < (wlive ? ns4 : 0); s0 += 4)
 #pragma unroll
       for (int s = s0; s < s0 + 4; ++s) {
         const R dx = xi - xs[s], dy = yi - ys[s], dz = zi - zs[s];
@@ -331,6 +334,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
   const int e0 = __builtin_amdgcn_readfirstlane(O.off[b]), e1 = __builtin_amdgcn_readfirstlane(O.off[b + 1]);
   if (e0 == e1) return;
   const bool valid = (int)threadIdx.x < tl.z;
+  const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
   const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       __syncthreads();
       R ar[NRC][3];
       for (int r = 0; r < NRC; ++r) ar[r][0] = ar[r][1] = ar[r][2] = (R)0;
-      for (int g = 0; g < ng; ++g) {
+      for (int g = 0; g < (wlive ? ng : 0); ++g) {
         // distance from this lane's target to the group's box; the wave
         // skips the group when no lane comes within 2a of it
         const R gx = max((R)0, max(gbox[g][0] - xi, xi - gbox[g][3]));
