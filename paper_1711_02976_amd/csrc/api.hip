@@ -333,10 +333,12 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     // between need a higher order), so the ladder is climbed until a tree's
     // near field alone, which only grows as the tree coarsens, costs more
     // than the best whole matvec.
-    // Trial trees are built without the O list: the overlapping bead pairs
-    // are fixed by the geometry, not by the tree, and dense clusters with
-    // small leaves make that list very long.  The chosen tree is rebuilt
-    // with it when some leaf is smaller than 2a.
+    // Every trial tree after the first copies the bounding cubes, Morton
+    // keys and sorted order of the best one so far (they do not depend on
+    // the limit).  Trial trees are built without the O list: the overlapping
+    // bead pairs are fixed by the geometry, not by the tree, and dense
+    // clusters with small leaves make that list very long.  The chosen tree
+    // is rebuilt with it when some leaf is smaller than 2a.
     int64_t nmax = 1;
     for (int s = 0; s < nsys; ++s) nmax = std::max<int64_t>(nmax, counts[s]);
     double best = 0, sl = 64;
@@ -346,6 +348,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       rpy::Built Bc;
       rpy::BuildArgs ba{n, nsys, sb.data(), positions, cand, P->max_depth, a, P->stream};
       ba.skip_o = true;
+      ba.presorted = P->leaf_size != 0 ? &P->B : nullptr;
       rc = rpy::build_tree(ba, &Bc, &err);
       TreeCost tc;
       if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, o.nrhs, &tc);
@@ -373,9 +376,12 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       while ((int64_t)sl < tc.same_hi);
     }
     if (rc == 0 && need_o) {
-      rpy::free_built(&P->B);
+      rpy::Built Bo;
       rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
-      rc = rpy::build_tree(ba, &P->B, &err);
+      ba.presorted = &P->B;
+      rc = rpy::build_tree(ba, &Bo, &err);
+      rpy::free_built(&P->B);
+      P->B = Bo;
     }
   }
   if (rc == 0 && P->p == 0)

@@ -75,6 +75,7 @@ struct BuildArgs {
   double a;
   hipStream_t stream;
   bool skip_o = false;          // leave the O list empty (trial trees of the leaf-size search)
+  const struct Built* presorted = nullptr;  // a tree of the same beads: copy its cubes and sort
 };
 
 // Everything rpy_plan builds on the device.  Owned buffers are released by

@@ -619,62 +619,88 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
   if (dalloc(&B->d_sys_begin, nsys + 1, B, err)) return -3;
   RPY_HIP(hipMemcpy(B->d_sys_begin, sb.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice));
 
-  // Bounding cubes and the non-finite check.
-  int nblk = 64;
-  double* part = nullptr;
-  double* bb = nullptr;
-  int* bad = nullptr;
-  if (dalloc(&part, (int64_t)nsys * nblk * 6, B, err)) return -3;
-  if (dalloc(&bb, nsys * 6, B, err)) return -3;
-  if (dalloc(&bad, 1, B, err)) return -3;
-  RPY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-  k_bbox_partial<<<dim3(nblk, nsys), BB_T, 0, s>>>(A.pos, B->d_sys_begin, nblk, part);
-  k_bbox_final<<<nsys, 64, 0, s>>>(part, nblk, B->d_sys_begin, bb, bad);
-  k_check_finite<<<1024, 256, 0, s>>>(A.pos, 3 * n, bad);
-  RPY_HIP(hipGetLastError());
-  std::vector<double> hbb(nsys * 6);
-  int hbad = 0;
-  RPY_HIP(hipMemcpyAsync(hbb.data(), bb, sizeof(double) * nsys * 6, hipMemcpyDeviceToHost, s));
-  RPY_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-  RPY_HIP(hipStreamSynchronize(s));
-  (void)hipFree(part); (void)hipFree(bb); (void)hipFree(bad);
-  B->bytes -= sizeof(double) * ((int64_t)nsys * nblk * 6 + nsys * 6) + sizeof(int);
-  if (hbad) {
-    err->code = -2;
-    err->msg = "a position is NaN or infinite";
-    return -2;
-  }
-  B->lo.assign(3 * nsys, 0.0);
-  B->side.assign(nsys, 1.0);
-  for (int k = 0; k < nsys; ++k) {
-    double sd = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      B->lo[3 * k + d] = hbb[6 * k + d];
-      double ext = hbb[6 * k + 3 + d] - hbb[6 * k + d];
-      if (ext > sd) sd = ext;
+  if (A.presorted) {
+    // Same beads and systems as an earlier tree: its cubes, keys and sorted
+    // order do not depend on the leaf size, so they are copied, not rebuilt.
+    const Built* S = A.presorted;
+    if (S->n != n || S->nsys != nsys) {
+      err->code = -1;
+      err->msg = "internal: presorted tree of other beads";
+      return -1;
     }
-    B->side[k] = sd == 0.0 ? 1.0 : sd;
-  }
-  if (dalloc(&B->d_lo, 3 * nsys, B, err) || dalloc(&B->d_side, nsys, B, err)) return -3;
-  RPY_HIP(hipMemcpyAsync(B->d_lo, B->lo.data(), sizeof(double) * 3 * nsys, hipMemcpyHostToDevice, s));
-  RPY_HIP(hipMemcpyAsync(B->d_side, B->side.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, s));
+    B->lo = S->lo;
+    B->side = S->side;
+    if (dalloc(&B->d_lo, 3 * nsys, B, err) || dalloc(&B->d_side, nsys, B, err) || dalloc(&B->keys, n, B, err) ||
+        dalloc(&B->perm, n, B, err) || dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) ||
+        dalloc(&B->sz, n, B, err))
+      return -3;
+    RPY_HIP(hipMemcpyAsync(B->d_lo, S->d_lo, sizeof(double) * 3 * nsys, hipMemcpyDeviceToDevice, s));
+    RPY_HIP(hipMemcpyAsync(B->d_side, S->d_side, sizeof(double) * nsys, hipMemcpyDeviceToDevice, s));
+    if (n > 0) {
+      RPY_HIP(hipMemcpyAsync(B->keys, S->keys, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+      RPY_HIP(hipMemcpyAsync(B->perm, S->perm, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+      RPY_HIP(hipMemcpyAsync(B->sx, S->sx, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      RPY_HIP(hipMemcpyAsync(B->sy, S->sy, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      RPY_HIP(hipMemcpyAsync(B->sz, S->sz, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+  } else {
+    // Bounding cubes and the non-finite check.
+    int nblk = 64;
+    double* part = nullptr;
+    double* bb = nullptr;
+    int* bad = nullptr;
+    if (dalloc(&part, (int64_t)nsys * nblk * 6, B, err)) return -3;
+    if (dalloc(&bb, nsys * 6, B, err)) return -3;
+    if (dalloc(&bad, 1, B, err)) return -3;
+    RPY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    k_bbox_partial<<<dim3(nblk, nsys), BB_T, 0, s>>>(A.pos, B->d_sys_begin, nblk, part);
+    k_bbox_final<<<nsys, 64, 0, s>>>(part, nblk, B->d_sys_begin, bb, bad);
+    k_check_finite<<<1024, 256, 0, s>>>(A.pos, 3 * n, bad);
+    RPY_HIP(hipGetLastError());
+    std::vector<double> hbb(nsys * 6);
+    int hbad = 0;
+    RPY_HIP(hipMemcpyAsync(hbb.data(), bb, sizeof(double) * nsys * 6, hipMemcpyDeviceToHost, s));
+    RPY_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    RPY_HIP(hipStreamSynchronize(s));
+    (void)hipFree(part); (void)hipFree(bb); (void)hipFree(bad);
+    B->bytes -= sizeof(double) * ((int64_t)nsys * nblk * 6 + nsys * 6) + sizeof(int);
+    if (hbad) {
+      err->code = -2;
+      err->msg = "a position is NaN or infinite";
+      return -2;
+    }
+    B->lo.assign(3 * nsys, 0.0);
+    B->side.assign(nsys, 1.0);
+    for (int k = 0; k < nsys; ++k) {
+      double sd = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        B->lo[3 * k + d] = hbb[6 * k + d];
+        double ext = hbb[6 * k + 3 + d] - hbb[6 * k + d];
+        if (ext > sd) sd = ext;
+      }
+      B->side[k] = sd == 0.0 ? 1.0 : sd;
+    }
+    if (dalloc(&B->d_lo, 3 * nsys, B, err) || dalloc(&B->d_side, nsys, B, err)) return -3;
+    RPY_HIP(hipMemcpyAsync(B->d_lo, B->lo.data(), sizeof(double) * 3 * nsys, hipMemcpyHostToDevice, s));
+    RPY_HIP(hipMemcpyAsync(B->d_side, B->side.data(), sizeof(double) * nsys, hipMemcpyHostToDevice, s));
 
-  // Morton keys and the stable sort by (key, caller index) [, system].
-  uint64_t *k0 = nullptr, *k1 = nullptr;
-  int *v0 = nullptr, *v1 = nullptr;
-  if (dalloc(&k0, n, B, err) || dalloc(&k1, n, B, err) || dalloc(&v0, n, B, err) || dalloc(&v1, n, B, err))
-    return -3;
-  if (n > 0) k_morton<<<nblocks(n, 256), 256, 0, s>>>(A.pos, n, B->d_sys_begin, nsys, B->d_lo, B->d_side, k0, v0);
-  RPY_HIP(hipGetLastError());
-  int npass_sys = nsys > 1 ? (nsys > 256 ? 2 : 1) : 0;
-  RPY_HIP(radix_sort(&k0, &v0, k1, v1, n, 8, npass_sys, B->d_sys_begin, nsys, s));
-  (void)hipFree(k1); (void)hipFree(v1);
-  B->bytes -= (sizeof(uint64_t) + sizeof(int)) * std::max<int64_t>(n, 1);
-  B->keys = k0;
-  B->perm = v0;
-  if (dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) return -3;
-  if (n > 0) k_gather_pos<<<nblocks(n, 256), 256, 0, s>>>(A.pos, v0, n, B->sx, B->sy, B->sz);
-  RPY_HIP(hipGetLastError());
+    // Morton keys and the stable sort by (key, caller index) [, system].
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    int *v0 = nullptr, *v1 = nullptr;
+    if (dalloc(&k0, n, B, err) || dalloc(&k1, n, B, err) || dalloc(&v0, n, B, err) || dalloc(&v1, n, B, err))
+      return -3;
+    if (n > 0) k_morton<<<nblocks(n, 256), 256, 0, s>>>(A.pos, n, B->d_sys_begin, nsys, B->d_lo, B->d_side, k0, v0);
+    RPY_HIP(hipGetLastError());
+    int npass_sys = nsys > 1 ? (nsys > 256 ? 2 : 1) : 0;
+    RPY_HIP(radix_sort(&k0, &v0, k1, v1, n, 8, npass_sys, B->d_sys_begin, nsys, s));
+    (void)hipFree(k1); (void)hipFree(v1);
+    B->bytes -= (sizeof(uint64_t) + sizeof(int)) * std::max<int64_t>(n, 1);
+    B->keys = k0;
+    B->perm = v0;
+    if (dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) return -3;
+    if (n > 0) k_gather_pos<<<nblocks(n, 256), 256, 0, s>>>(A.pos, v0, n, B->sx, B->sy, B->sz);
+    RPY_HIP(hipGetLastError());
+  }
 
   // Octree, level by level.
   int cap0 = (int)std::max<int64_t>(1024, 4 * (n / std::max(A.leaf_size, 1)) + 16 * nsys);
