@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "fmm.h"
@@ -192,9 +195,21 @@ void host_rot90(int n, std::vector<double>& D) {
   }
 }
 
-int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
-  tb->p = p;
-  tb->bytes = 0;
+namespace {
+// Host images of the translation tables of one order.  They depend on the
+// order alone, so each order is computed once per process (25 ms of host
+// work at p = 16, 83 ms at p = 21, 0.25 s at p = 27) and every later plan
+// only uploads it.
+struct HostTables {
+  std::vector<double2> oct, itab;
+  std::vector<double> rot, zt, geo, sf, rsc;
+  std::vector<float> rot32, zt32;
+  int rlen = 0, zlen = 0;
+};
+std::mutex g_tables_mu;
+std::map<int, std::shared_ptr<const HostTables>> g_tables;
+
+int compute_tables(int p, HostTables* h, Error* err) {
   const int F1 = (p + 1) * (p + 1), F2 = (2 * p + 1) * (2 * p + 1);
   std::vector<double2> oct(8 * F1), itab((size_t)343 * F2, make_double2(0, 0)), tmp;
   for (int o = 0; o < 8; ++o) {
@@ -285,9 +300,46 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
         q[3] = std::sin(th);
         q[4] = 1.0 / rho;
       }
-  std::vector<float> rot32(rot.begin(), rot.end()), zt32(zt.begin(), zt.end());
-  tb->rot_len = rlen;
-  tb->zt_len = zlen;
+  std::vector<double> rsc(ncoef(p));
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) rsc[tri(n) + m] = 1.0 / (sf[tri(n) + m] * sf[tri(n) + m]);
+  h->rot32.assign(rot.begin(), rot.end());
+  h->zt32.assign(zt.begin(), zt.end());
+  h->oct = std::move(oct);
+  h->itab = std::move(itab);
+  h->rot = std::move(rot);
+  h->zt = std::move(zt);
+  h->geo = std::move(geo);
+  h->sf = std::move(sf);
+  h->rsc = std::move(rsc);
+  h->rlen = rlen;
+  h->zlen = zlen;
+  return 0;
+}
+}  // namespace
+
+int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
+  tb->p = p;
+  tb->bytes = 0;
+  std::shared_ptr<const HostTables> hp;
+  {
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto it = g_tables.find(p);
+    if (it != g_tables.end()) hp = it->second;
+  }
+  if (!hp) {
+    auto h = std::make_shared<HostTables>();
+    const int rc = compute_tables(p, h.get(), err);
+    if (rc != 0) return rc;
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    hp = g_tables.emplace(p, std::move(h)).first->second;
+  }
+  const HostTables& H = *hp;
+  const auto &oct = H.oct, &itab = H.itab;
+  const auto &rot = H.rot, &zt = H.zt, &geo = H.geo, &sf = H.sf, &rsc = H.rsc;
+  const auto &rot32 = H.rot32, &zt32 = H.zt32;
+  tb->rot_len = H.rlen;
+  tb->zt_len = H.zlen;
   RPY_HIP(hipMalloc(&tb->oct, sizeof(double2) * oct.size()));
   RPY_HIP(hipMalloc(&tb->itab, sizeof(double2) * itab.size()));
   RPY_HIP(hipMalloc(&tb->rot64, sizeof(double) * rot.size()));
@@ -296,9 +348,6 @@ int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   RPY_HIP(hipMalloc(&tb->zt32, sizeof(float) * zt32.size()));
   RPY_HIP(hipMalloc(&tb->geo, sizeof(double) * geo.size()));
   RPY_HIP(hipMalloc(&tb->sfac, sizeof(double) * sf.size()));
-  std::vector<double> rsc(ncoef(p));
-  for (int n = 0; n <= p; ++n)
-    for (int m = 0; m <= n; ++m) rsc[tri(n) + m] = 1.0 / (sf[tri(n) + m] * sf[tri(n) + m]);
   RPY_HIP(hipMalloc(&tb->rscale, sizeof(double) * rsc.size()));
   RPY_HIP(hipMemcpy(tb->rscale, rsc.data(), sizeof(double) * rsc.size(), hipMemcpyHostToDevice));
   tb->bytes = sizeof(double2) * (oct.size() + itab.size()) + (sizeof(double) + sizeof(float)) * (rot.size() + zt.size()) +
