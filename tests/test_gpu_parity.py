@@ -202,6 +202,42 @@ def test_multi_rhs_equals_separate_calls(orc):
         P.free()
 
 
+def test_repeated_and_overlapping_plans_agree(orc):
+    # later plans reuse the cached translation tables and the side streams of
+    # freed plans: a plan built again on the same beads gives the same
+    # velocities (up to the order of atomic FP64 sums in the adaptive
+    # S->L pass), also while plans of other orders are alive
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    w = W.uniform_cube(6000, 1.0, 0.01, nrhs=2, seed=83)
+    log("repeated and overlapping plans")
+    F = to_dev(w.forces)
+    pos = to_dev(w.pos)
+
+    def once(order):
+        P = R.Plan(pos, w.a, w.eta, 1e-6, leaf_size=60, order=order)
+        try:
+            u = P.matvec(F)
+            torch.cuda.synchronize()
+            return u.cpu().numpy()
+        finally:
+            P.free()
+
+    first = {o: once(o) for o in (9, 16)}
+    alive = [R.Plan(pos, w.a, w.eta, 1e-6, leaf_size=60, order=o) for o in (16, 9, 16)]
+    try:
+        outs = [P.matvec(F) for P in alive]
+        torch.cuda.synchronize()
+        for o, u in zip((16, 9, 16), outs):
+            assert orc.rel_l2(u.cpu().numpy(), first[o]) <= 1e-14
+    finally:
+        for P in alive:
+            P.free()
+    for o in (16, 9):
+        assert orc.rel_l2(once(o), first[o]) <= 1e-14
+    assert orc.rel_l2(first[16], orc.rpy_direct(w.pos, w.forces, w.a, w.eta)) <= 1e-6
+
+
 def test_edge_cases(orc):
     import paper_1711_02976_amd as R
     torch = torch_cuda()
