@@ -72,7 +72,7 @@ int make_p2e_tables(int p, Tables* tb, Error* err);  // p2e.hip; called by make_
 // Host helpers (fmm.hip): paper-normalised Y_n^m for 0 <= m <= n <= p at
 // (cos theta, phi); the rotation by +90 degrees about y on degree-n sets,
 // D[(m'+n)(2n+1) + (m+n)].
-void host_ynm(int p, double ct, double phi, std::vector<double2>& y);
+void host_ynm(int p, double ct, double phi, std::vector<double2>& y, int nlo = 0);
 void host_rot90(int n, std::vector<double>& D);
 void free_tables(Tables* tb);
 

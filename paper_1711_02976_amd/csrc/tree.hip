@@ -577,9 +577,12 @@ int grow_tree(Built* B, int need, hipStream_t s, Error* err) {
   int* fields_new[10];
   for (int f = 0; f < 10; ++f) {
     if (dalloc(&fields_new[f], ncap, B, err)) return -3;
-    if (fields_old[f]) {
+    if (fields_old[f])
       RPY_HIP(hipMemcpyAsync(fields_new[f], fields_old[f], sizeof(int) * B->cap, hipMemcpyDeviceToDevice, s));
-      RPY_HIP(hipStreamSynchronize(s));
+  }
+  RPY_HIP(hipStreamSynchronize(s));
+  for (int f = 0; f < 10; ++f) {
+    if (fields_old[f]) {
       RPY_HIP(hipFree(fields_old[f]));
       B->bytes -= sizeof(int) * B->cap;
     }
@@ -791,21 +794,35 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
   k_lists<<<nblocks(nbox, 64), 64, 0, s>>>(t, B->colleague, nbox, 0, lcnt, none[0], none[1], none[2], none[3],
                                            none[4], want_o, B->d_side, A.a);
   RPY_HIP(hipGetLastError());
+  // The five scans, then one read-back of their last offsets and counts.
+  // Copies to or from the host arrays below are drained before any return.
+  int lastc[5][2];
+  int tot32[5];
+  hipError_t le = hipSuccess;
+  int lrc = 0;
+  for (int L = 0; L < 5 && le == hipSuccess; ++L) {
+    if ((lrc = dalloc(&B->lists[L].off, nbox + 1, B, err)) != 0) break;
+    le = scan_exclusive(lcnt + (int64_t)L * nbox, B->lists[L].off, nbox, lt, s);
+    if (le == hipSuccess)
+      le = hipMemcpyAsync(&lastc[L][0], B->lists[L].off + nbox - 1, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (le == hipSuccess)
+      le = hipMemcpyAsync(&lastc[L][1], lcnt + (int64_t)L * nbox + nbox - 1, sizeof(int), hipMemcpyDeviceToHost, s);
+  }
+  hipError_t se = hipStreamSynchronize(s);
+  if (lrc) return lrc;
+  RPY_HIP(le);
+  RPY_HIP(se);
   for (int L = 0; L < 5; ++L) {
-    if (dalloc(&B->lists[L].off, nbox + 1, B, err)) return -3;
-    RPY_HIP(hipMemsetAsync(B->lists[L].off + nbox, 0, sizeof(int), s));
-    RPY_HIP(scan_exclusive(lcnt + (int64_t)L * nbox, B->lists[L].off, nbox, lt, s));
-    int lastc[2];
-    RPY_HIP(hipMemcpyAsync(&lastc[0], B->lists[L].off + nbox - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    RPY_HIP(hipMemcpyAsync(&lastc[1], lcnt + (int64_t)L * nbox + nbox - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    RPY_HIP(hipStreamSynchronize(s));
-    int64_t total = (int64_t)lastc[0] + lastc[1];
+    const int64_t total = (int64_t)lastc[L][0] + lastc[L][1];
     B->lists[L].len = total;
-    int tot32 = (int)total;
-    RPY_HIP(hipMemcpy(B->lists[L].off + nbox, &tot32, sizeof(int), hipMemcpyHostToDevice));
+    tot32[L] = (int)total;
     if (dalloc(&B->lists[L].ent, total, B, err)) return -3;
   }
-  RPY_HIP(hipStreamSynchronize(s));
+  for (int L = 0; L < 5 && le == hipSuccess; ++L)
+    le = hipMemcpyAsync(B->lists[L].off + nbox, &tot32[L], sizeof(int), hipMemcpyHostToDevice, s);
+  se = hipStreamSynchronize(s);
+  RPY_HIP(le);
+  RPY_HIP(se);
   k_lists<<<nblocks(nbox, 64), 64, 0, s>>>(t, B->colleague, nbox, 1, lcnt, B->lists[0], B->lists[1], B->lists[2],
                                            B->lists[3], B->lists[4], want_o, B->d_side, A.a);
   RPY_HIP(hipGetLastError());
