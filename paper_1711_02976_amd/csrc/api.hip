@@ -56,8 +56,9 @@ int order_for_eps(double eps, bool adaptive) {
 // library (uniform cube, sphere surface, Gaussian blobs and batched systems,
 // p = 16 and 21):
 //   * P2P and the direct W sums per ordered bead pair, with targets padded to
-//     whole 128-bead tiles; a pass of 4 right-hand sides costs about 2.3x a
-//     pass of one;
+//     whole 64-bead waves (a wave with no target in its 128-bead tile skips
+//     the pair loop); a pass of 4 right-hand sides costs about 2.3x a pass
+//     of one;
 //   * per density (4 per right-hand side): M2L per V pair (O(p^3)), upward
 //     and downward translations per box (O(p^4)), S->M and evaluation sets
 //     per leaf, S->L per (bead, X box) and W-multipole evaluation per
@@ -99,7 +100,7 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
     if (child[b] < 0) {
       if (lev[b] < max_depth) lo = std::max(lo, nb);
       nleaf += 1;
-      const double padded = 128.0 * ((nb + 127) / 128);
+      const double padded = 64.0 * ((nb + 63) / 64);
       double src = 0;
       for (int k = uo[b]; k < uo[b + 1]; ++k) src += end[ue[k]] - beg[ue[k]];
       for (int k = wo[b]; k < wo[b + 1]; ++k) {
