@@ -378,7 +378,8 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     // than the best whole matvec.
     // Every trial tree after the first copies the bounding cubes, Morton
     // keys and sorted order of the best one so far (they do not depend on
-    // the limit).  Trial trees are built without the O list: the overlapping
+    // the limit), into the bead arrays of the last discarded tree when there
+    // is one.  Trial trees are built without the O list: the overlapping
     // bead pairs are fixed by the geometry, not by the tree, and dense
     // clusters with small leaves make that list very long.  The chosen tree
     // is rebuilt with it when some leaf is smaller than 2a.
@@ -386,12 +387,14 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     for (int s = 0; s < nsys; ++s) nmax = std::max<int64_t>(nmax, counts[s]);
     double best = 0, sl = 64;
     bool need_o = false;
+    rpy::Spare spare;  // bead arrays of the last discarded tree
     for (;;) {
       const int cand = (int)sl;
       rpy::Built Bc;
       rpy::BuildArgs ba{n, nsys, sb.data(), positions, cand, P->max_depth, a, P->stream};
       ba.skip_o = true;
       ba.presorted = P->leaf_size != 0 ? &P->B : nullptr;
+      ba.spare = &spare;
       rc = rpy::build_tree(ba, &Bc, &err);
       TreeCost tc;
       if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, o.nrhs, &tc);
@@ -401,7 +404,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       }
       const bool first = P->leaf_size == 0;
       if (first || tc.ns < best) {
-        if (!first) rpy::free_built(&P->B);
+        if (!first) rpy::retire_built(&P->B, &spare);
         P->B = Bc;
         P->leaf_size = cand;
         best = tc.ns;
@@ -409,7 +412,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
         for (int s = 0; s < nsys; ++s)
           if (ldexp(P->B.side[s], -P->B.depth) < 2.0 * a) need_o = true;
       } else {
-        rpy::free_built(&Bc);
+        rpy::retire_built(&Bc, &spare);
       }
       if (cand >= nmax || tc.same_hi > nmax) break;  // one leaf per system from here on
       // coarser trees only add near-field pairs: once this tree's near field
@@ -422,10 +425,12 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       rpy::Built Bo;
       rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
       ba.presorted = &P->B;
+      ba.spare = &spare;
       rc = rpy::build_tree(ba, &Bo, &err);
       rpy::free_built(&P->B);
       P->B = Bo;
     }
+    rpy::free_spare(&spare);
   }
   if (rc == 0 && P->p == 0)
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);

@@ -65,6 +65,15 @@ hipError_t radix_sort(uint64_t** keys, int** vals, uint64_t* kalt, int* valt, in
                       int sys_passes, const int* sys_begin, int nsys, hipStream_t s);
 
 // ---- tree build (tree.hip) ---------------------------------------------
+// The bead-sized arrays of a discarded trial tree (n entries each), kept for
+// the next trial tree of the same beads instead of being freed.
+struct Spare {
+  int64_t n = -1;  // -1: empty
+  uint64_t* keys = nullptr;
+  int* perm = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+};
+
 struct BuildArgs {
   int64_t n;
   int nsys;
@@ -76,6 +85,7 @@ struct BuildArgs {
   hipStream_t stream;
   bool skip_o = false;          // leave the O list empty (trial trees of the leaf-size search)
   const struct Built* presorted = nullptr;  // a tree of the same beads: copy its cubes and sort
+  Spare* spare = nullptr;                   // with presorted: bead arrays to reuse, if any
 };
 
 // Everything rpy_plan builds on the device.  Owned buffers are released by
@@ -119,6 +129,10 @@ struct Built {
 
 int build_tree(const BuildArgs& a, Built* out, Error* err);
 void free_built(Built* b);
+// Moves b's bead arrays into an empty spare (else leaves them in b); then
+// frees what is left of b.
+void retire_built(Built* b, Spare* spare);
+void free_spare(Spare* spare);
 
 }  // namespace rpy
 

@@ -596,6 +596,30 @@ int grow_tree(Built* B, int need, hipStream_t s, Error* err) {
 
 }  // namespace
 
+void retire_built(Built* b, Spare* spare) {
+  if (!b) return;
+  if (spare && spare->n < 0 && b->keys && b->perm && b->sx && b->sy && b->sz) {
+    spare->n = b->n;
+    spare->keys = b->keys;
+    spare->perm = b->perm;
+    spare->sx = b->sx;
+    spare->sy = b->sy;
+    spare->sz = b->sz;
+    b->keys = nullptr;
+    b->perm = nullptr;
+    b->sx = b->sy = b->sz = nullptr;
+  }
+  free_built(b);
+}
+
+void free_spare(Spare* spare) {
+  if (!spare) return;
+  void* ps[] = {spare->keys, spare->perm, spare->sx, spare->sy, spare->sz};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  *spare = Spare{};
+}
+
 void free_built(Built* b) {
   if (!b) return;
   void* ps[] = {b->keys, b->perm, b->sx, b->sy, b->sz, b->d_lo, b->d_side, b->d_sys_begin,
@@ -633,10 +657,20 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
     }
     B->lo = S->lo;
     B->side = S->side;
-    if (dalloc(&B->d_lo, 3 * nsys, B, err) || dalloc(&B->d_side, nsys, B, err) || dalloc(&B->keys, n, B, err) ||
-        dalloc(&B->perm, n, B, err) || dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) ||
-        dalloc(&B->sz, n, B, err))
+    Spare* sp = A.spare;
+    if (sp && sp->n == n) {
+      B->keys = sp->keys;
+      B->perm = sp->perm;
+      B->sx = sp->sx;
+      B->sy = sp->sy;
+      B->sz = sp->sz;
+      B->bytes += (int64_t)std::max<int64_t>(n, 1) * (sizeof(uint64_t) + sizeof(int) + 3 * sizeof(double));
+      *sp = Spare{};
+    } else if (dalloc(&B->keys, n, B, err) || dalloc(&B->perm, n, B, err) || dalloc(&B->sx, n, B, err) ||
+               dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) {
       return -3;
+    }
+    if (dalloc(&B->d_lo, 3 * nsys, B, err) || dalloc(&B->d_side, nsys, B, err)) return -3;
     RPY_HIP(hipMemcpyAsync(B->d_lo, S->d_lo, sizeof(double) * 3 * nsys, hipMemcpyDeviceToDevice, s));
     RPY_HIP(hipMemcpyAsync(B->d_side, S->d_side, sizeof(double) * nsys, hipMemcpyDeviceToDevice, s));
     if (n > 0) {
