@@ -172,6 +172,7 @@ void host_rot90(int n, std::vector<double>& D) {
   gauss_legendre(n + 1, gx, gw);
   const int nphi = 2 * n + 1;
   std::vector<double2> y, yr;
+  std::vector<double> ax(W), ay(W), bx(W), by(W);
   for (int i = 0; i <= n; ++i) {
     double ct = gx[i], st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
     for (int k = 0; k < nphi; ++k) {
@@ -183,15 +184,20 @@ void host_rot90(int n, std::vector<double>& D) {
       host_ynm(n, ct, ph, y, n);
       host_ynm(n, ctr, phr, yr, n);
       double wt = gw[i] * (2.0 * M_PI / nphi) * (2 * n + 1) / (4.0 * M_PI);
-      for (int mp = -n; mp <= n; ++mp) {
-        double2 a = y[tri(n) + std::abs(mp)];
-        if (mp < 0) a.y = -a.y;
-        for (int m = -n; m <= n; ++m) {
-          double2 b = yr[tri(n) + std::abs(m)];
-          if (m < 0) b.y = -b.y;
-          // Re(conj(a) b)
-          D[(size_t)(mp + n) * W + (m + n)] += wt * (a.x * b.x + a.y * b.y);
-        }
+      // degree-n values for orders -n..n (Y_n^{-m} = conj(Y_n^m) up to the
+      // (-1)^m that cancels in the product below)
+      for (int m = -n; m <= n; ++m) {
+        const double2 u = y[tri(n) + std::abs(m)], v = yr[tri(n) + std::abs(m)];
+        ax[m + n] = u.x;
+        ay[m + n] = m < 0 ? -u.y : u.y;
+        bx[m + n] = v.x;
+        by[m + n] = m < 0 ? -v.y : v.y;
+      }
+      for (int r = 0; r < W; ++r) {
+        const double arx = ax[r], ary = ay[r];
+        double* row = &D[(size_t)r * W];
+        // Re(conj(a) b)
+        for (int c = 0; c < W; ++c) row[c] += wt * (arx * bx[c] + ary * by[c]);
       }
     }
   }
@@ -199,8 +205,8 @@ void host_rot90(int n, std::vector<double>& D) {
 
 namespace {
 // Host images of the translation tables of one order.  They depend on the
-// order alone, so each order is computed once per process (13 ms of host
-// work at p = 16, 37 ms at p = 21, 0.11 s at p = 27) and every later plan
+// order alone, so each order is computed once per process (12 ms of host
+// work at p = 16, 32 ms at p = 21, 87 ms at p = 27) and every later plan
 // only uploads it.
 struct HostTables {
   std::vector<double2> oct, itab;
