@@ -138,6 +138,7 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   return 0;
 }
 
+
 // Side streams of freed plans, kept per device for later plans: creating a
 // stream costs about a millisecond of host time, a large share of a repeated
 // plan.  A pooled stream is idle (its plan synchronised it before handing it
@@ -177,7 +178,6 @@ void give_stream(hipStream_t st) {
   (void)hipGetLastError();
   (void)hipStreamDestroy(st);
 }
-
 }  // namespace
 
 struct rpy_plan_s {
