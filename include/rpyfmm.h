@@ -209,10 +209,8 @@ rpy_status rpy_plan_set_timing(rpy_plan_t* plan, int32_t enable);
 rpy_status rpy_plan_timings(rpy_plan_t* plan, rpy_timings_t* out);
 
 /* Release a plan and its device memory; NULL is a no-op.  Waits for the
- * plan's streams first.  The plan's two internal side streams are kept by the
- * library for later plans on the same device (at most 8 per device, until
- * the process ends).  The host images of the translation tables stay cached
- * per expansion order for the life of the process. */
+ * plan's streams first.  The host images of the translation tables stay
+ * cached per expansion order for the life of the process. */
 void rpy_plan_free(rpy_plan_t* plan);
 
 const char* rpy_status_string(rpy_status s);

@@ -7,8 +7,6 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -138,46 +136,6 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   return 0;
 }
 
-
-// Side streams of freed plans, kept per device for later plans: creating a
-// stream costs about a millisecond of host time, a large share of a repeated
-// plan.  A pooled stream is idle (its plan synchronised it before handing it
-// back); at most kStreamPool are kept per device, the rest are destroyed.
-constexpr size_t kStreamPool = 8;
-std::mutex g_streams_mu;
-std::map<int, std::vector<hipStream_t>> g_streams;
-
-hipError_t take_stream(hipStream_t* out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  {
-    std::lock_guard<std::mutex> lk(g_streams_mu);
-    std::vector<hipStream_t>& v = g_streams[dev];
-    if (!v.empty()) {
-      *out = v.back();
-      v.pop_back();
-      return hipSuccess;
-    }
-  }
-  // default priority (no priority argument)
-  return hipStreamCreateWithFlags(out, hipStreamNonBlocking);
-}
-
-void give_stream(hipStream_t st) {
-  if (!st) return;
-  hipDevice_t dev = 0;
-  if (hipStreamGetDevice(st, &dev) == hipSuccess) {
-    std::lock_guard<std::mutex> lk(g_streams_mu);
-    std::vector<hipStream_t>& v = g_streams[(int)dev];
-    if (v.size() < kStreamPool) {
-      v.push_back(st);
-      return;
-    }
-  }
-  (void)hipGetLastError();
-  (void)hipStreamDestroy(st);
-}
 }  // namespace
 
 struct rpy_plan_s {
@@ -442,21 +400,21 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (rc == 0) {
     // default priority (no priority argument); without it the near field
     // runs on the plan's stream
-    if (take_stream(&P->near) != hipSuccess ||
+    if (hipStreamCreateWithFlags(&P->near, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
-      give_stream(P->near);
+      if (P->near) (void)hipStreamDestroy(P->near);
       if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
       if (P->ev_join) (void)hipEventDestroy(P->ev_join);
       P->near = nullptr;
       P->ev_fork = P->ev_join = nullptr;
     }
-    if (take_stream(&P->far2) != hipSuccess ||
+    if (hipStreamCreateWithFlags(&P->far2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&P->ev_p2m, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->ev_m2l0, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
-      give_stream(P->far2);
+      if (P->far2) (void)hipStreamDestroy(P->far2);
       if (P->ev_p2m) (void)hipEventDestroy(P->ev_p2m);
       if (P->ev_m2l0) (void)hipEventDestroy(P->ev_m2l0);
       P->far2 = nullptr;
@@ -811,12 +769,12 @@ void rpy_plan_free(rpy_plan_t* P) {
   if (P->near) (void)hipStreamSynchronize(P->near);
   if (P->far2) (void)hipStreamSynchronize(P->far2);
   fold_events(P);
-  give_stream(P->far2);
+  if (P->far2) (void)hipStreamDestroy(P->far2);
   if (P->ev_p2m) (void)hipEventDestroy(P->ev_p2m);
   if (P->ev_m2l0) (void)hipEventDestroy(P->ev_m2l0);
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
-  give_stream(P->near);
+  if (P->near) (void)hipStreamDestroy(P->near);
   for (hipEvent_t e : P->ev_pool) (void)hipEventDestroy(e);
   free_ws(P);
   if (P->kbuf) (void)hipFree(P->kbuf);

@@ -203,8 +203,8 @@ def test_multi_rhs_equals_separate_calls(orc):
 
 
 def test_repeated_and_overlapping_plans_agree(orc):
-    # later plans reuse the cached translation tables and the side streams of
-    # freed plans: a plan built again on the same beads gives the same
+    # later plans reuse the cached translation tables: a plan built again on
+    # the same beads gives the same
     # velocities (up to the order of atomic FP64 sums in the adaptive
     # S->L pass), also while plans of other orders are alive
     import paper_1711_02976_amd as R
