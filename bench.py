@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the RPY mobility matvec on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube-1M]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube-15M]
 
-A step is one full matvec (tree reused): permute, near field (P2P + overlap
-correction), S->M, M->M, M->L, S->L, L->L, target evaluation (eq. 2.8) and
-un-permute, over device-resident forces.  After the timed region each form
-also draws Brownian displacement directions D^{1/2} z once (rpy_sqrt_matvec,
-z = the force vectors), reported under "brownian".  Prints one JSON line with the
+A step is one full matvec over all right-hand sides (tree reused): permute,
+near field (P2P + overlap correction), S->M, M->M, M->L, S->L, L->L, target
+evaluation (eq. 2.8) and un-permute, over device-resident forces.  The default
+workload is the largest single-GPU one: 15,000,000 beads uniform in a cube of
+side 2,000 (a = 0.5, eta = 1) with 20 right-hand sides per matvec, eps 1e-6,
+timed in the plain FP64 form and the mixed-precision form.  Each timed call
+is bracketed by HIP events on the plan's stream; ms_per_step is the median.
+After the timed region each form may draw Brownian displacement directions
+D^{1/2} z once (rpy_sqrt_matvec, z = the force vectors) when that fits the
+time budget, reported under "brownian".  Prints one JSON line with the
 metric, the live roofline of the dominant kernel (HIP events around each
-phase inside the timed region) and the FP64 CPU oracle timed on a bounded
-sample of the same workload (which also gates the accuracy).
+phase inside the timed region), the M2L and bead-pass rates, and the FP64 CPU
+oracle timed on a bounded sample of the same workload (which also gates the
+accuracy).
 """
 from __future__ import annotations
 
@@ -40,7 +46,8 @@ def progress(msg):
 
 def algorithmic_counts(P, p, nrc):
     """Algorithmic flops per launch of the P2P and M2L kernels, from the
-    plan's lists (host arithmetic on exported integers only)."""
+    plan's lists (host arithmetic on exported integers only); nrc is the
+    number of right-hand sides one launch carries."""
     ex = P.export()
     boxes = ex["boxes"]
     cnt = boxes[:, 5] - boxes[:, 4]
@@ -54,9 +61,14 @@ def algorithmic_counts(P, p, nrc):
     vo, _ = ex["lists"]["V"]
     npair_v = int(vo[-1])
     T = (p + 1) * (p + 2) // 2
-    # P2P: 8 flops of geometry + 12 for the RPY coefficients per pair, and 18
-    # per right-hand side (d.F, the scaled dyad and the accumulate).
-    p2p_flops = pairs * (20 + 18 * nrc)
+    # P2P, the measurement's per-pair count: about 16 flops and a reciprocal
+    # square root of geometry shared by the right-hand sides, and 12 flops
+    # per right-hand side (u += A F + B (d.F) d).
+    p2p_flops = pairs * (16 + 12 * nrc)
+    # This kernel's own count of the same work: 8 flops for the difference
+    # and r^2, 12 for the RPY coefficients, and per right-hand side 18 (d.F,
+    # the scaled dyad and the three accumulating multiply-adds).
+    p2p_flops_kernel = pairs * (20 + 18 * nrc)
     # M2L (dense): per V pair and density, T x (p+1)^2 complex multiply-adds.
     m2l_flops = npair_v * 4 * nrc * T * (p + 1) ** 2 * 8
     # M2L (rotation): per V pair and density, four real-split rotations of
@@ -65,8 +77,25 @@ def algorithmic_counts(P, p, nrc):
     # (the O(p^2) diagonal phase and scale factors are not counted).
     S = (p + 1) * (p + 2) * (2 * p + 3) // 6
     m2l_rot_flops = npair_v * 4 * nrc * 20 * S
-    return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "m2l_flops": m2l_flops,
-            "m2l_rot_flops": m2l_rot_flops}
+    return {"p2p_pairs": pairs, "v_pairs": npair_v, "p2p_flops": p2p_flops, "p2p_flops_kernel": p2p_flops_kernel,
+            "m2l_flops": m2l_flops, "m2l_rot_flops": m2l_rot_flops}
+
+
+def bead_pass_bytes(n, sort_passes):
+    """Algorithmic bytes of the plan's bead passes: 24 per bead for the
+    bounding cube, 36 for the keys, 24 per radix pass and 48 for the
+    position gather."""
+    return n * (24 + 36 + 24 * sort_passes + 48)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def traffic_for(kernel_file, launches_key):
@@ -91,7 +120,13 @@ def run(args):
     import paper_1711_02976_amd as R
     import workloads as W
 
-    w = W.config(WORKLOADS[args.workload], nsample=args.cpu_targets)
+    cid = WORKLOADS[args.workload]
+    k = args.cpu_targets
+    if k <= 0:
+        w0 = W.config(cid, scale=1e-3)  # bead and rhs counts of the full workload, cheaply
+        n_full, r_full = round(w0.n * 1e3), w0.nrhs
+        k = int(min(12000, max(200, 6e9 / (n_full * (1 + 0.25 * r_full)))))
+    w = W.config(cid, nsample=k)
     if args.eps:
         import dataclasses
         w = dataclasses.replace(w, eps=args.eps)
@@ -116,15 +151,21 @@ def run(args):
             progress(f"{w.name} {prec}: warm-up matvec done")
         torch.cuda.synchronize()
         P.set_timing(True)
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for e0, e1 in ev:
+            e0.record(stream)
             P.matvec(F, out=U)
+            e1.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         tm = P.timings()
-        ms = (t1 - t0) * 1e3 / args.steps
-        progress(f"{w.name} {prec}: {args.steps} timed matvecs, {ms:.2f} ms each")
+        calls = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        ms = float(np.median(calls))
+        wall_ms = (t1 - t0) * 1e3 / args.steps
+        progress(f"{w.name} {prec}: {args.steps} timed matvecs, median {ms:.2f} ms (wall mean {wall_ms:.2f} ms)")
         # one more matvec, outside the timed region, with every phase run
         # alone on the plan stream: isolated per-phase times
         P.set_timing(2)
@@ -135,7 +176,7 @@ def run(args):
         # (rpy_sqrt_matvec), z = the standard-normal force vectors; skipped
         # when the iteration cap would take more than about 20 s
         brown = None
-        if args.brownian_tol > 0 and ms * args.brownian_iters <= 20e3:
+        if args.brownian_tol > 0 and ms * args.brownian_iters <= args.brownian_budget_s * 1e3:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, info = P.sqrt_matvec(F, tol=args.brownian_tol, max_iter=args.brownian_iters)
@@ -147,8 +188,12 @@ def run(args):
                      f"converged={info['converged']}")
         nrc = 4 if w.nrhs >= 4 else (2 if w.nrhs >= 2 else 1)
         alg = algorithmic_counts(P, st["order"], nrc)
-        results[prec] = {"plan": P, "stats": st, "ms": ms, "timings": tm, "serial": tms, "alg": alg, "brownian": brown,
-                         "u": U[:, w.sample].cpu().numpy()}
+        results[prec] = {"stats": st, "ms": ms, "wall_ms": wall_ms, "calls_ms": calls, "timings": tm,
+                         "serial": tms, "alg": alg, "brownian": brown,
+                         "u": U[:, torch.as_tensor(w.sample, device=dev)].cpu().numpy()}
+        # plan memory is released before the next form is planned
+        P.free()
+        torch.cuda.empty_cache()
 
     # CPU baseline: the FP64 oracle's direct sum on the sampled targets.
     cpu = None
@@ -161,9 +206,11 @@ def run(args):
         ref = oracle.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
         tc = time.perf_counter() - t0
         cpu = {"value": k * w.nrhs / tc, "unit": "beads*matvecs/s", "cores": oracle.max_threads(),
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"direct O(N^2) FP64 sum for {k} sampled targets of {w.n} (all sources, "
-                         f"nrhs={w.nrhs}), {tc:.2f} s; value = targets*rhs/s"}
+                         f"nrhs={w.nrhs}), {tc:.2f} s; value = targets*rhs/s",
+               "pairs_per_s": k * w.n / tc,
+               "full_matvec_s_extrapolated": tc * w.n / k}
         for prec, r in results.items():
             errs[prec] = oracle.rel_l2(r["u"], ref)
 
@@ -172,25 +219,64 @@ def run(args):
     best = min(ok or list(results), key=lambda p: results[p]["ms"])
     r = results[best]
     value = w.n * w.nrhs / (r["ms"] * 1e-3)
+    mixed = best == "mixed"
+
+    def rates(q, is_mixed):
+        """Live rates of one form from the HIP events of the timed region:
+        P2P flop/s against the vector peak of its precision, by the
+        measurement's per-pair count (16 flops of geometry per launch and 12
+        per right-hand side) and by this kernel's own count; M2L flop/s of
+        the rotation operator (20 S flops per V pair and density) against
+        the same peak (no MFMA instruction is issued)."""
+        tm = q["timings"]
+        steps = max(args.steps, 1)
+        L_p2p = tm["launches"]["p2p"] / steps
+        t_p2p = tm["ms"]["p2p"] / steps * 1e-3
+        pairs, npv = q["alg"]["p2p_pairs"], q["alg"]["v_pairs"]
+        p = q["stats"]["order"]
+        S = (p + 1) * (p + 2) * (2 * p + 3) // 6
+        peak = PEAK_FP32_TFLOPS if is_mixed else PEAK_FP64_TFLOPS
+        f_p2p = pairs * (16 * L_p2p + 12 * w.nrhs)
+        f_p2p_kernel = pairs * (20 * L_p2p + 18 * w.nrhs)
+        t_m2l = tm["ms"]["m2l"] / steps * 1e-3
+        f_m2l = npv * 4 * w.nrhs * 20 * S
+        out = {"p2p": {"launches_per_matvec": L_p2p, "ms_per_matvec": round(t_p2p * 1e3, 4),
+                       "avg_launch_ms": round(t_p2p * 1e3 / max(L_p2p, 1), 4),
+                       "pairs": pairs, "flops_per_matvec": f_p2p,
+                       "achieved_tflops": round(f_p2p / t_p2p / 1e12, 3) if t_p2p > 0 else None,
+                       "frac": round(f_p2p / t_p2p / 1e12 / peak, 4) if t_p2p > 0 else None,
+                       "kernel_count_tflops": round(f_p2p_kernel / t_p2p / 1e12, 3) if t_p2p > 0 else None,
+                       "peak_tflops": peak},
+               "m2l": {"ms_per_matvec": round(t_m2l * 1e3, 4), "v_pairs": npv, "flops_per_matvec": f_m2l,
+                       "achieved_tflops": round(f_m2l / t_m2l / 1e12, 3) if t_m2l > 0 else None,
+                       "frac": round(f_m2l / t_m2l / 1e12 / peak, 4) if t_m2l > 0 else None,
+                       "peak_tflops": peak, "mfma_instructions": 0}}
+        st = q["stats"]
+        if st.get("bead_pass_ms", 0) > 0:
+            b = bead_pass_bytes(w.n, st["sort_passes"])
+            gbs = b / (st["bead_pass_ms"] * 1e-3) / 1e9
+            out["bead_passes"] = {"ms": round(st["bead_pass_ms"], 4), "bytes": b, "achieved_gbs": round(gbs, 1),
+                                  "frac": round(gbs / PEAK_HBM_GBS, 4), "sort_passes": st["sort_passes"]}
+        return out
+
+    rr = rates(r, mixed)
+    dom = max(("p2p", "m2l"), key=lambda k: rr[k]["ms_per_matvec"])
+    d = rr[dom]
+    if dom == "p2p":
+        launches = max(d["launches_per_matvec"], 1)
+        roof = {"bound": "alu", "kernel": "k_p2p", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
+                "unit": "TFLOP/s", "frac": d["frac"],
+                "traffic": traffic_for("nearfield.hip", f"p2p:{args.workload}:{best}"),
+                "avg_launch_ms": d["avg_launch_ms"], "algorithmic_flops_per_launch": d["flops_per_matvec"] / launches,
+                "count": "per ordered pair: 16 flops + 1 rsqrt per launch, 12 flops per right-hand side",
+                "kernel_count_achieved": d["kernel_count_tflops"]}
+    else:
+        roof = {"bound": "alu", "kernel": "k_m2l_rot", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
+                "unit": "TFLOP/s", "frac": d["frac"], "traffic": None,
+                "algorithmic_flops_per_matvec": d["flops_per_matvec"],
+                "count": "per V pair and density: 20 S flops, S = sum_n (n+1)^2"}
     tm = r["timings"]
     phase_ms = {k: v / max(args.steps, 1) for k, v in tm["ms"].items()}
-    dom = max(("p2p", "m2l"), key=lambda k: tm["ms"][k])
-    launches = max(tm["launches"][dom], 1)
-    avg_ms = tm["ms"][dom] / launches
-    mixed = best == "mixed"
-    if dom == "p2p":
-        flops = r["alg"]["p2p_flops"]
-        peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
-        kfile = "nearfield.hip"
-    else:
-        dense = r["stats"].get("m2l_mode", 1) == 1
-        flops = r["alg"]["m2l_flops"] if dense else r["alg"]["m2l_rot_flops"]
-        peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
-        kfile = "fmm.hip" if dense else "m2l_rot.hip"
-    achieved = flops / (avg_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic_for(kfile, f"{dom}:{args.workload}:{best}"),
-            "avg_launch_ms": round(avg_ms, 4), "algorithmic_flops_per_launch": flops}
     line = {
         "metric": METRIC,
         "value": value,
@@ -208,16 +294,21 @@ def run(args):
                    "precision": best, "order": r["stats"]["order"], "leaf_size": r["stats"]["leaf_size"],
                    "boxes": r["stats"]["nbox"], "depth": r["stats"]["depth"],
                    "plan_ms": round(r["stats"]["plan_ms"], 2)},
+        "timing": "median of per-call HIP-event times on the plan stream",
         "rel_l2_vs_direct": errs.get(best),
         "phases_ms": {k: round(v, 4) for k, v in phase_ms.items()},
         "phases_serial_ms": {k: round(v, 4) for k, v in r["serial"]["ms"].items()},
-        "forms": {p: {"ms_per_step": round(q["ms"], 4), "value": w.n * w.nrhs / (q["ms"] * 1e-3),
-                      "rel_l2_vs_direct": errs.get(p), "brownian": q["brownian"]} for p, q in results.items()},
+        "forms": {p: {"ms_per_step": round(q["ms"], 4), "ms_mean_wall": round(q["wall_ms"], 4),
+                      "ms_min": round(q["calls_ms"][0], 4), "ms_max": round(q["calls_ms"][-1], 4),
+                      "value": w.n * w.nrhs / (q["ms"] * 1e-3), "rel_l2_vs_direct": errs.get(p),
+                      "plan_ms": round(q["stats"]["plan_ms"], 2), "order": q["stats"]["order"],
+                      "leaf_size": q["stats"]["leaf_size"], "rates": rates(q, p == "mixed"),
+                      "brownian": q["brownian"]} for p, q in results.items()},
+        "speedup_mixed_vs_fp64": (round(results["fp64"]["ms"] / results["mixed"]["ms"], 3)
+                                  if "fp64" in results and "mixed" in results else None),
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    for q in results.values():
-        q["plan"].free()
     print(json.dumps(line), flush=True)
     if errs and errs[best] > w.eps:
         print(f"accuracy gate failed: rel-L2 {errs[best]:.3e} > {w.eps:.0e}", file=sys.stderr)
@@ -292,19 +383,22 @@ def copy_probe(mib):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube-1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cube-15M", choices=sorted(WORKLOADS))
     ap.add_argument("--precisions", default="fp64,mixed", help="comma list of forms to time: fp64,mixed")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--brownian-tol", type=float, default=1e-3,
                     help="after the timed matvecs, one rpy_sqrt_matvec at this tolerance (0: skip)")
     ap.add_argument("--brownian-iters", type=int, default=60, help="iteration cap of that call")
+    ap.add_argument("--brownian-budget-s", type=float, default=20.0,
+                    help="skip that call when the iteration cap times the matvec time exceeds this many seconds")
     ap.add_argument("--order", type=int, default=0)
     ap.add_argument("--eps", type=float, default=0.0,
                     help="accuracy target in place of the workload's (e.g. 1e-9, the 9-digit setting)")
-    ap.add_argument("--cpu-targets", type=int, default=12000,
-                    help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate)")
+    ap.add_argument("--cpu-targets", type=int, default=0,
+                    help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate); 0: a "
+                         "sample of about 6e9 pair evaluations times right-hand sides, at least 200 targets")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")

@@ -40,13 +40,15 @@ typedef enum {
   RPY_ENONFINITE = -2,   /* a position is NaN or infinite */
   RPY_ENOMEM = -3,       /* device allocation failed */
   RPY_EDEVICE = -4,      /* a HIP call failed; sticky on the plan */
-  RPY_EUNSUPPORTED = -5  /* option combination not built */
+  RPY_EUNSUPPORTED = -5  /* option combination not built (reserved: every
+                            combination accepted by validation is built) */
 } rpy_status;
 
 typedef enum {
   RPY_PREC_FP64 = 0,   /* every kernel in FP64 */
-  RPY_PREC_MIXED = 1   /* near field and M2L in FP32 (pair differences and
-                          expansion storage/sums in FP64) */
+  RPY_PREC_MIXED = 1   /* P2P, the direct W sums and M2L in FP32 (pair
+                          differences, expansion storage, the overlap
+                          correction and every sum across kernels in FP64) */
 } rpy_precision;
 
 typedef struct {
@@ -69,6 +71,14 @@ typedef struct {
                             so larger leaves pay); 0 = 1.  Any nrhs may still
                             be passed to rpy_matvec.  Callers built against a
                             struct_size that ends at `stream` get 0. */
+  int32_t w_direct;      /* W-list evaluation (adaptive trees): a W box's
+                            contribution is the far formula summed over its
+                            beads, which its multipole approximates (Theorem
+                            1).  W boxes with at most w_direct beads are
+                            summed directly, the others through their
+                            multipoles.  0 = library choice, (p+1)(p+2);
+                            -1 = every W box through its multipole.  Callers
+                            whose struct_size ends before it get 0. */
 } rpy_options;
 
 typedef struct rpy_plan_s rpy_plan_t;
@@ -86,6 +96,15 @@ typedef struct {
   int64_t list_len[5];   /* entries of the U, V, W, X, O lists */
   int64_t device_bytes;  /* device memory held by the plan */
   double plan_ms;        /* wall time of rpy_plan / rpy_plan_batched */
+  int32_t w_direct;      /* W boxes of at most this many beads are summed
+                            directly (-1: none) */
+  int32_t p2l_items;     /* S->L work items (a box's X list may be split) */
+  int32_t p2l_split_boxes; /* boxes whose S->L work is split over several
+                            items (their shares are added in a fixed order) */
+  int32_t sort_passes;   /* radix-sort passes of the bead sort */
+  double bead_pass_ms;   /* GPU time of the bead passes of the plan's first
+                            tree: bounding cubes, Morton keys, radix sort,
+                            position gather */
 } rpy_plan_stats_t;
 
 /* Fills *opt with the defaults (FP64, automatic leaf size and order,
@@ -111,7 +130,11 @@ rpy_status rpy_plan(rpy_plan_t** out, int64_t n, const double* positions, double
 /* Build one plan for nsys independent systems whose beads are concatenated
  * in positions (device [sum counts][3]); counts is host [nsys].  Systems do
  * not interact; each gets its own bounding cube and tree, and one launch of
- * each kernel serves all of them. */
+ * each kernel serves all of them.  Each system is the paper's problem
+ * (Sec. 4.2: sources = targets, one radius per evaluation); the batch serves
+ * callers with many such systems, such as independent Brownian trajectories
+ * (Sec. 1).  Validation and errors as for rpy_plan; counts may contain
+ * zeros, and n = sum counts must be below 2^31 - 1. */
 rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* counts,
                             const double* positions, double a, double eta, double eps,
                             const rpy_options* opt);
@@ -158,11 +181,17 @@ typedef struct {
 rpy_status rpy_sqrt_matvec(rpy_plan_t* plan, int32_t nrhs, const double* z, double* y, double tol,
                            int32_t max_iter, rpy_sqrt_info_t* info);
 
-/* Sizes and settings of a plan (host struct). */
+/* Sizes and settings of a plan (host struct *out, caller allocated): the
+ * tree depth and refinement limit (Sec. 4.2 "threshold"), the expansion
+ * order, the lengths of the adaptive FMM's U, V, W, X lists (Sec. 2, Fig. 1)
+ * and of the O list, and device memory.  RPY_EINVAL for NULL. */
 rpy_status rpy_plan_stats(const rpy_plan_t* plan, rpy_plan_stats_t* out);
 
-/* Copy the tree out for inspection and tests (all host arrays, caller
- * allocated; any pointer may be NULL to skip it):
+/* Copy the tree out for inspection and tests: the adaptive octree of the
+ * refinement limit (Sec. 4.2) and the interaction lists of Fig. 1's
+ * operators (U: S->T, V: M->L, W: M->T, X: S->L).  All host arrays, caller
+ * allocated and sized from rpy_plan_stats; any pointer may be NULL to skip
+ * it.  Waits for the plan's stream; RPY_EDEVICE if a copy fails:
  *   perm     [n]          caller index of the k-th bead in tree order
  *   keys     [n]          63-bit Morton keys in tree order
  *   boxes    [nbox][8]    level, anchor x, y, z, begin, end, parent,
@@ -207,6 +236,14 @@ rpy_status rpy_plan_set_timing(rpy_plan_t* plan, int32_t enable);
 
 /* Waits for the plan's stream, folds all recorded events into *out. */
 rpy_status rpy_plan_timings(rpy_plan_t* plan, rpy_timings_t* out);
+
+/* Failure-path testing: the next matvec pass of the plan reports a HIP
+ * error at `phase` (an rpy_phase) instead of issuing that phase, exactly as
+ * a failed launch would: rpy_matvec returns RPY_EDEVICE, nothing after the
+ * failed phase is issued, and the plan is in the sticky error state.
+ * phase = -1 clears a pending injection.  Returns RPY_EINVAL for other
+ * values.  No kernel is made to fail on the device. */
+rpy_status rpy_plan_inject_error(rpy_plan_t* plan, int32_t phase);
 
 /* Release a plan and its device memory; NULL is a no-op.  Waits for the
  * plan's streams first.  The host images of the translation tables stay

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rpy_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-GCC_CMD = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+GCC_CMD = ["gcc", "-O3", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
            "-Wall", "-o", _LIB, _SRC, "-lm"]
 
 
@@ -59,7 +59,7 @@ def lib():
         L.orc_translate.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L.orc_eval_expansion.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_fmm.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, C.c_double, C.c_int,
-                              C.c_int, C.c_int, _dp, C.c_int]
+                              C.c_int, C.c_int, C.c_int64, _dp, C.c_int]
         L.orc_fmm.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
         L.orc_rpy_dense.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
@@ -246,9 +246,11 @@ class Tree:
         return self.lo[None, :] + (self.anchor + 0.5) * h[:, None]
 
 
-def fmm(pos, forces, a, eta, p, leaf_size, max_depth=14, nthreads=0):
+def fmm(pos, forces, a, eta, p, leaf_size, w_direct, max_depth=14, nthreads=0):
     """The four-Laplace adaptive FMM (O4) in FP64.  forces [nrhs,n,3] or
-    [n,3]; returns the same shape."""
+    [n,3]; returns the same shape.  W-list boxes with at most w_direct beads
+    are summed directly with the far formula, the others through their
+    multipoles (w_direct < 0: all through multipoles); the caller chooses."""
     pos = _f64(pos)
     F = _f64(forces)
     squeeze = F.ndim == 2
@@ -256,7 +258,7 @@ def fmm(pos, forces, a, eta, p, leaf_size, max_depth=14, nthreads=0):
         F = F[None]
     out = np.zeros_like(F)
     rc = lib().orc_fmm(pos.shape[0], pos, F.shape[0], F, a, eta, int(p), int(leaf_size),
-                       int(max_depth), out, nthreads)
+                       int(max_depth), int(w_direct), out, nthreads)
     if rc != 0:
         raise ValueError("orc_fmm rejected its arguments")
     return out[0] if squeeze else out

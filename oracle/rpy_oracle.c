@@ -94,38 +94,61 @@ void orc_rpy_block(const double d[3], double a, double eta, double out[9]) {
     for (int j = 0; j < 3; ++j) out[3 * i + j] = (i == j ? A : 0.0) + B * d[i] * d[j];
 }
 
-/* Neumaier-compensated accumulation. */
+/* Compensated accumulation (Neumaier's scheme): the exact rounding error of
+ * each addition s + t, obtained by Knuth's branch-free TwoSum, is collected
+ * in c, and the result is s + c. */
 static inline void neu_add(double* s, double* c, double t) {
-  double u = *s + t;
-  if (fabs(*s) >= fabs(t)) *c += (*s - u) + t;
-  else *c += (t - u) + *s;
+  const double u = *s + t;
+  const double bp = u - *s;
+  *c += (*s - (u - bp)) + (t - bp);
   *s = u;
 }
 
 /* u_i = sum_j M(r_i - r_j) F_j over all beads j, self included (Sec. 1).
  * pos [n][3]; F [nrhs][n][3]; tgt (nullable) lists the nt target indices;
- * out [nrhs][nt][3].  Sums are Neumaier-compensated FP64. */
+ * out [nrhs][nt][3].  The 3x3 block of each pair is formed once and applied
+ * to every right-hand side; sums are Neumaier-compensated FP64. */
 void orc_rpy_direct(int64_t n, const double* pos, int nrhs, const double* F, double a,
                     double eta, int64_t nt, const int64_t* tgt, double* out, int nthreads) {
   set_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 8)
-  for (int64_t ti = 0; ti < nt; ++ti) {
-    int64_t i = tgt ? tgt[ti] : ti;
-    for (int r = 0; r < nrhs; ++r) {
-      double s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
-      const double* Fr = F + (size_t)r * n * 3;
+  /* forces regrouped per bead and component, [n][3][nrhs], so that one
+     source's right-hand sides are contiguous */
+  const size_t R = (size_t)nrhs;
+  double* Ft = malloc(sizeof(double) * 3 * R * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < n; ++j)
+    for (size_t r = 0; r < R; ++r)
+      for (int k = 0; k < 3; ++k) Ft[((size_t)j * 3 + k) * R + r] = F[(r * n + j) * 3 + k];
+#pragma omp parallel
+  {
+    /* per component k and right-hand side r: sum s and compensation c */
+    double* s = malloc(sizeof(double) * 6 * R);
+    double* c = s + 3 * R;
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t ti = 0; ti < nt; ++ti) {
+      int64_t i = tgt ? tgt[ti] : ti;
+      for (size_t q = 0; q < 3 * R; ++q) s[q] = c[q] = 0.0;
       for (int64_t j = 0; j < n; ++j) {
         double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                        pos[3 * i + 2] - pos[3 * j + 2]};
         double M[9];
         orc_rpy_block(d, a, eta, M);
-        for (int k = 0; k < 3; ++k)
-          neu_add(&s[k], &c[k],
-                  M[3 * k] * Fr[3 * j] + M[3 * k + 1] * Fr[3 * j + 1] + M[3 * k + 2] * Fr[3 * j + 2]);
+        const double* fx = Ft + (size_t)j * 3 * R;
+        const double* fy = fx + R;
+        const double* fz = fy + R;
+        for (int k = 0; k < 3; ++k) {
+          const double m0 = M[3 * k], m1 = M[3 * k + 1], m2 = M[3 * k + 2];
+          double* sk = s + k * R;
+          double* ck = c + k * R;
+          for (size_t r = 0; r < R; ++r) neu_add(&sk[r], &ck[r], m0 * fx[r] + m1 * fy[r] + m2 * fz[r]);
+        }
       }
-      for (int k = 0; k < 3; ++k) out[((size_t)r * nt + ti) * 3 + k] = s[k] + c[k];
+      for (size_t r = 0; r < R; ++r)
+        for (int k = 0; k < 3; ++k) out[(r * nt + ti) * 3 + k] = s[k * R + r] + c[k * R + r];
     }
+    free(s);
   }
+  free(Ft);
 }
 
 /* ------------------------------------------------------------------ O5 --- */
@@ -766,14 +789,17 @@ static void box_center(const orc_tree* t, int64_t b, double c[3]) {
  * assembles eq. (2.8); U-list beads are summed directly with the exact RPY
  * block, and O-list pairs with r < 2a receive (M_overlap - M_far) F.
  * The paper leaves the evaluation of W lists to the adaptive FMM it builds
- * on; here a W box with at most (p+1)(p+2) beads is summed directly with
- * the far formula (cheaper than its multipole at that size, and exact for
- * what the far field represents), the others through Theorem 1.
+ * on.  A W box C's contribution at a target of B is the far formula summed
+ * over C's beads, which C's multipole approximates (Theorem 1); either form
+ * is a valid far field.  Here a W box with at most w_direct beads is summed
+ * directly with the far formula and the others go through Theorem 1
+ * (w_direct < 0: every W box through its multipole).  The threshold is an
+ * input, so that a caller can choose either branch for any W box.
  * pos [n][3], F [nrhs][n][3], out [nrhs][n][3], all in caller order.
  * Returns 0, or -1 for invalid arguments.
  */
 int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, double eta, int p,
-            int leaf_size, int max_depth, double* out, int nthreads) {
+            int leaf_size, int max_depth, int64_t w_direct, double* out, int nthreads) {
   if (n < 0 || p < 0 || p > 40 || nrhs < 1 || a <= 0 || eta <= 0 || leaf_size < 1) return -1;
   if (n == 0) return 0;
   set_threads(nthreads);
@@ -897,7 +923,7 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
         double wd[3] = {0, 0, 0};
         for (int64_t e = t->off[2][b]; e < t->off[2][b + 1]; ++e) {
           int64_t C = t->ent[2][e];
-          if (t->end[C] - t->begin[C] <= 2 * T) {
+          if (t->end[C] - t->begin[C] <= w_direct) {
             /* few beads: the far formula summed directly (what the far field
                stands for); the O list corrects pairs closer than 2a */
             for (int64_t j = t->begin[C]; j < t->end[C]; ++j) {

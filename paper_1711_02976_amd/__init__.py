@@ -34,14 +34,16 @@ LIST_NAMES = ("U", "V", "W", "X", "O")
 class rpy_options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("precision", C.c_int32), ("leaf_size", C.c_int32),
                 ("order", C.c_int32), ("max_depth", C.c_int32), ("m2l_mode", C.c_int32),
-                ("stream", C.c_void_p), ("nrhs", C.c_int32)]
+                ("stream", C.c_void_p), ("nrhs", C.c_int32), ("w_direct", C.c_int32)]
 
 
 class rpy_plan_stats_t(C.Structure):
     _fields_ = [("n", C.c_int64), ("nsys", C.c_int32), ("order", C.c_int32), ("leaf_size", C.c_int32),
                 ("depth", C.c_int32), ("precision", C.c_int32), ("m2l_mode", C.c_int32),
                 ("nbox", C.c_int64), ("nleaf", C.c_int64), ("list_len", C.c_int64 * 5),
-                ("device_bytes", C.c_int64), ("plan_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("plan_ms", C.c_double), ("w_direct", C.c_int32),
+                ("p2l_items", C.c_int32), ("p2l_split_boxes", C.c_int32), ("sort_passes", C.c_int32),
+                ("bead_pass_ms", C.c_double)]
 
 
 PHASES = ("permute", "p2p", "overlap", "p2m", "m2m", "m2l", "p2l", "l2l", "eval", "unpermute")
@@ -65,7 +67,7 @@ class RpyError(RuntimeError):
 _lib = None
 
 EXPORTED = ("rpy_default_options", "rpy_plan", "rpy_plan_batched", "rpy_matvec", "rpy_sqrt_matvec", "rpy_plan_stats",
-            "rpy_plan_export", "rpy_plan_set_timing", "rpy_plan_timings", "rpy_plan_free",
+            "rpy_plan_export", "rpy_plan_set_timing", "rpy_plan_timings", "rpy_plan_inject_error", "rpy_plan_free",
             "rpy_status_string", "rpy_last_error")
 
 
@@ -96,6 +98,8 @@ def lib():
         L.rpy_plan_set_timing.restype = C.c_int
         L.rpy_plan_timings.argtypes = [C.c_void_p, C.POINTER(rpy_timings_t)]
         L.rpy_plan_timings.restype = C.c_int
+        L.rpy_plan_inject_error.argtypes = [C.c_void_p, C.c_int32]
+        L.rpy_plan_inject_error.restype = C.c_int
         L.rpy_plan_free.argtypes = [C.c_void_p]
         L.rpy_status_string.argtypes = [C.c_int]
         L.rpy_status_string.restype = C.c_char_p
@@ -113,7 +117,8 @@ def _check(status):
 M2L_MODES = {"auto": 0, "dense": 1, "rotation": 2}
 
 
-def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=None, m2l="auto", nrhs=0):
+def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=None, m2l="auto", nrhs=0,
+                 w_direct=0):
     o = rpy_options()
     lib().rpy_default_options(C.byref(o))
     o.m2l_mode = M2L_MODES[m2l] if isinstance(m2l, str) else int(m2l)
@@ -123,6 +128,7 @@ def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=
     o.max_depth = int(max_depth)
     o.stream = stream
     o.nrhs = int(nrhs)
+    o.w_direct = int(w_direct)
     return o
 
 
@@ -161,7 +167,8 @@ def rpy_plan_stats(plan):
     return {"n": s.n, "nsys": s.nsys, "order": s.order, "leaf_size": s.leaf_size, "depth": s.depth,
             "precision": s.precision, "m2l_mode": s.m2l_mode, "nbox": s.nbox, "nleaf": s.nleaf,
             "list_len": dict(zip(LIST_NAMES, list(s.list_len))), "device_bytes": s.device_bytes,
-            "plan_ms": s.plan_ms}
+            "plan_ms": s.plan_ms, "w_direct": s.w_direct, "p2l_items": s.p2l_items,
+            "p2l_split_boxes": s.p2l_split_boxes, "sort_passes": s.sort_passes, "bead_pass_ms": s.bead_pass_ms}
 
 
 def rpy_plan_export(plan):
@@ -195,6 +202,10 @@ def rpy_plan_timings(plan):
             "passes": t.passes}
 
 
+def rpy_plan_inject_error(plan, phase):
+    _check(lib().rpy_plan_inject_error(plan, int(phase)))
+
+
 def rpy_plan_free(plan):
     if plan:
         lib().rpy_plan_free(plan)
@@ -210,7 +221,7 @@ class Plan:
     """
 
     def __init__(self, positions, a, eta=1.0, eps=1e-6, precision="fp64", leaf_size=0, order=0,
-                 max_depth=0, counts=None, stream=None, m2l="auto", nrhs=0):
+                 max_depth=0, counts=None, stream=None, m2l="auto", nrhs=0, w_direct=0):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a float64 CUDA tensor")
@@ -223,7 +234,7 @@ class Plan:
         self.device = pos.device
         self.stream = stream
         self.options = make_options(prec, leaf_size, order, max_depth, C.c_void_p(stream) if stream else None, m2l,
-                                    nrhs)
+                                    nrhs, w_direct)
         self.n = int(pos.shape[0])
         self.counts = [self.n] if counts is None else [int(c) for c in counts]
         if sum(self.counts) != self.n:
@@ -283,6 +294,15 @@ class Plan:
 
     def timings(self):
         return rpy_plan_timings(self.handle)
+
+    def inject_error(self, phase):
+        """Failure-path testing: the next matvec pass reports a HIP error at
+        `phase` (a name from PHASES or its index; -1 clears)."""
+        if isinstance(phase, str):
+            phase = PHASES.index(phase)
+        if not -1 <= int(phase) < len(PHASES):
+            raise ValueError(f"phase must be -1 or one of {PHASES}")
+        rpy_plan_inject_error(self.handle, phase)
 
     def free(self):
         if getattr(self, "handle", None):

@@ -71,7 +71,7 @@ struct TreeCost {
   bool adaptive = false;
 };
 
-static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, int max_depth, int nrhs,
+static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, int max_depth, int nrhs, int wd_opt,
                       TreeCost* out) {
   const rpy::Tree& t = B.tree;
   const int nbox = t.nbox;
@@ -90,7 +90,7 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
     return -4;
   const bool adaptive = W.len > 0 || X.len > 0;
   const int p = order ? order : order_for_eps(eps, adaptive);
-  const int wmax = rpy::wdirect_max(p);
+  const int wmax = wd_opt == 0 ? rpy::wdirect_default(p) : wd_opt;
   double pairs = 0, weval = 0, xpairs = 0, nleaf = 0;
   int lo = 0, hi = 0x7fffffff;
   for (int b = 0; b < nbox; ++b) {
@@ -103,7 +103,7 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
       for (int k = uo[b]; k < uo[b + 1]; ++k) src += end[ue[k]] - beg[ue[k]];
       for (int k = wo[b]; k < wo[b + 1]; ++k) {
         const int nc = end[we[k]] - beg[we[k]];
-        if (nc > wmax) weval += nb;
+        if (wmax < 0 || nc > wmax) weval += nb;
         else src += nc;
       }
       pairs += padded * src;
@@ -144,6 +144,8 @@ struct rpy_plan_s {
   rpy::Tiles tiles{};
   rpy::EvalPlan ep{};
   int p = 0, leaf_size = 0, max_depth = 14, precision = 0, m2l_mode = 2;
+  int wd = 0;         // W-list boxes of at most wd beads are summed directly (< 0: none)
+  int inject = -1;    // phase at which the next pass reports a HIP error (tests)
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
   // The near field (P2P, overlap and direct W sums) runs on a second stream
@@ -167,11 +169,15 @@ struct rpy_plan_s {
   double* Q = nullptr;   // per-bead charges for S->M / S->L, tree order
   double2* DL = nullptr;  // evaluation sets (local expansions of the leaves)
   double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
+  double2* XP = nullptr;  // S->L partial sums of boxes split over several work items
   int64_t ws_bytes = 0;
   // Krylov workspace (rpy_sqrt_matvec), grown on demand
   double* kbuf = nullptr;
   int64_t kbuf_doubles = 0;
   double plan_ms = 0;
+  // bead passes of the first tree built (bounding cubes, keys, sort, gather)
+  double bead_pass_ms = 0;
+  int sort_passes = 0;
   // per-phase timing
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -214,10 +220,10 @@ static void fold_events(rpy_plan_t* P) {
 }
 
 static void free_ws(rpy_plan_t* P) {
-  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q, P->DL, P->DW};
+  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q, P->DL, P->DW, P->XP};
   for (void* p : ps)
     if (p) (void)hipFree(p);
-  P->M = P->L = P->DL = P->DW = nullptr;
+  P->M = P->L = P->DL = P->DW = P->XP = nullptr;
   P->sF = P->u = P->uf = P->Q = nullptr;
   P->ws_nrc = 0;
   P->ws_bytes = 0;
@@ -235,17 +241,81 @@ static int alloc_ws(rpy_plan_t* P, int nrc) {
   size_t vb = sizeof(double) * 3 * nrc * n, qb = sizeof(double) * 4 * nrc * (n + 64);
   int64_t dwb = 0;
   const size_t dlb = (size_t)rpy::eval_sets_bytes(&P->B, P->ep, P->p, nrc, &dwb);
+  const size_t xpb = sizeof(double2) * std::max<int64_t>(P->B.nxshared, 1) * 4 * nrc * T;
   if (hipMalloc(&P->M, ex) != hipSuccess || hipMalloc(&P->L, ex) != hipSuccess ||
       hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess ||
       hipMalloc(&P->uf, vb) != hipSuccess || hipMalloc(&P->Q, qb) != hipSuccess ||
       hipMemset(P->Q, 0, qb) != hipSuccess || hipMalloc(&P->DL, dlb) != hipSuccess ||
-      hipMalloc(&P->DW, (size_t)dwb) != hipSuccess) {
+      hipMalloc(&P->DW, (size_t)dwb) != hipSuccess || hipMalloc(&P->XP, xpb) != hipSuccess) {
     free_ws(P);
     return -1;
   }
   P->ws_nrc = nrc;
-  P->ws_bytes = 2 * ex + 3 * vb + qb + dlb + dwb;
+  P->ws_bytes = 2 * ex + 3 * vb + qb + dlb + dwb + xpb;
   return 0;
+}
+
+// One matvec pass over right-hand sides r0 .. r0 + c - 1.  Every step runs
+// only if all earlier ones were issued without error; the first error is
+// returned and nothing after it is issued.
+static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const rpy::Exp& e, const double* forces, int nrhs,
+                              int r0, int c, int mixed, double* velocities) {
+  const rpy::Built& B = P->B;
+  const int nlev = B.depth;
+  const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
+  // timing mode 2 runs the near field on the plan stream too, so that each
+  // phase's events measure that phase alone
+  const bool fork = P->near && P->timing != 2;
+  const hipStream_t s0 = P->stream, s1 = fork ? P->near : P->stream;
+  rpy::Launch ln = l;
+  ln.s = s1;
+  // a phase named by rpy_plan_inject_error reports an error instead of running
+  auto step = [&](int phase, int launches, hipStream_t st, auto&& f) -> hipError_t {
+    if (P->inject == phase) {
+      P->inject = -1;
+      return hipErrorLaunchFailure;
+    }
+    return timed(P, phase, launches, st, f);
+  };
+  hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
+  // near field on s1, after the permute
+  if (he == hipSuccess && fork) {
+    he = hipEventRecord(P->ev_fork, s0);
+    if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
+  }
+  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, P->sF, P->u, mixed); });
+  if (he == hipSuccess && haveO)
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, P->sF, P->u); });
+  if (he == hipSuccess && haveW)
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, P->sF, P->u, mixed); });
+  if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
+  // far field on s0
+  if (he == hipSuccess) he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
+  // the deepest level's M->L needs only S->M: on a third stream, beside
+  // the upward pass (it writes L of other boxes than the second part)
+  const bool split = fork && P->far2 && P->m2l_mode != 1;
+  if (he == hipSuccess && split) {
+    rpy::Launch l2 = l;
+    l2.s = P->far2;
+    he = hipEventRecord(P->ev_p2m, s0);
+    if (he == hipSuccess) he = hipStreamWaitEvent(P->far2, P->ev_p2m, 0);
+    if (he == hipSuccess) he = step(RPY_PH_M2L, 1, P->far2, [&] { return rpy::run_m2l_rot(l2, c, e, mixed, 0); });
+    if (he == hipSuccess) he = hipEventRecord(P->ev_m2l0, P->far2);
+  }
+  if (he == hipSuccess) he = step(RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
+  if (he == hipSuccess) he = step(RPY_PH_M2L, 1, s0, [&] {
+    if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
+    return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
+  });
+  if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
+  if (he == hipSuccess && haveX) he = step(RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
+  if (he == hipSuccess) he = step(RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
+  if (he == hipSuccess) he = step(RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
+  // join, then near + far back to caller order
+  if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
+  if (he == hipSuccess)
+    he = step(RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
+  return he;
 }
 
 extern "C" {
@@ -305,6 +375,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.max_depth < 1 || o.max_depth > 21) return fail(RPY_EINVAL, "max_depth must be 1..21");
   if (o.nrhs < 0) return fail(RPY_EINVAL, "nrhs must be >= 0");
   if (o.m2l_mode < 0 || o.m2l_mode > 2) return fail(RPY_EINVAL, "m2l_mode must be 0, 1 or 2");
+  if (o.w_direct < -1) return fail(RPY_EINVAL, "w_direct must be -1, 0 or a bead count");
 
   rpy_plan_t* P = new rpy_plan_t();
   P->a = a;
@@ -318,6 +389,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   // library choice: the rotation operator (measured 5x faster than the dense
   // one at p = 16 in FP64); the mixed form runs it in FP32.
   P->m2l_mode = o.m2l_mode != 0 ? o.m2l_mode : 2;
+  P->wd = o.w_direct;
 
   std::vector<int64_t> sb(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) sb[s + 1] = sb[s] + counts[s];
@@ -326,6 +398,8 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.leaf_size > 0) {
     rpy::BuildArgs ba{n, nsys, sb.data(), positions, P->leaf_size, P->max_depth, a, P->stream};
     rc = rpy::build_tree(ba, &P->B, &err);
+    P->bead_pass_ms = P->B.bead_pass_ms;
+    P->sort_passes = P->B.sort_passes;
   } else {
     // Refinement limit chosen by the cost model over a ladder of limits
     // (64 * 1.5^k) up to the largest system; limits that provably give the
@@ -354,8 +428,13 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
       ba.presorted = P->leaf_size != 0 ? &P->B : nullptr;
       ba.spare = &spare;
       rc = rpy::build_tree(ba, &Bc, &err);
+      if (!ba.presorted) {
+        P->bead_pass_ms = Bc.bead_pass_ms;
+        P->sort_passes = Bc.sort_passes;
+      }
       TreeCost tc;
-      if (rc == 0) rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, o.nrhs, &tc);
+      if (rc == 0)
+        rc = model_tree(Bc, o.order, eps, o.precision == RPY_PREC_MIXED, P->max_depth, o.nrhs, o.w_direct, &tc);
       if (rc != 0) {
         rpy::free_built(&Bc);
         break;
@@ -392,9 +471,10 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   }
   if (rc == 0 && P->p == 0)
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
+  if (P->wd == 0) P->wd = rpy::wdirect_default(P->p);
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
-  if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, &P->ep, P->stream, &err);
+  if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, P->wd, &P->ep, P->stream, &err);
   if (rc == 0) rc = rpy::make_m2l_map(&P->B, P->stream, &err);
   if (rc == 0) rc = rpy::make_p2l_work(&P->B, P->stream, &err);
   if (rc == 0) {
@@ -454,56 +534,12 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
-  rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream};
-  rpy::Exp e{P->M, P->L, P->Q, P->DL, P->DW};
+  rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
+  rpy::Exp e{P->M, P->L, P->Q, P->DL, P->DW, P->XP};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
     int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
-    const rpy::Built& B = P->B;
-    const int nlev = B.depth;
-    const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
-    // timing mode 2 runs the near field on the plan stream too, so that each
-    // phase's events measure that phase alone
-    const bool fork = P->near && P->timing != 2;
-    const hipStream_t s0 = P->stream, s1 = fork ? P->near : P->stream;
-    rpy::Launch ln = l;
-    ln.s = s1;
-    hipError_t he = timed(P, RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
-    // near field on s1, after the permute
-    if (he == hipSuccess && fork) {
-      he = hipEventRecord(P->ev_fork, s0);
-      if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
-    }
-    if (he == hipSuccess) he = timed(P, RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && haveO) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && haveW) he = timed(P, RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, P->sF, P->u, mixed); });
-    if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
-    // far field on s0
-    if (he == hipSuccess) he = timed(P, RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
-    // the deepest level's M->L needs only S->M: on a third stream, beside
-    // the upward pass (it writes L of other boxes than the second part)
-    const bool split = fork && P->far2 && P->m2l_mode != 1;
-    if (split) {
-      rpy::Launch l2 = l;
-      l2.s = P->far2;
-      he = hipEventRecord(P->ev_p2m, s0);
-      if (he == hipSuccess) he = hipStreamWaitEvent(P->far2, P->ev_p2m, 0);
-      if (he == hipSuccess)
-        he = timed(P, RPY_PH_M2L, 1, P->far2, [&] { return rpy::run_m2l_rot(l2, c, e, mixed, 0); });
-      if (he == hipSuccess) he = hipEventRecord(P->ev_m2l0, P->far2);
-    }
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_M2L, 1, s0, [&] {
-      if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
-      return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
-    });
-    if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
-    if (he == hipSuccess && haveX) he = timed(P, RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
-    if (he == hipSuccess) he = timed(P, RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
-    // join, then near + far back to caller order
-    if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
-    if (he == hipSuccess) he = timed(P, RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
+    const hipError_t he = matvec_pass(P, l, e, forces, nrhs, r0, c, mixed, velocities);
     if (P->timing) P->acc.passes += 1;
     if (he != hipSuccess) {
       P->sticky = 1;
@@ -698,6 +734,18 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   for (int L = 0; L < 5; ++L) out->list_len[L] = P->B.lists[L].len;
   out->device_bytes = P->B.bytes + P->tb.bytes + P->ws_bytes + (int64_t)(sizeof(int4) + 6 * sizeof(double)) * P->tiles.n;
   out->plan_ms = P->plan_ms;
+  out->w_direct = P->wd;
+  out->p2l_items = P->B.nxwork;
+  out->p2l_split_boxes = P->B.nxred;
+  out->bead_pass_ms = P->bead_pass_ms;
+  out->sort_passes = P->sort_passes;
+  return RPY_OK;
+}
+
+rpy_status rpy_plan_inject_error(rpy_plan_t* P, int32_t phase) {
+  if (!P) return fail(RPY_EINVAL, "plan is NULL");
+  if (phase < -1 || phase >= RPY_NPHASE) return fail(RPY_EINVAL, "phase must be -1 or a rpy_phase");
+  P->inject = phase;
   return RPY_OK;
 }
 

@@ -120,10 +120,19 @@ struct Built {
   int* m2l_map = nullptr;
   int m2l_part[3] = {0, 0, 0};
   // S->L work items (make_p2l_work): (box, first X entry, end X entry,
-  // shared) and the range of 64-bead chunks taken from each entry
+  // 1 + partial-sum slot or 0) and the range of 64-bead chunks taken from
+  // each entry; a box split over several items has one reduction entry
+  // (box, first slot, slot count) in xred
   int4* xwork = nullptr;
   int2* xchunks = nullptr;
+  int4* xred = nullptr;
   int nxwork = 0;
+  int nxshared = 0;   // partial-sum slots (items whose box is split)
+  int nxred = 0;      // boxes split over several items
+  // bead passes of the build (bounding cubes, keys, sort, gather): GPU time
+  // and radix-sort passes; 0 for a tree that copied them from another
+  double bead_pass_ms = 0.0;
+  int sort_passes = 0;
   int64_t bytes = 0;
 };
 

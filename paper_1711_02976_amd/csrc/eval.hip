@@ -248,12 +248,12 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4*
 }
 
 // W-list boxes whose multipoles the evaluation uses: flag[C] = 1 for every
-// W-list entry C with more than wdirect_max(p) beads.
-__global__ void k_wbig_flag(List W, Tree t, int p, int* flag) {
+// W-list entry C with more than wd beads (every entry when wd < 0).
+__global__ void k_wbig_flag(List W, Tree t, int wd, int* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= W.len) return;
   const int C = W.ent[i];
-  if (t.end[C] - t.begin[C] > wdirect_max(p)) flag[C] = 1;
+  if (wd < 0 || t.end[C] - t.begin[C] > wd) flag[C] = 1;
 }
 
 __global__ void k_wbig_index(const int* flag, const int* off, int nbox, int* widx, int* wbig) {
@@ -288,7 +288,7 @@ hipError_t launch_eval(const Launch& l, const EvalPlan& ep, Exp e, double* u) {
 
 }  // namespace
 
-int make_eval_plan(const Built* B, int p, EvalPlan* out, hipStream_t s, Error* err) {
+int make_eval_plan(const Built* B, int p, int wd, EvalPlan* out, hipStream_t s, Error* err) {
   out->nwbig = 0;
   out->widx = out->wbig = nullptr;
   if (make_tiles(B, 64, &out->tiles, s, err) != 0) return -1;
@@ -300,7 +300,7 @@ int make_eval_plan(const Built* B, int p, EvalPlan* out, hipStream_t s, Error* e
   RPY_HIP(hipMalloc(&tmp, sizeof(int) * scan_tmp_ints(nbox)));
   RPY_HIP(hipMemsetAsync(flag, 0, sizeof(int) * nbox, s));
   const List& W = B->lists[LW];
-  if (W.len > 0) k_wbig_flag<<<(unsigned)((W.len + 255) / 256), 256, 0, s>>>(W, B->tree, p, flag);
+  if (W.len > 0) k_wbig_flag<<<(unsigned)((W.len + 255) / 256), 256, 0, s>>>(W, B->tree, wd, flag);
   RPY_HIP(hipGetLastError());
   RPY_HIP(scan_exclusive(flag, off, nbox, tmp, s));
   int last[2] = {0, 0};

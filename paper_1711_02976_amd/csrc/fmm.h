@@ -20,6 +20,7 @@ struct Exp {
   double* Q;  // per-bead charges [n][4 nrc] for S->M and S->L (written by run_p2m)
   double2* DL;  // evaluation sets of the leaves' local expansions (eval.hip)
   double2* DW;  // evaluation sets of the W-list multipoles that are evaluated
+  double2* XP;  // S->L partial sums of split boxes [Built::nxshared][4 nrc][T]
 };
 
 // Per wave and pass of the S->M / S->L kernels (p2e.hip): bit k of `start`
@@ -82,6 +83,7 @@ struct Launch {
   int p;
   double a, eta;
   hipStream_t s;
+  int wd;  // W-list boxes of at most wd beads are summed directly (wd < 0: none)
 };
 
 // Forces (caller order, [nrhs][n][3]) -> sorted SoA [nrc][3][n] for rhs r0..r0+nrc-1.
@@ -110,13 +112,14 @@ struct Tiles {
 };
 int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err);
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
-// W-list boxes of at most wdirect_max(p) = 2 (p+1)(p+2)/2 beads are summed
-// directly (far formula) by run_wdirect; the target evaluation uses the
-// multipoles of the others only.  Per target and right-hand side the
-// multipole route costs about 12 sets x (p+3)(p+4)/2 coefficients, the
-// direct route a few tens of operations per source bead.
-__host__ __device__ constexpr int wdirect_max(int p) { return (p + 1) * (p + 2); }
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);  // FP64
+// W-list boxes of at most Launch::wd beads are summed directly (far
+// formula) by run_wdirect; the target evaluation uses the multipoles of the
+// others only.  Per target and right-hand side the multipole route costs
+// about 12 sets x (p+3)(p+4)/2 coefficients, the direct route a few tens of
+// operations per source bead, so the library's default threshold is
+// wdirect_default(p) = 2 (p+1)(p+2)/2 beads.
+__host__ __device__ constexpr int wdirect_default(int p) { return (p + 1) * (p + 2); }
 hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
 
 // Target evaluation (eval.hip).  tiles: up to 64 beads of one leaf each
@@ -129,7 +132,7 @@ struct EvalPlan {
   int* wbig = nullptr;
   int nwbig = 0;
 };
-int make_eval_plan(const Built* B, int p, EvalPlan* out, hipStream_t s, Error* err);
+int make_eval_plan(const Built* B, int p, int wd, EvalPlan* out, hipStream_t s, Error* err);
 void free_eval_plan(EvalPlan* ep);
 // Bytes of the evaluation-set arrays for nrc right-hand sides: returns the
 // leaves' (Exp::DL), stores the W multipoles' (Exp::DW) in *dw_bytes.

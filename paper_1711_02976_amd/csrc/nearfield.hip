@@ -87,21 +87,17 @@ int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err) 
 }
 
 // ------------------------------------------------------------ pair math ---
-// Coefficients of the RPY block M(d) = A I + B d d^T for one pair.
-struct RpyConst {
-  double c0;      // 1/(6 pi eta a): self mobility
-  double c1;      // 1/(8 pi eta)
-  double c1a3;    // c1 * 2a^2/3
-  double c1a2;    // c1 * 2a^2
-  double four_a2; // (2a)^2
-  double k9;      // 9/(32a)
-  double c0k3;    // c0 * 3/(32a)
-};
 
 // Pair coefficients of the P2P sum with the far prefactor c1 = 1/(8 pi eta)
 // taken out of the sum (applied once per target):
 //   far      A' = 1/r + (2a^2/3)/r^3,        B' = (1 - 2a^2/r^2)/r^3,
-//   overlap  A' = (c0/c1)(1 - 9r/(32a)),     B' = (c0/c1)(3/(32a))/r.
+//   overlap  A' = (c0/c1)(1 - 9r/(32a)),     B' = (c0/c1)(3/(32a))/r,
+// c0/c1 = 4/(3a).  The pair kernels work in units scaled by a power of two S
+// chosen so that 2aS lies in [1, 2): positions are scaled by S (exactly),
+// the constants are those of the radius aS, and the sums come out divided by
+// S, which the prefactor c1 S restores.  Apart from overflow and underflow
+// this is the same arithmetic rounded the same way, and it keeps every pair
+// quantity of order one whatever the length unit.
 template <class R>
 struct PairK {
   R a3;       // 2a^2/3
@@ -113,16 +109,21 @@ struct PairK {
   R r2min;    // floor added to r^2 before the reciprocal square root (coincident beads)
 };
 
+// Power of two S with 2aS in [1, 2).
+static double pair_scale(double a) { return std::ldexp(1.0, -std::ilogb(2.0 * a)); }
+
+// Constants for the scaled radius as = a S.
 template <class R>
-static PairK<R> pair_const(const RpyConst& k, double a) {
-  const double oc = k.c0 / k.c1;
-  return PairK<R>{(R)(2.0 * a * a / 3.0), (R)(2.0 * a * a), (R)k.four_a2, (R)oc, (R)(oc * k.k9),
-                  (R)(oc * 3.0 / (32.0 * a)), (R)1e-30};
+static PairK<R> pair_const(double as) {
+  const double oc = 4.0 / (3.0 * as);
+  return PairK<R>{(R)(2.0 * as * as / 3.0), (R)(2.0 * as * as), (R)(4.0 * as * as), (R)oc,
+                  (R)(oc * 9.0 / (32.0 * as)), (R)(oc * 3.0 / (32.0 * as)), (R)1e-30};
 }
 
 __device__ inline float rinv_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
 // single-precision estimate refined by one Newton step (relative error
-// below 2^-44); r2 >= 1e-30 here, so the estimate is finite
+// below 2^-44); r2 >= 1e-30 here (a normal FP32 number), so the estimate is
+// finite
 __device__ inline double rinv_of(double r2) {
   double y = (double)__builtin_amdgcn_rsqf((float)r2);
   return y * fma(-0.5 * r2, y * y, 1.5);
@@ -132,18 +133,20 @@ __device__ inline double rinv_of(double r2) {
 // The overlap formula is evaluated only when some lane of the wave has a
 // source closer than 2a (a wave-uniform branch), since such pairs are rare
 // apart from each target's own bead.  For r = 0 (the bead itself, or a
-// coincident bead) r^2 carries a floor of 1e-30 (added in the first FMA; it
-// changes no r^2 above 1e-23) before the reciprocal square root: the far
-// values are then finite and discarded, and the overlap values give the
-// r -> 0 limit A' = c0/c1, B' d = 0.
+// coincident bead) r^2 carries a floor of 1e-30 in the scaled units (added
+// in the first FMA) before the reciprocal square root: the far values are
+// then finite and discarded, and the overlap values give the r -> 0 limit
+// A' = c0/c1, B' d = 0.  Since 2a >= 1 in these units, the floor changes
+// r^2 by a relative amount below 1e-30 at every r >= 2a, where the far
+// formula applies.
 // Positions enter the pair arithmetic relative to the target leaf's centre
-// (differences taken in FP64 and rounded once); in the mixed form the pair
-// arithmetic and per-source-leaf sums run in FP32.
+// (differences taken in FP64, scaled by S and rounded once); in the mixed
+// form the pair arithmetic and per-source-leaf sums run in FP32.
 template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
                                                PairK<typename std::conditional<MIXED, float, double>::type> k,
-                                               double c1, double* u) {
+                                               double S, double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
   using V4 = typename std::conditional<MIXED, float4, double4>::type;
   __shared__ alignas(32) R xs[P2P_T];
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];
-  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
+  const R xi = (R)((sx[i] - ox) * S), yi = (R)((sy[i] - oy) * S), zi = (R)((sz[i] - oz) * S);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   const int e0 = __builtin_amdgcn_readfirstlane(U.off[b]), e1 = __builtin_amdgcn_readfirstlane(U.off[b + 1]);
@@ -171,7 +174,8 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
+        xs[threadIdx.x] = (R)((sx[j] - ox) * S); ys[threadIdx.x] = (R)((sy[j] - oy) * S);
+        zs[threadIdx.x] = (R)((sz[j] - oz) * S);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
         xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
@@ -244,7 +248,7 @@ template <int NRC, bool MIXED>
 __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, List W, int wmax, const double* sx,
                                                    const double* sy, const double* sz, const double* sF, int64_t n,
                                                    PairK<typename std::conditional<MIXED, float, double>::type> k,
-                                                   double c1, double* u) {
+                                                   double S, double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
   __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
   __shared__ R fs[NRC * 3][P2P_T];
@@ -256,7 +260,7 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
   const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
-  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
+  const R xi = (R)((sx[i] - ox) * S), yi = (R)((sy[i] - oy) * S), zi = (R)((sz[i] - oz) * S);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   bool any = false;
@@ -271,7 +275,8 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
+        xs[threadIdx.x] = (R)((sx[j] - ox) * S); ys[threadIdx.x] = (R)((sy[j] - oy) * S);
+        zs[threadIdx.x] = (R)((sz[j] - oz) * S);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
         xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
@@ -323,7 +328,7 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
                                                    double four_a2, const double* sx,
                                                    const double* sy, const double* sz, const double* sF, int64_t n,
                                                    PairK<typename std::conditional<MIXED, float, double>::type> k,
-                                                   double c1, double* u) {
+                                                   double S, double c1, double* u) {
   using R = typename std::conditional<MIXED, float, double>::type;
   constexpr int NG = P2P_T / OV_G;
   __shared__ R xs[P2P_T], ys[P2P_T], zs[P2P_T];
@@ -337,10 +342,11 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
   const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
   const int i = tl.y + (valid ? threadIdx.x : 0);
   const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];  // positions relative to the target leaf
-  const R xi = (R)(sx[i] - ox), yi = (R)(sy[i] - oy), zi = (R)(sz[i] - oz);
-  // a group is skipped only when its box is clearly 2a away (rounding margin);
-  // idle lanes repeat the tile's first bead, so they add no extra groups
-  const R skip2 = (R)(four_a2 * (1.0 + 1e-4));
+  const R xi = (R)((sx[i] - ox) * S), yi = (R)((sy[i] - oy) * S), zi = (R)((sz[i] - oz) * S);
+  // a group is skipped only when its box is clearly 2a away (rounding margin,
+  // scaled units); idle lanes repeat the tile's first bead, so they add no
+  // extra groups
+  const R skip2 = k.four_a2 * (R)(1.0 + 1e-4);
   double acc[NRC][3];
   for (int r = 0; r < NRC; ++r) acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
   double blo[3], bhi[3];
@@ -367,7 +373,8 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       __syncthreads();
       if ((int)threadIdx.x < ns) {
         int j = jc + threadIdx.x;
-        xs[threadIdx.x] = (R)(sx[j] - ox); ys[threadIdx.x] = (R)(sy[j] - oy); zs[threadIdx.x] = (R)(sz[j] - oz);
+        xs[threadIdx.x] = (R)((sx[j] - ox) * S); ys[threadIdx.x] = (R)((sy[j] - oy) * S);
+        zs[threadIdx.x] = (R)((sz[j] - oz) * S);
         for (int q = 0; q < NRC * 3; ++q) fs[q][threadIdx.x] = (R)sF[(int64_t)q * n + j];
       } else if ((int)threadIdx.x < ns4) {
         xs[threadIdx.x] = (R)1e30; ys[threadIdx.x] = (R)1e30; zs[threadIdx.x] = (R)1e30;
@@ -430,32 +437,36 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
       for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] += c1 * acc[r][c];
 }
 
-static RpyConst rpy_const(double a, double eta) {
-  RpyConst k;
-  k.c0 = 1.0 / (6.0 * PI * eta * a);
-  k.c1 = 1.0 / (8.0 * PI * eta);
-  k.c1a3 = k.c1 * 2.0 * a * a / 3.0;
-  k.c1a2 = k.c1 * 2.0 * a * a;
-  k.four_a2 = 4.0 * a * a;
-  k.k9 = 9.0 / (32.0 * a);
-  k.c0k3 = k.c0 * 3.0 / (32.0 * a);
-  return k;
+// Launch arguments shared by the pair kernels: the scale S (2aS in [1, 2)),
+// the constants of the scaled radius in both precisions and the prefactor
+// c1 S = S / (8 pi eta) that undoes the scaling of the sums.
+struct PairLaunch {
+  double S, c1S;
+  PairK<float> kf;
+  PairK<double> kd;
+};
+
+static PairLaunch pair_launch(double a, double eta) {
+  PairLaunch q;
+  q.S = pair_scale(a);
+  q.c1S = q.S / (8.0 * PI * eta);
+  q.kf = pair_const<float>(a * q.S);
+  q.kd = pair_const<double>(a * q.S);
+  return q;
 }
 
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   if (tiles.n == 0) return hipSuccess;
   const Built* B = l.B;
-  const RpyConst k = rpy_const(l.a, l.eta);
-  const PairK<float> kf = pair_const<float>(k, l.a);
-  const PairK<double> kd = pair_const<double>(k, l.a);
+  const PairLaunch q = pair_launch(l.a, l.eta);
 #define P2P_CASE(NR)                                                                                               \
   case NR:                                                                                                         \
     if (mixed)                                                                                                     \
-      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, kf, \
-                                                  k.c1, u);                                                        \
+      k_p2p<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n,     \
+                                                  q.kf, q.S, q.c1S, u);                                            \
     else                                                                                                           \
-      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n, kd, \
-                                                   k.c1, u);                                                       \
+      k_p2p<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n,    \
+                                                   q.kd, q.S, q.c1S, u);                                           \
     break;
   switch (nrc) {
     P2P_CASE(1)
@@ -467,20 +478,19 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
   return hipGetLastError();
 }
 
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
+// The overlap correction is a near/far correction sum: it runs in FP64 in
+// both precision forms (the mixed form keeps such sums in FP64).  Its
+// difference M_overlap - M_far cancels as r approaches 2a, where the two
+// branches meet.
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u) {
   const Built* B = l.B;
   if (tiles.n == 0 || B->lists[LO].len == 0) return hipSuccess;
-  const RpyConst k = rpy_const(l.a, l.eta);
-  const PairK<float> kf = pair_const<float>(k, l.a);
-  const PairK<double> kd = pair_const<double>(k, l.a);
+  const PairLaunch q = pair_launch(l.a, l.eta);
+  const double four_a2 = 4.0 * l.a * l.a;
 #define OV_CASE(NR)                                                                                                 \
   case NR:                                                                                                          \
-    if (mixed)                                                                                                      \
-      k_overlap<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], k.four_a2, B->sx,  \
-                                                      B->sy, B->sz, sF, B->n, kf, k.c1, u);                         \
-    else                                                                                                            \
-      k_overlap<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], k.four_a2, B->sx, \
-                                                       B->sy, B->sz, sF, B->n, kd, k.c1, u);                        \
+    k_overlap<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], four_a2, B->sx,     \
+                                                     B->sy, B->sz, sF, B->n, q.kd, q.S, q.c1S, u);                  \
     break;
   switch (nrc) {
     OV_CASE(1)
@@ -492,21 +502,21 @@ hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const doubl
   return hipGetLastError();
 }
 
+// The direct W sums are far-formula pair sums like the P2P: FP32 in the
+// mixed form.
 hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   const Built* B = l.B;
-  if (tiles.n == 0 || B->lists[LW].len == 0) return hipSuccess;
-  const RpyConst k = rpy_const(l.a, l.eta);
-  const PairK<float> kf = pair_const<float>(k, l.a);
-  const PairK<double> kd = pair_const<double>(k, l.a);
-  const int wmax = wdirect_max(l.p);
+  if (tiles.n == 0 || B->lists[LW].len == 0 || l.wd < 0) return hipSuccess;
+  const PairLaunch q = pair_launch(l.a, l.eta);
+  const int wmax = l.wd;
 #define WD_CASE(NR)                                                                                                 \
   case NR:                                                                                                          \
     if (mixed)                                                                                                      \
       k_wdirect<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LW], wmax, B->sx, B->sy, B->sz, sF, \
-                                                      B->n, kf, k.c1, u);                                           \
+                                                      B->n, q.kf, q.S, q.c1S, u);                                   \
     else                                                                                                            \
       k_wdirect<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, B->tree, B->lists[LW], wmax, B->sx, B->sy, B->sz,    \
-                                                       sF, B->n, kd, k.c1, u);                                      \
+                                                       sF, B->n, q.kd, q.S, q.c1S, u);                              \
     break;
   switch (nrc) {
     WD_CASE(1)

@@ -80,23 +80,25 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
                                                      const P2EPass* __restrict__ desc,
                                                      const int* __restrict__ slot_coef,
                                                      const double* __restrict__ slot_scale,
-                                                     const double* __restrict__ dk, double2* E) {
+                                                     const double* __restrict__ dk, double2* E,
+                                                     double2* __restrict__ part) {
   constexpr int NRC = ND / 4;
   constexpr int S = P2E_WAVES * K, G = S / 64, NB = P2E_WAVES / G, BPW = P2E_CHUNK / NB;
   constexpr int LD = S + 1;  // odd row stride: conflict-free [bead][slot] writes
   const int T = ncoef(p);
   // S->M: one leaf per block.  S->L: one work item per block, a run of the
   // box's X entries and a range of 64-bead chunks of each; a box whose X
-  // work was split over several items adds its share atomically
+  // work was split over several items writes each item's share to its own
+  // slot of `part`, and k_p2l_reduce adds the slots in a fixed order
   int b, e0 = 0, e1 = 1, clo = 0, chi = 0x7fffffff;
-  bool shared = false;
+  int pslot = -1;
   if (LOCAL) {
     const int4 wk = xwork[blockIdx.x];
     const int2 ch = xchunks[blockIdx.x];
     b = wk.x;
     e0 = wk.y;
     e1 = wk.z;
-    shared = wk.w != 0;
+    pslot = wk.w - 1;
     clo = ch.x;
     chi = ch.y;
   } else {
@@ -263,12 +265,11 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
           v.x += w.x;
           v.y += w.y;
         }
-        double2* out = E + ((int64_t)b * ND + d0 + d) * T + c;
-        if (LOCAL && shared) {
-          atomicAdd(&out->x, v.x);
-          atomicAdd(&out->y, v.y);
+        if (LOCAL && pslot >= 0) {
+          part[((int64_t)pslot * ND + d0 + d) * T + c] = v;
           continue;
         }
+        double2* out = E + ((int64_t)b * ND + d0 + d) * T + c;
         if (LOCAL) {
           const double2 o0 = *out;
           v.x += o0.x;
@@ -284,8 +285,27 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
   }
 }
 
+// Adds the split S->L shares of one box (xred: box, first slot, slot count)
+// to its local expansion, slot by slot in item order.
+template <int ND>
+__global__ void __launch_bounds__(256) k_p2l_reduce(int p, const int4* __restrict__ xred, const double2* __restrict__ part,
+                                                    double2* E) {
+  const int T = ncoef(p);
+  const int4 rd = xred[blockIdx.x];
+  for (int i = threadIdx.x; i < ND * T; i += blockDim.x) {
+    double2 v = E[(int64_t)rd.x * ND * T + i];
+    for (int k = 0; k < rd.z; ++k) {
+      const double2 w = part[(int64_t)(rd.y + k) * ND * T + i];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    E[(int64_t)rd.x * ND * T + i] = v;
+  }
+}
+
 template <int ND, bool LOCAL, int K, int P>
-hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* ids, const double* Q, double2* E) {
+hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* ids, const double* Q, double2* E,
+                      double2* part) {
   const Built* B = l.B;
   if (grid == 0) return hipSuccess;
   const size_t shm = sizeof(double2) * P2E_CHUNK * (P2E_WAVES * K + 1);
@@ -294,7 +314,10 @@ hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* 
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (he != hipSuccess) return he;
   kern<<<grid, P2E_THREADS, shm, l.s>>>(l.p, ids, B->xwork, B->xchunks, B->tree, B->lists[LX], B->sx, B->sy, B->sz, Q,
-                                        sc.desc, sc.slot, sc.scale, l.tb->p2e_dk, E);
+                                        sc.desc, sc.slot, sc.scale, l.tb->p2e_dk, E, part);
+  he = hipGetLastError();
+  if (he != hipSuccess || !LOCAL || B->nxred == 0) return he;
+  k_p2l_reduce<ND><<<B->nxred, 256, 0, l.s>>>(l.p, B->xred, part, E);
   return hipGetLastError();
 }
 
@@ -302,42 +325,43 @@ hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* 
 // CU) unless the accumulators of 16 densities over more than two passes
 // would not fit in registers; then 16 steps (132 KB, one block per CU).
 template <int ND, bool LOCAL>
-hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double* Q, double2* E) {
+hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double* Q, double2* E, double2* part) {
   const P2ESched& s8 = l.tb->p2e[0];
   const P2ESched& s16 = l.tb->p2e[1];
   if constexpr (ND <= 8) {
     switch (s8.P) {
-      case 1: return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E);
-      case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
-      case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E);
-      case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E);
+      case 1: return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E, part);
+      case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E, part);
+      case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E, part);
+      case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E, part);
       default: break;
     }
     // orders above 21 run one right-hand side per pass: up to 7 passes
     if constexpr (ND == 4) {
       switch (s8.P) {
-        case 5: return launch_p2e<ND, LOCAL, 8, 5>(l, s8, grid, ids, Q, E);
-        case 6: return launch_p2e<ND, LOCAL, 8, 6>(l, s8, grid, ids, Q, E);
-        case 7: return launch_p2e<ND, LOCAL, 8, 7>(l, s8, grid, ids, Q, E);
+        case 5: return launch_p2e<ND, LOCAL, 8, 5>(l, s8, grid, ids, Q, E, part);
+        case 6: return launch_p2e<ND, LOCAL, 8, 6>(l, s8, grid, ids, Q, E, part);
+        case 7: return launch_p2e<ND, LOCAL, 8, 7>(l, s8, grid, ids, Q, E, part);
         default: break;
       }
     }
     return hipErrorInvalidValue;
   } else {
-    if (s8.P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E);
-    if (s8.P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E);
-    if (s16.P == 1) return launch_p2e<ND, LOCAL, 16, 1>(l, s16, grid, ids, Q, E);
-    if (s16.P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, s16, grid, ids, Q, E);
+    if (s8.P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E, part);
+    if (s8.P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E, part);
+    if (s16.P == 1) return launch_p2e<ND, LOCAL, 16, 1>(l, s16, grid, ids, Q, E, part);
+    if (s16.P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, s16, grid, ids, Q, E, part);
     return hipErrorInvalidValue;
   }
 }
 
 template <bool LOCAL>
-hipError_t launch_p2e_nd(const Launch& l, int nrc, int grid, const int* ids, const double* Q, double2* E) {
+hipError_t launch_p2e_nd(const Launch& l, int nrc, int grid, const int* ids, const double* Q, double2* E,
+                         double2* part) {
   switch (nrc) {
-    case 1: return launch_p2e_kp<4, LOCAL>(l, grid, ids, Q, E);
-    case 2: return launch_p2e_kp<8, LOCAL>(l, grid, ids, Q, E);
-    case 4: return launch_p2e_kp<16, LOCAL>(l, grid, ids, Q, E);
+    case 1: return launch_p2e_kp<4, LOCAL>(l, grid, ids, Q, E, part);
+    case 2: return launch_p2e_kp<8, LOCAL>(l, grid, ids, Q, E, part);
+    case 4: return launch_p2e_kp<16, LOCAL>(l, grid, ids, Q, E, part);
     default: return hipErrorInvalidValue;
   }
 }
@@ -417,9 +441,11 @@ static int build_sched(int p, int K, int maxp, P2ESched* out, Error* err, int64_
 int make_p2l_work(Built* B, hipStream_t s, Error* err) {
   if (B->xwork) (void)hipFree(B->xwork);
   if (B->xchunks) (void)hipFree(B->xchunks);
+  if (B->xred) (void)hipFree(B->xred);
   B->xwork = nullptr;
   B->xchunks = nullptr;
-  B->nxwork = 0;
+  B->xred = nullptr;
+  B->nxwork = B->nxshared = B->nxred = 0;
   const List& X = B->lists[LX];
   const int nbox = B->tree.nbox;
   if (X.len == 0 || nbox == 0) return 0;
@@ -433,8 +459,9 @@ int make_p2l_work(Built* B, hipStream_t s, Error* err) {
   int64_t total = 0;
   for (int64_t e = 0; e < X.len; ++e) total += chunks((int)e);
   const int cap = (int)std::max<int64_t>(16, total / 2048);
-  std::vector<int4> work;
+  std::vector<int4> work, red;
   std::vector<int2> rng;
+  int nslot = 0;
   for (int b = 0; b < nbox; ++b) {
     const size_t first = work.size();
     int e = off[b];
@@ -454,15 +481,25 @@ int make_p2l_work(Built* B, hipStream_t s, Error* err) {
       rng.push_back(make_int2(0, 0x7fffffff));
       e = e1;
     }
-    if (work.size() - first > 1)
-      for (size_t i = first; i < work.size(); ++i) work[i].w = 1;
+    if (work.size() - first > 1) {
+      // shares of one box: slots nslot.. in item order, reduced afterwards
+      red.push_back(make_int4(b, nslot, (int)(work.size() - first), 0));
+      for (size_t i = first; i < work.size(); ++i) work[i].w = 1 + nslot++;
+    }
   }
   B->nxwork = (int)work.size();
+  B->nxshared = nslot;
+  B->nxred = (int)red.size();
   RPY_HIP(hipMalloc(&B->xwork, sizeof(int4) * work.size()));
   RPY_HIP(hipMalloc(&B->xchunks, sizeof(int2) * rng.size()));
   RPY_HIP(hipMemcpy(B->xwork, work.data(), sizeof(int4) * work.size(), hipMemcpyHostToDevice));
   RPY_HIP(hipMemcpy(B->xchunks, rng.data(), sizeof(int2) * rng.size(), hipMemcpyHostToDevice));
   B->bytes += (int64_t)(sizeof(int4) + sizeof(int2)) * work.size();
+  if (!red.empty()) {
+    RPY_HIP(hipMalloc(&B->xred, sizeof(int4) * red.size()));
+    RPY_HIP(hipMemcpy(B->xred, red.data(), sizeof(int4) * red.size(), hipMemcpyHostToDevice));
+    B->bytes += (int64_t)sizeof(int4) * red.size();
+  }
   return 0;
 }
 
@@ -501,7 +538,7 @@ hipError_t run_p2m(const Launch& l, int nrc, const double* sF, Exp e) {
   }
   hipError_t he = hipGetLastError();
   if (he != hipSuccess) return he;
-  return launch_p2e_nd<false>(l, nrc, B->nleaf, B->leaf_ids, e.Q, e.M);
+  return launch_p2e_nd<false>(l, nrc, B->nleaf, B->leaf_ids, e.Q, e.M, nullptr);
 }
 
 hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
@@ -509,7 +546,8 @@ hipError_t run_p2l(const Launch& l, int nrc, const double* sF, Exp e) {
   const Built* B = l.B;
   if (B->lists[LX].len == 0) return hipSuccess;
   if (!B->xwork && B->nxwork > 0) return hipErrorInvalidValue;
-  return launch_p2e_nd<true>(l, nrc, B->nxwork, nullptr, e.Q, e.L);
+  if (B->nxred > 0 && !e.XP) return hipErrorInvalidValue;
+  return launch_p2e_nd<true>(l, nrc, B->nxwork, nullptr, e.Q, e.L, e.XP);
 }
 
 }  // namespace rpy

@@ -625,7 +625,7 @@ void free_built(Built* b) {
   void* ps[] = {b->keys, b->perm, b->sx, b->sy, b->sz, b->d_lo, b->d_side, b->d_sys_begin,
                 b->tree.level, b->tree.sys, b->tree.ax, b->tree.ay, b->tree.az, b->tree.begin,
                 b->tree.end, b->tree.parent, b->tree.child, b->tree.nchild, b->tree.cx, b->tree.cy,
-                b->tree.cz, b->tree.h, b->colleague, b->leaf_ids, b->m2l_map, b->xwork, b->xchunks};
+                b->tree.cz, b->tree.h, b->colleague, b->leaf_ids, b->m2l_map, b->xwork, b->xchunks, b->xred};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   for (auto& L : b->lists) {
@@ -690,9 +690,23 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
     if (dalloc(&bb, nsys * 6, B, err)) return -3;
     if (dalloc(&bad, 1, B, err)) return -3;
     RPY_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
+    // the bead passes (bounding cubes, keys, sort, gather) are timed with
+    // events for the plan statistics
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    auto rec = [&](int i) {
+      if (ev[i]) (void)hipEventRecord(ev[i], s);
+    };
+    auto drop = [&]() {
+      for (hipEvent_t& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    };
+    rec(0);
     k_bbox_partial<<<dim3(nblk, nsys), BB_T, 0, s>>>(A.pos, B->d_sys_begin, nblk, part);
     k_bbox_final<<<nsys, 64, 0, s>>>(part, nblk, B->d_sys_begin, bb, bad);
     k_check_finite<<<1024, 256, 0, s>>>(A.pos, 3 * n, bad);
+    rec(1);
     RPY_HIP(hipGetLastError());
     std::vector<double> hbb(nsys * 6);
     int hbad = 0;
@@ -702,6 +716,7 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
     (void)hipFree(part); (void)hipFree(bb); (void)hipFree(bad);
     B->bytes -= sizeof(double) * ((int64_t)nsys * nblk * 6 + nsys * 6) + sizeof(int);
     if (hbad) {
+      drop();
       err->code = -2;
       err->msg = "a position is NaN or infinite";
       return -2;
@@ -724,19 +739,33 @@ int build_tree(const BuildArgs& A, Built* B, Error* err) {
     // Morton keys and the stable sort by (key, caller index) [, system].
     uint64_t *k0 = nullptr, *k1 = nullptr;
     int *v0 = nullptr, *v1 = nullptr;
-    if (dalloc(&k0, n, B, err) || dalloc(&k1, n, B, err) || dalloc(&v0, n, B, err) || dalloc(&v1, n, B, err))
+    if (dalloc(&k0, n, B, err) || dalloc(&k1, n, B, err) || dalloc(&v0, n, B, err) || dalloc(&v1, n, B, err)) {
+      drop();
       return -3;
+    }
+    rec(2);
     if (n > 0) k_morton<<<nblocks(n, 256), 256, 0, s>>>(A.pos, n, B->d_sys_begin, nsys, B->d_lo, B->d_side, k0, v0);
     RPY_HIP(hipGetLastError());
     int npass_sys = nsys > 1 ? (nsys > 256 ? 2 : 1) : 0;
+    B->sort_passes = 8 + npass_sys;
     RPY_HIP(radix_sort(&k0, &v0, k1, v1, n, 8, npass_sys, B->d_sys_begin, nsys, s));
     (void)hipFree(k1); (void)hipFree(v1);
     B->bytes -= (sizeof(uint64_t) + sizeof(int)) * std::max<int64_t>(n, 1);
     B->keys = k0;
     B->perm = v0;
-    if (dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) return -3;
+    if (dalloc(&B->sx, n, B, err) || dalloc(&B->sy, n, B, err) || dalloc(&B->sz, n, B, err)) {
+      drop();
+      return -3;
+    }
     if (n > 0) k_gather_pos<<<nblocks(n, 256), 256, 0, s>>>(A.pos, v0, n, B->sx, B->sy, B->sz);
+    rec(3);
     RPY_HIP(hipGetLastError());
+    if (ev[0] && ev[1] && ev[2] && ev[3] && hipEventSynchronize(ev[3]) == hipSuccess) {
+      float t0 = 0.f, t1 = 0.f;
+      if (hipEventElapsedTime(&t0, ev[0], ev[1]) == hipSuccess && hipEventElapsedTime(&t1, ev[2], ev[3]) == hipSuccess)
+        B->bead_pass_ms = (double)t0 + (double)t1;
+    }
+    drop();
   }
 
   // Octree, level by level.

@@ -68,5 +68,9 @@ def test_host_validation_without_gpu():
     o.struct_size = R.rpy_options.stream.offset
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
     assert b"struct_size" in L.rpy_last_error()
+    o = R.make_options(w_direct=-2)
+    assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    assert b"w_direct" in L.rpy_last_error()
+    assert L.rpy_plan_inject_error(None, 0) == R.RPY_EINVAL
     L.rpy_plan_free(None)  # NULL-safe
     assert L.rpy_status_string(R.RPY_ENONFINITE) == b"non-finite position"

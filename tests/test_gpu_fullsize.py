@@ -6,10 +6,17 @@ size and order, both precision forms).
   * cube-1M:    1,000,000 uniform beads, one rhs, at both accuracy settings
                 (eps 1e-3 and 1e-6), on 10,000 sampled targets;
   * blobs-4M:   4,000,000 clustered beads (2,000 Gaussian blobs), 4 rhs,
-                adaptive tree with W/X lists and overlapping pairs outside U;
-  * batched-64: 64 independent systems of 1e3 .. 2e5 beads, 16 rhs, one plan;
-  * cube-15M:   15,000,000 uniform beads, 20 rhs;
-  * sphere-8M:  8,000,000 beads uniform on a sphere surface (adaptive tree).
+                adaptive tree with W/X lists and overlapping pairs outside U,
+                on 2,000 sampled targets;
+  * batched-64: 64 independent systems of 1e3 .. 2e5 beads, 16 rhs, one plan,
+                min(n_s, 500) sampled targets per system;
+  * cube-15M:   15,000,000 uniform beads, 20 rhs, on 2,000 sampled targets;
+  * sphere-8M:  8,000,000 beads uniform on a sphere surface (adaptive tree),
+                on 2,000 sampled targets.
+Every case checks the rel-L2 error over all sampled targets and right-hand
+sides against eps, and each target's error against 20 eps times the largest
+reference velocity.  The direct-sum references are computed once per
+workload and shared by the two precision forms.
 """
 import numpy as np
 import pytest
@@ -51,32 +58,39 @@ def _direct_by_system(orc, w):
     return out
 
 
+_refs = {}
+
+
+def _check(orc, key, w, u, st, direct=None):
+    if key not in _refs:
+        _refs[key] = (direct or (lambda: orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)))()
+    ref = _refs[key]
+    err = orc.rel_l2(u, ref)
+    d = np.linalg.norm(u - ref, axis=-1).max() / np.linalg.norm(ref, axis=-1).max()
+    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} lists={st['list_len']} "
+        f"rel-L2 = {err:.3e}, max target error / max |ref| = {d:.3e} ({len(w.sample)} targets)")
+    assert err <= w.eps
+    assert d <= 20 * w.eps
+    return err
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_blobs_4M(orc, precision):
-    w = W.config(3, nsample=400)
+    w = W.config(3, nsample=2000)
     log(f"{w.name} n={w.n} nrhs={w.nrhs} {precision}")
     u, st = _run(w, precision)
-    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
-    err = orc.rel_l2(u, ref)
-    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} "
-        f"W={st['list_len']['W']} X={st['list_len']['X']} O={st['list_len']['O']} rel-L2 = {err:.3e}")
     assert st["list_len"]["O"] > 0, "the clustered workload is expected to need the overlap correction"
-    assert err <= w.eps
+    _check(orc, "blobs", w, u, st)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_64(orc, precision):
-    w = W.config(4, nsample=60)
+    w = W.config(4, nsample=500)
     log(f"{w.name} systems={len(w.counts)} n={w.n} nrhs={w.nrhs} {precision}")
     u, st = _run(w, precision, counts=w.counts)
-    ref = _direct_by_system(orc, w)
-    err = orc.rel_l2(u, ref)
-    log(f"  p={st['order']} s={st['leaf_size']} nbox={st['nbox']} rel-L2 = {err:.3e}")
     assert st["nsys"] == 64
-    assert err <= w.eps
-
-
-_cube_ref = {}
+    assert len(w.sample) == sum(min(c, 500) for c in w.counts)
+    _check(orc, "batched", w, u, st, direct=lambda: _direct_by_system(orc, w))
 
 
 @pytest.mark.parametrize("precision,eps", [("fp64", 1e-3), ("mixed", 1e-3), ("fp64", 1e-6), ("mixed", 1e-6)])
@@ -85,30 +99,21 @@ def test_cube_1M(orc, precision, eps):
     w = dataclasses.replace(W.config(2), eps=eps)  # 10,000 sampled targets
     log(f"{w.name} n={w.n} eps={eps} {precision}")
     u, st = _run(w, precision)
-    if "ref" not in _cube_ref:
-        _cube_ref["ref"] = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
-    err = orc.rel_l2(u, _cube_ref["ref"])
-    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} rel-L2 = {err:.3e}")
     assert len(w.sample) == 10_000
-    assert err <= eps
+    _check(orc, "cube1M", w, u, st)
 
 
-def test_cube_15M_mixed(orc):
-    w = W.config(5, nsample=150)
-    log(f"{w.name} n={w.n} nrhs={w.nrhs} mixed")
-    u, st = _run(w, "mixed")
-    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
-    err = orc.rel_l2(u, ref)
-    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} rel-L2 = {err:.3e}")
-    assert err <= w.eps
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cube_15M(orc, precision):
+    w = W.config(5, nsample=2000)
+    log(f"{w.name} n={w.n} nrhs={w.nrhs} {precision}")
+    u, st = _run(w, precision)
+    _check(orc, "cube15M", w, u, st)
 
 
-def test_sphere_8M_mixed(orc):
-    w = W.config(6, nsample=200)
-    log(f"{w.name} n={w.n} nrhs={w.nrhs} mixed")
-    u, st = _run(w, "mixed")
-    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
-    err = orc.rel_l2(u, ref)
-    log(f"  p={st['order']} s={st['leaf_size']} depth={st['depth']} nbox={st['nbox']} "
-        f"W={st['list_len']['W']} O={st['list_len']['O']} rel-L2 = {err:.3e}")
-    assert err <= w.eps
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sphere_8M(orc, precision):
+    w = W.config(6, nsample=2000)
+    log(f"{w.name} n={w.n} nrhs={w.nrhs} {precision}")
+    u, st = _run(w, precision)
+    _check(orc, "sphere8M", w, u, st)
