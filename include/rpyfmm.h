@@ -40,8 +40,8 @@ typedef enum {
   RPY_ENONFINITE = -2,   /* a position is NaN or infinite */
   RPY_ENOMEM = -3,       /* device allocation failed */
   RPY_EDEVICE = -4,      /* a HIP call failed; sticky on the plan */
-  RPY_EUNSUPPORTED = -5  /* option combination not built (reserved: every
-                            combination accepted by validation is built) */
+  RPY_EUNSUPPORTED = -5  /* option combination not built (polynomial
+                            evaluation above order 21) */
 } rpy_status;
 
 typedef enum {
@@ -79,6 +79,16 @@ typedef struct {
                             multipoles.  0 = library choice, (p+1)(p+2);
                             -1 = every W box through its multipole.  Callers
                             whose struct_size ends before it get 0. */
+  int32_t eval_mode;     /* evaluation of the leaves' local expansions at the
+                            targets, the two approaches of Sec. 2 (after
+                            Theorem 2): 1 = differentiate each Laplace
+                            expansion (derivative sets), then assemble eq.
+                            (2.8) per target; 2 = pre-assemble each velocity
+                            component into one polynomial per leaf, then
+                            evaluate it (orders <= 21; RPY_EUNSUPPORTED
+                            above); 0 = library choice (2 up to order 10,
+                            else 1).  Both give the same result to rounding.
+                            Callers whose struct_size ends before it get 0. */
 } rpy_options;
 
 typedef struct rpy_plan_s rpy_plan_t;
@@ -105,6 +115,8 @@ typedef struct {
   double bead_pass_ms;   /* GPU time of the bead passes of the plan's first
                             tree: bounding cubes, Morton keys, radix sort,
                             position gather */
+  int32_t eval_mode;     /* evaluation approach in use (1 or 2, see options) */
+  int32_t reserved;
 } rpy_plan_stats_t;
 
 /* Fills *opt with the defaults (FP64, automatic leaf size and order,

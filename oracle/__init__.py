@@ -59,7 +59,8 @@ def lib():
         L.orc_translate.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp]
         L.orc_eval_expansion.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_fmm.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, C.c_double, C.c_int,
-                              C.c_int, C.c_int, C.c_int64, _dp, C.c_int]
+                              C.c_int, C.c_int, C.c_int64, C.c_int, _dp, C.c_int]
+        L.orc_solid_monomials.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp]
         L.orc_fmm.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
         L.orc_rpy_dense.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
@@ -246,11 +247,14 @@ class Tree:
         return self.lo[None, :] + (self.anchor + 0.5) * h[:, None]
 
 
-def fmm(pos, forces, a, eta, p, leaf_size, w_direct, max_depth=14, nthreads=0):
+def fmm(pos, forces, a, eta, p, leaf_size, w_direct, max_depth=14, nthreads=0, eval_mode=0):
     """The four-Laplace adaptive FMM (O4) in FP64.  forces [nrhs,n,3] or
     [n,3]; returns the same shape.  W-list boxes with at most w_direct beads
     are summed directly with the far formula, the others through their
-    multipoles (w_direct < 0: all through multipoles); the caller chooses."""
+    multipoles (w_direct < 0: all through multipoles); the caller chooses.
+    eval_mode: 0 = Sec. 2's first evaluation approach (Theorem 2 derivatives
+    per Laplace expansion, then eq. (2.8)); 1 = its second approach (one
+    pre-assembled polynomial per velocity component and leaf)."""
     pos = _f64(pos)
     F = _f64(forces)
     squeeze = F.ndim == 2
@@ -258,10 +262,19 @@ def fmm(pos, forces, a, eta, p, leaf_size, w_direct, max_depth=14, nthreads=0):
         F = F[None]
     out = np.zeros_like(F)
     rc = lib().orc_fmm(pos.shape[0], pos, F.shape[0], F, a, eta, int(p), int(leaf_size),
-                       int(max_depth), int(w_direct), out, nthreads)
+                       int(max_depth), int(w_direct), int(eval_mode), out, nthreads)
     if rc != 0:
         raise ValueError("orc_fmm rejected its arguments")
     return out[0] if squeeze else out
+
+
+def solid_monomials(P, n, m):
+    """Monomial coefficients [a, b, c] (a + b + c <= P) of r^n P_n^m(cos t)
+    e^{i m phi}, Condon-Shortley phase, as a complex (P+1)^3 array."""
+    re = np.zeros((P + 1) ** 3)
+    im = np.zeros((P + 1) ** 3)
+    lib().orc_solid_monomials(int(P), int(n), int(m), re, im)
+    return (re + 1j * im).reshape(P + 1, P + 1, P + 1)
 
 
 def rel_l2(u, ref):

@@ -776,6 +776,137 @@ void orc_p2l(int p, int64_t nb, const double* pos, const double* q, const double
   free(L);
 }
 
+/* ------------------------------------------- O4, second evaluation approach --- */
+
+/* Sec. 2 names two ways to evaluate eq. (2.8) at a target: differentiate each
+ * Laplace expansion and assemble (the first, used by l2t/m2t above), or
+ * simplify each velocity component into a single expansion first and then
+ * evaluate it (the second).  Near a leaf centre c, the local part of each
+ * component, u_k(v) = C1 L_k - C1 sum_s v_s d_k L_s + C1 d_k L_4 - C2 d_k
+ * sum_s d_s L_s with v = x - c, is a polynomial of degree p in v (the
+ * product v_s d_k L_s is not harmonic, so the single expansion is written in
+ * monomials v_x^a v_y^b v_z^c; these are also the polynomial expansions the
+ * paper's conclusion proposes at low accuracy).  Polynomials of degree <= P
+ * are dense arrays PC(a, b, c) over a, b, c <= P with a + b + c <= P. */
+#define PC(a, b, c) (((a) * (P + 1) + (b)) * (P + 1) + (c))
+
+static double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  return fact(n) / (fact(k) * fact(n - k));
+}
+
+/* Monomial coefficients of r^n P_n^m(cos theta) e^{i m phi}, 0 <= m <= n <= P
+ * (Condon-Shortley phase), written out from Rodrigues' formula:
+ *   P_n(t) = 2^-n sum_k (-1)^k C(n,k) C(2n-2k,n) t^(n-2k),
+ *   P_n^m(t) = (-1)^m (1 - t^2)^(m/2) d^m P_n / dt^m,
+ * so that, with t = z/r and r sin(theta) e^{i phi} = x + i y,
+ *   r^n P_n^m e^{i m phi} = (-1)^m (x + iy)^m sum_k a_k z^(n-m-2k) (x^2+y^2+z^2)^k,
+ *   a_k = 2^-n (-1)^k C(n,k) C(2n-2k,n) (n-2k)! / (n-2k-m)!,
+ * expanded with the binomial and trinomial theorems.  out holds (P+1)^3
+ * complex coefficients and is overwritten. */
+void orc_solid_monomials(int P, int n, int m, double* out_re, double* out_im) {
+  const int N3 = (P + 1) * (P + 1) * (P + 1);
+  for (int i = 0; i < N3; ++i) out_re[i] = out_im[i] = 0.0;
+  const double sgn_m = (m & 1) ? -1.0 : 1.0;
+  for (int k = 0; 2 * k <= n - m; ++k) {
+    const double ak = ldexp(1.0, -n) * ((k & 1) ? -1.0 : 1.0) * binom(n, k) * binom(2 * n - 2 * k, n) *
+                      fact(n - 2 * k) / fact(n - 2 * k - m);
+    const int zp = n - m - 2 * k;
+    for (int j = 0; j <= m; ++j) {        /* (x + iy)^m: C(m,j) x^(m-j) (iy)^j */
+      const double cj = binom(m, j);
+      const double ire = (j % 4 == 0) ? 1.0 : (j % 4 == 2 ? -1.0 : 0.0);
+      const double iim = (j % 4 == 1) ? 1.0 : (j % 4 == 3 ? -1.0 : 0.0);
+      for (int k1 = 0; k1 <= k; ++k1)     /* (x^2 + y^2 + z^2)^k */
+        for (int k2 = 0; k1 + k2 <= k; ++k2) {
+          const int k3 = k - k1 - k2;
+          const double tri = fact(k) / (fact(k1) * fact(k2) * fact(k3));
+          const int a = m - j + 2 * k1, b = j + 2 * k2, c = zp + 2 * k3;
+          const double w = sgn_m * ak * cj * tri;
+          out_re[PC(a, b, c)] += w * ire;
+          out_im[PC(a, b, c)] += w * iim;
+        }
+    }
+  }
+}
+
+/* The local expansion sum_{n,m} L_n^m r^n Y_n^m (Sec. 2) of a real field, m >= 0
+ * stored, as a real polynomial of degree p: out (P >= p) overwritten. */
+static void local_to_poly(int p, int P, const cplx* L, double* out, double* tre, double* tim) {
+  const int N3 = (P + 1) * (P + 1) * (P + 1);
+  for (int i = 0; i < N3; ++i) out[i] = 0.0;
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      orc_solid_monomials(P, n, m, tre, tim);
+      const cplx c = (m ? 2.0 : 1.0) * L[IDX(n, m)] * sqrt(fact(n - m) / fact(n + m));
+      for (int i = 0; i < N3; ++i) out[i] += creal(c) * tre[i] - cimag(c) * tim[i];
+    }
+}
+
+/* out += w * d/dv_k of f (degree <= P). */
+static void poly_add_deriv(int P, const double* f, int k, double w, double* out) {
+  for (int a = 0; a <= P; ++a)
+    for (int b = 0; a + b <= P; ++b)
+      for (int c = 0; a + b + c <= P; ++c) {
+        const int e[3] = {a, b, c};
+        if (e[k] == 0) continue;
+        int d[3] = {a, b, c};
+        d[k] -= 1;
+        out[PC(d[0], d[1], d[2])] += w * e[k] * f[PC(a, b, c)];
+      }
+}
+
+/* out += w * v_k * f, f of degree <= P - 1. */
+static void poly_add_times_v(int P, const double* f, int k, double w, double* out) {
+  for (int a = 0; a <= P; ++a)
+    for (int b = 0; a + b <= P; ++b)
+      for (int c = 0; a + b + c < P; ++c) {
+        int d[3] = {a, b, c};
+        d[k] += 1;
+        out[PC(d[0], d[1], d[2])] += w * f[PC(a, b, c)];
+      }
+}
+
+static double poly_eval(int P, const double* f, const double v[3]) {
+  double s = 0.0, xa = 1.0;
+  for (int a = 0; a <= P; ++a, xa *= v[0]) {
+    double yb = xa;
+    for (int b = 0; a + b <= P; ++b, yb *= v[1]) {
+      double zc = yb;
+      for (int c = 0; a + b + c <= P; ++c, zc *= v[2]) s += f[PC(a, b, c)] * zc;
+    }
+  }
+  return s;
+}
+
+/* The three velocity polynomials U_k (degree p) of a leaf from its four local
+ * expansions L (box-centred fourth density), eq. (2.8) with the C2 term's
+ * minus sign: U_k = C1 L_k - C1 sum_s v_s d_k L_s + C1 d_k L_4 - C2 d_k sum_s d_s L_s.
+ * U holds 3 (P+1)^3 doubles, P = p. */
+static void leaf_velocity_polys(int p, const cplx* L, int T, double C1, double C2, double* U) {
+  const int P = p, N3 = (P + 1) * (P + 1) * (P + 1);
+  double* Lp = malloc(sizeof(double) * 4 * N3);
+  double* D = malloc(sizeof(double) * 3 * N3);  /* d_k L_s scratch */
+  double* LC = malloc(sizeof(double) * N3);     /* sum_s d_s L_s */
+  double* tre = malloc(sizeof(double) * N3);
+  double* tim = malloc(sizeof(double) * N3);
+  for (int s = 0; s < 4; ++s) local_to_poly(p, P, L + (size_t)s * T, Lp + (size_t)s * N3, tre, tim);
+  for (int i = 0; i < N3; ++i) LC[i] = 0.0;
+  for (int s = 0; s < 3; ++s) poly_add_deriv(P, Lp + (size_t)s * N3, s, 1.0, LC);
+  for (int k = 0; k < 3; ++k) {
+    double* Uk = U + (size_t)k * N3;
+    for (int i = 0; i < N3; ++i) Uk[i] = C1 * Lp[(size_t)k * N3 + i];
+    poly_add_deriv(P, Lp + 3 * (size_t)N3, k, C1, Uk);
+    poly_add_deriv(P, LC, k, -C2, Uk);
+    for (int s = 0; s < 3; ++s) {
+      for (int i = 0; i < N3; ++i) D[i] = 0.0;
+      poly_add_deriv(P, Lp + (size_t)s * N3, k, 1.0, D);  /* d_k L_s, degree p - 1 */
+      poly_add_times_v(P, D, s, -C1, Uk);
+    }
+  }
+  free(Lp); free(D); free(LC); free(tre); free(tim);
+}
+#undef PC
+
 static void box_center(const orc_tree* t, int64_t b, double c[3]) {
   double h = ldexp(t->side, -t->level[b]);
   for (int k = 0; k < 3; ++k) c[k] = t->lo[k] + ((double)t->anchor[3 * b + k] + 0.5) * h;
@@ -795,12 +926,18 @@ static void box_center(const orc_tree* t, int64_t b, double c[3]) {
  * directly with the far formula and the others go through Theorem 1
  * (w_direct < 0: every W box through its multipole).  The threshold is an
  * input, so that a caller can choose either branch for any W box.
+ * eval_mode selects how the local expansions are evaluated at the targets:
+ * 0 = the first approach of Sec. 2 (each Laplace expansion differentiated by
+ * Theorem 2, then eq. (2.8)); 1 = the second approach (each velocity
+ * component pre-assembled into one polynomial per leaf, then evaluated).
+ * W-list multipoles are always evaluated by the first approach.
  * pos [n][3], F [nrhs][n][3], out [nrhs][n][3], all in caller order.
  * Returns 0, or -1 for invalid arguments.
  */
 int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, double eta, int p,
-            int leaf_size, int max_depth, int64_t w_direct, double* out, int nthreads) {
+            int leaf_size, int max_depth, int64_t w_direct, int eval_mode, double* out, int nthreads) {
   if (n < 0 || p < 0 || p > 40 || nrhs < 1 || a <= 0 || eta <= 0 || leaf_size < 1) return -1;
+  if (eval_mode != 0 && eval_mode != 1) return -1;
   if (n == 0) return 0;
   set_threads(nthreads);
   orc_tree* t = orc_tree_build(n, pos, leaf_size, max_depth, a);
@@ -914,12 +1051,20 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
       if (t->nchild[b]) continue;
       const double* cb = ctr + 3 * b;
       cplx* Mw = malloc(sizeof(cplx) * T * 4);
+      /* second approach: the leaf's three velocity polynomials, once */
+      const int N3 = (p + 1) * (p + 1) * (p + 1);
+      double* Up = NULL;
+      if (eval_mode == 1) {
+        Up = malloc(sizeof(double) * 3 * N3);
+        leaf_velocity_polys(p, L + (size_t)b * 4 * T, T, C1, C2, Up);
+      }
       for (int64_t i = t->begin[b]; i < t->end[b]; ++i) {
         const double* x = spos + 3 * i;
         double v[3] = {x[0] - cb[0], x[1] - cb[1], x[2] - cb[2]};
         vgh_t f[4];
         memset(f, 0, sizeof f);
-        for (int s = 0; s < 4; ++s) l2t(&o, L + ((size_t)b * 4 + s) * T, v, &f[s]);
+        if (eval_mode == 0)
+          for (int s = 0; s < 4; ++s) l2t(&o, L + ((size_t)b * 4 + s) * T, v, &f[s]);
         double wd[3] = {0, 0, 0};
         for (int64_t e = t->off[2][b]; e < t->off[2][b + 1]; ++e) {
           int64_t C = t->ent[2][e];
@@ -947,6 +1092,7 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
           double xs = 0, gLc = 0;
           for (int s = 0; s < 3; ++s) { xs += v[s] * f[s].g[k]; gLc += f[s].h[k][s]; }
           u[k] = C1 * f[k].v - C1 * xs + C1 * f[3].g[k] - C2 * gLc + wd[k];
+          if (eval_mode == 1) u[k] += poly_eval(p, Up + (size_t)k * N3, v);
         }
         for (int64_t e = t->off[0][b]; e < t->off[0][b + 1]; ++e) {
           int64_t C = t->ent[0][e];
@@ -979,6 +1125,7 @@ int orc_fmm(int64_t n, const double* pos, int nrhs, const double* F, double a, d
         for (int k = 0; k < 3; ++k) ro[3 * ci + k] = u[k];
       }
       free(Mw);
+      free(Up);
     }
   }
   free(spos); free(ctr); free(M); free(L); free(sF); free(o.s);

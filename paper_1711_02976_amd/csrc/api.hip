@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,10 +16,18 @@
 
 namespace {
 
-thread_local std::string g_last_error;
+// Detail of the last failure on this thread: a fixed buffer (trivially
+// destructible, so no thread-exit or process-exit handler is registered).
+thread_local char g_last_error[512];
+
+void set_error(const std::string& msg) {
+  const size_t k = std::min(msg.size(), sizeof(g_last_error) - 1);
+  std::memcpy(g_last_error, msg.data(), k);
+  g_last_error[k] = 0;
+}
 
 rpy_status fail(rpy_status s, const std::string& msg) {
-  g_last_error = msg;
+  set_error(msg);
   return s;
 }
 
@@ -34,6 +43,9 @@ rpy_status fail(rpy_status s, const std::string& msg) {
 // 9-digit setting) the order is the highest built, 27: on 20k beads in a
 // uniform cube p = 21, 24, 27 give 3.3e-8, 9.0e-9, 2.6e-9, and on 20k
 // clustered beads (adaptive tree) 1.3e-7, 3.1e-8, 7.5e-9.
+// Highest order at which the library picks the polynomial evaluation.
+constexpr int EVAL_POLY_AUTO_MAX = 10;
+
 int order_for_eps(double eps, bool adaptive) {
   static const double tol[] = {1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 3e-5, 1e-5, 3e-6, 1e-6, 3e-7, 1e-7,
                                3e-8, 1e-8};
@@ -138,6 +150,21 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
 
 }  // namespace
 
+// Matvec workspace for the right-hand sides of one pass.
+struct Work {
+  double2* M = nullptr;   // multipoles [nbox][4 nrc][T]
+  double2* L = nullptr;   // local expansions [nbox][4 nrc][T]
+  double* sF = nullptr;   // forces, tree order [nrc][3][n]
+  double* u = nullptr;    // near-field velocities, tree order
+  double* uf = nullptr;   // far-field velocities, tree order
+  double* Q = nullptr;    // per-bead charges for S->M / S->L [n + 64][4 nrc]
+  double2* DL = nullptr;  // evaluation sets (local expansions of the leaves)
+  double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
+  double2* XP = nullptr;  // S->L partial sums of boxes split over several work items
+  double* PV = nullptr;   // polynomial evaluation: the leaves' density polynomials
+};
+constexpr int WS_N = 10;  // arrays of Work, in the order above
+
 struct rpy_plan_s {
   rpy::Built B;
   rpy::Tables tb{};
@@ -145,7 +172,9 @@ struct rpy_plan_s {
   rpy::EvalPlan ep{};
   int p = 0, leaf_size = 0, max_depth = 14, precision = 0, m2l_mode = 2;
   int wd = 0;         // W-list boxes of at most wd beads are summed directly (< 0: none)
+  int eval_mode = 0;  // rpy::EVAL_SETS or rpy::EVAL_POLY
   int inject = -1;    // phase at which the next pass reports a HIP error (tests)
+  int device = 0;     // device current when the plan was built
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
   // The near field (P2P, overlap and direct W sums) runs on a second stream
@@ -161,15 +190,7 @@ struct rpy_plan_s {
   int sticky = 0;
   // matvec workspace, sized for `ws_nrc` right-hand sides per pass
   int ws_nrc = 0;
-  double2* M = nullptr;
-  double2* L = nullptr;
-  double* sF = nullptr;
-  double* u = nullptr;   // near-field velocities, tree order
-  double* uf = nullptr;  // far-field velocities, tree order
-  double* Q = nullptr;   // per-bead charges for S->M / S->L, tree order
-  double2* DL = nullptr;  // evaluation sets (local expansions of the leaves)
-  double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
-  double2* XP = nullptr;  // S->L partial sums of boxes split over several work items
+  Work ws{};
   int64_t ws_bytes = 0;
   // Krylov workspace (rpy_sqrt_matvec), grown on demand
   double* kbuf = nullptr;
@@ -184,6 +205,26 @@ struct rpy_plan_s {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;  // (phase, start, stop)
   rpy_timings_t acc{};
 };
+
+// Bytes of each Work array for nrc right-hand sides per pass.  Q carries
+// 64 rows past the last bead that the S->M/S->L kernels may read (with zero
+// weight); they must hold finite values (zeros).
+static void ws_sizes(const rpy_plan_t* P, int nrc, size_t sz[WS_N]) {
+  const int64_t T = rpy::ncoef(P->p);
+  const int64_t nbox = std::max(P->B.tree.nbox, 1);
+  const int64_t n = std::max<int64_t>(P->B.n, 1);
+  const size_t ex = sizeof(double2) * nbox * 4 * nrc * T;
+  const size_t vb = sizeof(double) * 3 * nrc * n;
+  int64_t dwb = 0, pvb = 0;
+  const size_t dlb = (size_t)rpy::eval_sets_bytes(&P->B, P->ep, P->p, nrc, &dwb, &pvb);
+  sz[0] = sz[1] = ex;
+  sz[2] = sz[3] = sz[4] = vb;
+  sz[5] = sizeof(double) * 4 * nrc * (n + 64);
+  sz[6] = dlb;
+  sz[7] = (size_t)dwb;
+  sz[8] = sizeof(double2) * std::max<int64_t>(P->B.nxshared, 1) * 4 * nrc * T;
+  sz[9] = (size_t)pvb;
+}
 
 static hipEvent_t get_event(rpy_plan_t* P) {
   if (!P->ev_pool.empty()) {
@@ -220,11 +261,11 @@ static void fold_events(rpy_plan_t* P) {
 }
 
 static void free_ws(rpy_plan_t* P) {
-  void* ps[] = {P->M, P->L, P->sF, P->u, P->uf, P->Q, P->DL, P->DW, P->XP};
+  Work& w = P->ws;
+  void* ps[] = {w.M, w.L, w.sF, w.u, w.uf, w.Q, w.DL, w.DW, w.XP, w.PV};
   for (void* p : ps)
     if (p) (void)hipFree(p);
-  P->M = P->L = P->DL = P->DW = P->XP = nullptr;
-  P->sF = P->u = P->uf = P->Q = nullptr;
+  w = Work{};
   P->ws_nrc = 0;
   P->ws_bytes = 0;
 }
@@ -232,34 +273,37 @@ static void free_ws(rpy_plan_t* P) {
 static int alloc_ws(rpy_plan_t* P, int nrc) {
   if (P->ws_nrc >= nrc) return 0;
   free_ws(P);
-  const int64_t T = rpy::ncoef(P->p);
-  const int64_t nbox = std::max(P->B.tree.nbox, 1);
-  const int64_t n = std::max<int64_t>(P->B.n, 1);
-  size_t ex = sizeof(double2) * nbox * 4 * nrc * T;
-  // Q: per-bead charges plus 64 rows that the S->M/S->L kernels may read past
-  // the last bead (with zero weight); zeroed once so every row is finite
-  size_t vb = sizeof(double) * 3 * nrc * n, qb = sizeof(double) * 4 * nrc * (n + 64);
-  int64_t dwb = 0;
-  const size_t dlb = (size_t)rpy::eval_sets_bytes(&P->B, P->ep, P->p, nrc, &dwb);
-  const size_t xpb = sizeof(double2) * std::max<int64_t>(P->B.nxshared, 1) * 4 * nrc * T;
-  if (hipMalloc(&P->M, ex) != hipSuccess || hipMalloc(&P->L, ex) != hipSuccess ||
-      hipMalloc(&P->sF, vb) != hipSuccess || hipMalloc(&P->u, vb) != hipSuccess ||
-      hipMalloc(&P->uf, vb) != hipSuccess || hipMalloc(&P->Q, qb) != hipSuccess ||
-      hipMemset(P->Q, 0, qb) != hipSuccess || hipMalloc(&P->DL, dlb) != hipSuccess ||
-      hipMalloc(&P->DW, (size_t)dwb) != hipSuccess || hipMalloc(&P->XP, xpb) != hipSuccess) {
+  size_t sz[WS_N];
+  ws_sizes(P, nrc, sz);
+  Work& w = P->ws;
+  void** dst[WS_N] = {(void**)&w.M, (void**)&w.L, (void**)&w.sF, (void**)&w.u, (void**)&w.uf,
+                      (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV};
+  int64_t tot = 0;
+  for (int k = 0; k < WS_N; ++k) {
+    if (hipMalloc(dst[k], sz[k]) != hipSuccess) {
+      (void)hipGetLastError();
+      *dst[k] = nullptr;
+      free_ws(P);
+      return -1;
+    }
+    tot += sz[k];
+  }
+  // zeroed once so that every row of Q, including the padding, is finite
+  if (hipMemset(w.Q, 0, sz[5]) != hipSuccess) {
     free_ws(P);
     return -1;
   }
   P->ws_nrc = nrc;
-  P->ws_bytes = 2 * ex + 3 * vb + qb + dlb + dwb + xpb;
+  P->ws_bytes = tot;
   return 0;
 }
 
 // One matvec pass over right-hand sides r0 .. r0 + c - 1.  Every step runs
 // only if all earlier ones were issued without error; the first error is
 // returned and nothing after it is issued.
-static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const rpy::Exp& e, const double* forces, int nrhs,
-                              int r0, int c, int mixed, double* velocities) {
+static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const Work& w, const double* forces, int nrhs,
+                              int r0, int c, int mixed, double* velocities, bool untimed = false) {
+  const rpy::Exp e{w.M, w.L, w.Q, w.DL, w.DW, w.XP, w.PV};
   const rpy::Built& B = P->B;
   const int nlev = B.depth;
   const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
@@ -275,22 +319,23 @@ static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const rpy::Ex
       P->inject = -1;
       return hipErrorLaunchFailure;
     }
+    if (untimed) return f();
     return timed(P, phase, launches, st, f);
   };
-  hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, P->sF); });
+  hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, w.sF); });
   // near field on s1, after the permute
   if (he == hipSuccess && fork) {
     he = hipEventRecord(P->ev_fork, s0);
     if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
   }
-  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, P->sF, P->u, mixed); });
+  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, w.sF, w.u, mixed); });
   if (he == hipSuccess && haveO)
-    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, P->sF, P->u); });
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, w.sF, w.u); });
   if (he == hipSuccess && haveW)
-    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, P->sF, P->u, mixed); });
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, w.sF, w.u, mixed); });
   if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
   // far field on s0
-  if (he == hipSuccess) he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, P->sF, e); });
+  if (he == hipSuccess) he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, w.sF, e); });
   // the deepest level's M->L needs only S->M: on a third stream, beside
   // the upward pass (it writes L of other boxes than the second part)
   const bool split = fork && P->far2 && P->m2l_mode != 1;
@@ -308,13 +353,13 @@ static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const rpy::Ex
     return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
   });
   if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
-  if (he == hipSuccess && haveX) he = step(RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, P->sF, e); });
+  if (he == hipSuccess && haveX) he = step(RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, w.sF, e); });
   if (he == hipSuccess) he = step(RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
-  if (he == hipSuccess) he = step(RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, P->uf); });
+  if (he == hipSuccess) he = step(RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, w.uf); });
   // join, then near + far back to caller order
   if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
   if (he == hipSuccess)
-    he = step(RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, P->u, P->uf, r0, c, velocities); });
+    he = step(RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, w.u, w.uf, r0, c, velocities); });
   return he;
 }
 
@@ -340,7 +385,7 @@ const char* rpy_status_string(rpy_status s) {
   return "unknown status";
 }
 
-const char* rpy_last_error(void) { return g_last_error.c_str(); }
+const char* rpy_last_error(void) { return g_last_error; }
 
 rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* counts, const double* positions,
                             double a, double eta, double eps, const rpy_options* opt) {
@@ -376,8 +421,16 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.nrhs < 0) return fail(RPY_EINVAL, "nrhs must be >= 0");
   if (o.m2l_mode < 0 || o.m2l_mode > 2) return fail(RPY_EINVAL, "m2l_mode must be 0, 1 or 2");
   if (o.w_direct < -1) return fail(RPY_EINVAL, "w_direct must be -1, 0 or a bead count");
+  if (o.eval_mode < 0 || o.eval_mode > 2) return fail(RPY_EINVAL, "eval_mode must be 0, 1 or 2");
+  if (o.eval_mode == 2 && o.order > rpy::EVAL_POLY_MAX_ORDER)
+    return fail(RPY_EUNSUPPORTED, "polynomial evaluation is built up to order 21");
 
   rpy_plan_t* P = new rpy_plan_t();
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return fail(RPY_EDEVICE, "hipGetDevice failed");
+  }
   P->a = a;
   P->eta = eta;
   P->eps = eps;
@@ -390,6 +443,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   // one at p = 16 in FP64); the mixed form runs it in FP32.
   P->m2l_mode = o.m2l_mode != 0 ? o.m2l_mode : 2;
   P->wd = o.w_direct;
+  P->eval_mode = o.eval_mode;
 
   std::vector<int64_t> sb(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) sb[s + 1] = sb[s] + counts[s];
@@ -472,9 +526,16 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (rc == 0 && P->p == 0)
     P->p = order_for_eps(eps, P->B.lists[rpy::LW].len > 0 || P->B.lists[rpy::LX].len > 0);
   if (P->wd == 0) P->wd = rpy::wdirect_default(P->p);
+  if (rc == 0 && P->eval_mode == 2 && P->p > rpy::EVAL_POLY_MAX_ORDER) {
+    rpy_plan_free(P);
+    return fail(RPY_EUNSUPPORTED, "polynomial evaluation is built up to order 21");
+  }
+  // library choice: the component polynomials at low orders (fewer
+  // operations per target), the derivative sets above
+  if (P->eval_mode == 0) P->eval_mode = P->p <= EVAL_POLY_AUTO_MAX ? rpy::EVAL_POLY : rpy::EVAL_SETS;
   if (rc == 0) rc = rpy::make_tables(P->p, &P->tb, P->stream, &err);
   if (rc == 0) rc = rpy::make_tiles(&P->B, 128, &P->tiles, P->stream, &err);
-  if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, P->wd, &P->ep, P->stream, &err);
+  if (rc == 0) rc = rpy::make_eval_plan(&P->B, P->p, P->wd, P->eval_mode, &P->ep, P->stream, &err);
   if (rc == 0) rc = rpy::make_m2l_map(&P->B, P->stream, &err);
   if (rc == 0) rc = rpy::make_p2l_work(&P->B, P->stream, &err);
   if (rc == 0) {
@@ -504,7 +565,7 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
 
   if (rc != 0) {
     rpy_status st = rc == -2 ? RPY_ENONFINITE : rc == -3 ? RPY_ENOMEM : RPY_EDEVICE;
-    g_last_error = err.msg;
+    set_error(err.msg);
     rpy_plan_free(P);
     return st;
   }
@@ -535,11 +596,10 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
-  rpy::Exp e{P->M, P->L, P->Q, P->DL, P->DW, P->XP};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
     int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
-    const hipError_t he = matvec_pass(P, l, e, forces, nrhs, r0, c, mixed, velocities);
+    const hipError_t he = matvec_pass(P, l, P->ws, forces, nrhs, r0, c, mixed, velocities);
     if (P->timing) P->acc.passes += 1;
     if (he != hipSuccess) {
       P->sticky = 1;
@@ -735,6 +795,7 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   out->device_bytes = P->B.bytes + P->tb.bytes + P->ws_bytes + (int64_t)(sizeof(int4) + 6 * sizeof(double)) * P->tiles.n;
   out->plan_ms = P->plan_ms;
   out->w_direct = P->wd;
+  out->eval_mode = P->eval_mode;
   out->p2l_items = P->B.nxwork;
   out->p2l_split_boxes = P->B.nxred;
   out->bead_pass_ms = P->bead_pass_ms;

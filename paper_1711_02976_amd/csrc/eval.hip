@@ -247,6 +247,190 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4*
       for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + tl.y + lane] = vel[r][k];
 }
 
+// ------------------------------------------- second evaluation approach ---
+// Sec. 2 names a second way to evaluate eq. (2.8): simplify each velocity
+// component into a single expansion, then evaluate it.  About a leaf centre c
+// the local part of component k,
+//   U_k(v) = C1 L_k - C1 sum_s v_s d_k L_s + C1 d_k L_4 - C2 d_k sum_s d_s L_s,
+// v = x - c, is a polynomial of degree p in v (v_s d_k L_s is not harmonic),
+// so each leaf's three components are pre-assembled as polynomials in the
+// monomials u_x^a u_y^b u_z^c of u = v / h, and every target evaluates them
+// with nested Horner-like products.  These are also the polynomial
+// expansions the paper's conclusion proposes for low accuracy: per target
+// and right-hand side 3 (p+1)(p+2)(p+3)/6 multiply-adds and no harmonic
+// recurrence, against 12 complex sets of (p+1)(p+2)/2 coefficients.
+//
+// Three kernels: k_poly_conv turns each (leaf, density) local expansion into
+// monomial coefficients (a dense product with a table KcT of the monomial
+// coefficients of R_n^m, shared by all leaves), k_poly_assemble forms the
+// three components by index arithmetic (derivatives and products with u_s
+// shift monomial indices), and k_eval_poly_apply evaluates them and adds the
+// W-list multipoles (first approach, harmonic sets).
+//
+// Monomials of degree <= p are numbered with a outermost, then b, then c:
+//   mono_index(a, b, c) = t3(p+1) - t3(p+1-a) + b (p-a+1) - b (b-1)/2 + c,
+// t3(n) = n(n+1)(n+2)/6 (the number of monomials of degree < n).
+__host__ __device__ inline int t3(int n) { return n * (n + 1) * (n + 2) / 6; }
+__host__ __device__ inline int mono_count(int p) { return t3(p + 1); }
+__host__ __device__ inline int mono_index(int p, int a, int b, int c) {
+  return t3(p + 1) - t3(p + 1 - a) + b * (p - a + 1) - b * (b - 1) / 2 + c;
+}
+
+constexpr int POLY_T = 256;
+
+// C[(i * ND + d) * NM + j] = (1/h) Re sum_n,m f_m E_d[n][m] R_n^m |_j for the
+// ND densities of leaf i (f_m = 2 for m > 0), from the stored coefficients
+// (L h^{n+1}) and KcT[t'][j] (t' = 2 (n,m) + {0: real, 1: imaginary part}).
+// One block per leaf; each thread takes monomials j and keeps ND sums.
+template <int ND>
+__global__ void __launch_bounds__(POLY_T) k_poly_conv(int p, const int* leaves, Tree t, const double2* E,
+                                                      const double* __restrict__ kct, double* C) {
+  const int i = blockIdx.x, b = leaves[i];
+  const int T = ncoef(p), NM = mono_count(p);
+  extern __shared__ double Lr[];  // [2T][ND]
+  const double2* src = E + (int64_t)b * ND * T;
+  for (int x = threadIdx.x; x < ND * T; x += POLY_T) {
+    const int d = x / T, c = x - d * T;
+    const double2 v = src[x];
+    Lr[(2 * c) * ND + d] = v.x;
+    Lr[(2 * c + 1) * ND + d] = v.y;
+  }
+  __syncthreads();
+  const double ih = 1.0 / t.h[b];
+  for (int j = threadIdx.x; j < NM; j += POLY_T) {
+    double acc[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+    for (int q = 0; q < 2 * T; ++q) {
+      const double k = kct[(int64_t)q * NM + j];
+      if (k == 0.0) continue;  // R_n^m has only degree-n monomials
+#pragma unroll
+      for (int d = 0; d < ND; ++d) acc[d] = fma(k, Lr[q * ND + d], acc[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) C[((int64_t)i * ND + d) * NM + j] = acc[d] * ih;
+  }
+}
+
+// The three component polynomials of leaf i and right-hand side r from its
+// four density polynomials c_s (in u = v/h, with d/dv = (1/h) d/du):
+//   U_k = C1 c_k - C1 sum_s u_s d_k c_s + (C1/h) d_k c_4 - (C2/h^2) d_k sum_s d_s c_s,
+// written to U[((i * NM + j) * NRC + r) * 3 + k] (the order the evaluation
+// reads them).
+template <int NRC>
+__global__ void __launch_bounds__(POLY_T) k_poly_assemble(int p, const int* leaves, Tree t, const double* C,
+                                                          double C1, double C2, double* U) {
+  constexpr int ND = 4 * NRC;
+  const int i = blockIdx.x, r = blockIdx.y, b = leaves[i];
+  const int NM = mono_count(p);
+  extern __shared__ double cs[];  // [4][NM]
+  for (int x = threadIdx.x; x < 4 * NM; x += POLY_T) {
+    const int s = x / NM, j = x - s * NM;
+    cs[x] = C[((int64_t)i * ND + 4 * r + s) * NM + j];
+  }
+  __syncthreads();
+  const double h = t.h[b], c1h = C1 / h, c2h = C2 / (h * h);
+  // coefficient of density s at exponents e (0 past degree p or below 0)
+  auto at = [&](int s, int e0, int e1, int e2) -> double {
+    if (e0 < 0 || e1 < 0 || e2 < 0 || e0 + e1 + e2 > p) return 0.0;
+    return cs[s * NM + mono_index(p, e0, e1, e2)];
+  };
+  for (int x = threadIdx.x; x < 3 * NM; x += POLY_T) {
+    const int k = x / NM, j = x - k * NM;
+    int al[3] = {0, 0, 0};
+    {
+      int a = 0;
+      while (t3(p + 1) - t3(p - a) <= j) ++a;
+      const int rem = j - (t3(p + 1) - t3(p + 1 - a));
+      int bb = 0;
+      while (bb * (p - a + 1) - bb * (bb - 1) / 2 + (p - a - bb + 1) <= rem) ++bb;
+      al[0] = a;
+      al[1] = bb;
+      al[2] = rem - (bb * (p - a + 1) - bb * (bb - 1) / 2);
+    }
+    double v = C1 * cs[k * NM + j];
+    // -C1 sum_s u_s d_k c_s: the monomial alpha comes from beta = alpha - e_s
+    // of d_k c_s, whose coefficient is (beta_k + 1) c_s[beta + e_k]
+    for (int s = 0; s < 3; ++s) {
+      if (al[s] == 0) continue;
+      int be[3] = {al[0], al[1], al[2]};
+      be[s] -= 1;
+      const int bk = be[k];
+      be[k] += 1;
+      v -= C1 * (bk + 1) * at(s, be[0], be[1], be[2]);
+    }
+    int ak[3] = {al[0], al[1], al[2]};
+    ak[k] += 1;  // alpha + e_k
+    v += c1h * (al[k] + 1) * at(3, ak[0], ak[1], ak[2]);
+    // -(C2/h^2) d_k sum_s d_s c_s
+    double lc = 0.0;
+    for (int s = 0; s < 3; ++s) {
+      int g[3] = {ak[0], ak[1], ak[2]};
+      const int gs = g[s];
+      g[s] += 1;
+      lc += (gs + 1) * at(s, g[0], g[1], g[2]);
+    }
+    v -= c2h * (al[k] + 1) * lc;
+    U[(((int64_t)i * NM + j) * NRC + r) * 3 + k] = v;
+  }
+}
+
+// One wave per tile of up to 64 beads of one leaf (as k_eval_apply): the
+// leaf's component polynomials at u = (x - c)/h, read through scalar loads,
+// plus the W-list multipoles through their evaluation sets.
+template <int NRC>
+__global__ void __launch_bounds__(64 * EV_WAVES) k_eval_poly_apply(int p, const int4* tiles, int ntiles, Tree t,
+                                                                   List W, const int* widx, const double* sx,
+                                                                   const double* sy, const double* sz, int64_t n,
+                                                                   const double* __restrict__ DP,
+                                                                   const double2* __restrict__ DW, double C1,
+                                                                   double* __restrict__ u) {
+  const int ti = blockIdx.x * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (ti >= ntiles) return;
+  const int4 tl = tiles[ti];
+  const int b = tl.x, lane = threadIdx.x & 63;
+  const int j = tl.y + min(lane, tl.z - 1);
+  const double px = sx[j], py = sy[j], pz = sz[j];
+  const int To = ncoef(p + 2), NM = mono_count(p);
+  const double ih = 1.0 / t.h[b];
+  const double ux = (px - t.cx[b]) * ih, uy = (py - t.cy[b]) * ih, uz = (pz - t.cz[b]) * ih;
+  double vel[NRC][3];
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) vel[r][0] = vel[r][1] = vel[r][2] = 0.0;
+  const double* D = DP + (int64_t)tl.w * NM * NRC * 3;
+  double xa = 1.0;
+  for (int a = 0; a <= p; ++a) {
+    double yb = xa;
+    for (int bb = 0; a + bb <= p; ++bb) {
+      double zc = yb;
+      for (int c = 0; a + bb + c <= p; ++c) {
+#pragma unroll
+        for (int r = 0; r < NRC; ++r)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) vel[r][k] = fma(D[3 * r + k], zc, vel[r][k]);
+        D += 3 * NRC;
+        zc *= uz;
+      }
+      yb *= uy;
+    }
+    xa *= ux;
+  }
+  const int w0 = W.off[b], w1 = W.off[b + 1];
+  for (int r = 0; r < NRC; ++r)
+    for (int e = w0; e < w1; ++e) {
+      const int C = W.ent[e];
+      const int wi = widx[C];
+      if (wi < 0) continue;  // few beads: summed directly with the near field
+      eval_sets<true>(DW + ((int64_t)wi * NRC + r) * To * 12, p + 2, px - t.cx[C], py - t.cy[C], pz - t.cz[C],
+                      t.h[C], C1, vel[r]);
+    }
+  if (lane < tl.z)
+#pragma unroll
+    for (int r = 0; r < NRC; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) u[((int64_t)r * 3 + k) * n + tl.y + lane] = vel[r][k];
+}
+
 // W-list boxes whose multipoles the evaluation uses: flag[C] = 1 for every
 // W-list entry C with more than wd beads (every entry when wd < 0).
 __global__ void k_wbig_flag(List W, Tree t, int wd, int* flag) {
@@ -274,11 +458,31 @@ hipError_t launch_eval(const Launch& l, const EvalPlan& ep, Exp e, double* u) {
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(ks), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)shm_m);
   if (he != hipSuccess) return he;
-  ks<<<dim3(B->nleaf, NRC), SETS_T, shm_l, l.s>>>(p, false, B->leaf_ids, B->tree, e.L, l.tb->rscale, C1, C2, e.DL);
   if (ep.nwbig > 0)
     ks<<<dim3(ep.nwbig, NRC), SETS_T, shm_m, l.s>>>(p, true, ep.wbig, B->tree, e.M, l.tb->rscale, C1, C2, e.DW);
   he = hipGetLastError();
   if (he != hipSuccess) return he;
+  if (ep.mode == EVAL_POLY) {
+    // second approach: component polynomials per leaf (DL's buffer holds them)
+    constexpr int ND = 4 * NRC;
+    const int NM = mono_count(p);
+    double* DP = reinterpret_cast<double*>(e.DL);
+    const size_t shm_c = sizeof(double) * 2 * ncoef(p) * ND, shm_a = sizeof(double) * 4 * NM;
+    auto kc = k_poly_conv<ND>;
+    auto ka = k_poly_assemble<NRC>;
+    he = hipFuncSetAttribute(reinterpret_cast<const void*>(kc), hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_c);
+    if (he == hipSuccess)
+      he = hipFuncSetAttribute(reinterpret_cast<const void*>(ka), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm_a);
+    if (he != hipSuccess) return he;
+    kc<<<B->nleaf, POLY_T, shm_c, l.s>>>(p, B->leaf_ids, B->tree, e.L, ep.kct, e.PV);
+    ka<<<dim3(B->nleaf, NRC), POLY_T, shm_a, l.s>>>(p, B->leaf_ids, B->tree, e.PV, C1, C2, DP);
+    if (ep.tiles.n > 0)
+      k_eval_poly_apply<NRC><<<(ep.tiles.n + EV_WAVES - 1) / EV_WAVES, 64 * EV_WAVES, 0, l.s>>>(
+          p, ep.tiles.t, ep.tiles.n, B->tree, B->lists[LW], ep.widx, B->sx, B->sy, B->sz, B->n, DP, e.DW, C1, u);
+    return hipGetLastError();
+  }
+  ks<<<dim3(B->nleaf, NRC), SETS_T, shm_l, l.s>>>(p, false, B->leaf_ids, B->tree, e.L, l.tb->rscale, C1, C2, e.DL);
   if (ep.tiles.n > 0)
     k_eval_apply<NRC><<<(ep.tiles.n + EV_WAVES - 1) / EV_WAVES, 64 * EV_WAVES, 0, l.s>>>(
         p, ep.tiles.t, ep.tiles.n, B->tree, B->lists[LW], ep.widx, B->sx, B->sy, B->sz,
@@ -288,9 +492,84 @@ hipError_t launch_eval(const Launch& l, const EvalPlan& ep, Exp e, double* u) {
 
 }  // namespace
 
-int make_eval_plan(const Built* B, int p, int wd, EvalPlan* out, hipStream_t s, Error* err) {
+// Monomial coefficients of the regular harmonics R_n^m(u) = r^n P_n^m e^{i m phi}
+// / (n+m)! (0 <= m <= n <= p), generated as polynomials by the recurrence
+//   R_0^0 = 1,  R_m^m = -(u_x + i u_y) R_{m-1}^{m-1} / (2m),  R_{m+1}^m = u_z R_m^m,
+//   R_n^m = ((2n-1) u_z R_{n-1}^m - |u|^2 R_{n-2}^m) / ((n+m)(n-m)),
+// and written, with the factor 2 for m > 0, as the real table
+// KcT[2 (n,m) + 0][j] = f_m Re R_n^m|_j, KcT[2 (n,m) + 1][j] = -f_m Im R_n^m|_j,
+// so that Re(f_m E R_n^m) = sum_q KcT[q][j] e_q for E = e_0 + i e_1.
+static std::vector<double> poly_table(int p) {
+  const int T = ncoef(p), NM = mono_count(p);
+  std::vector<double> re((size_t)T * NM, 0.0), im((size_t)T * NM, 0.0);
+  auto I = [&](int n, int m) { return (size_t)tri(n) + m; };
+  auto J = [&](int a, int b, int c) { return mono_index(p, a, b, c); };
+  // dst (degree n) += w * (u_z^k or |u|^2 or (u_x + i u_y)) * src (degree n-1 or n-2)
+  re[I(0, 0) * NM + J(0, 0, 0)] = 1.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      const double w = -1.0 / (2.0 * m);
+      const size_t s = I(m - 1, m - 1) * NM, d = I(m, m) * NM;
+      for (int a = 0; a <= p; ++a)
+        for (int b = 0; a + b <= p; ++b)
+          for (int c = 0; a + b + c < p; ++c) {
+            const double xr = re[s + J(a, b, c)], xi = im[s + J(a, b, c)];
+            if (xr == 0.0 && xi == 0.0) continue;
+            // (u_x + i u_y)(xr + i xi) = u_x xr - u_y xi + i (u_x xi + u_y xr)
+            re[d + J(a + 1, b, c)] += w * xr;
+            im[d + J(a + 1, b, c)] += w * xi;
+            re[d + J(a, b + 1, c)] -= w * xi;
+            im[d + J(a, b + 1, c)] += w * xr;
+          }
+    }
+    for (int n = m + 1; n <= p; ++n) {
+      const size_t d = I(n, m) * NM, s1 = I(n - 1, m) * NM;
+      const double w1 = n == m + 1 ? 1.0 : (2.0 * n - 1.0) / ((double)(n + m) * (n - m));
+      const double w2 = n == m + 1 ? 0.0 : -1.0 / ((double)(n + m) * (n - m));
+      for (int a = 0; a <= p; ++a)
+        for (int b = 0; a + b <= p; ++b)
+          for (int c = 0; a + b + c < p; ++c) {
+            const double xr = re[s1 + J(a, b, c)], xi = im[s1 + J(a, b, c)];
+            re[d + J(a, b, c + 1)] += w1 * xr;
+            im[d + J(a, b, c + 1)] += w1 * xi;
+          }
+      if (w2 != 0.0) {
+        const size_t s2 = I(n - 2, m) * NM;
+        for (int a = 0; a <= p; ++a)
+          for (int b = 0; a + b <= p; ++b)
+            for (int c = 0; a + b + c + 2 <= p; ++c) {
+              const double xr = re[s2 + J(a, b, c)], xi = im[s2 + J(a, b, c)];
+              const int e[3][3] = {{a + 2, b, c}, {a, b + 2, c}, {a, b, c + 2}};
+              for (const auto& q : e) {
+                re[d + J(q[0], q[1], q[2])] += w2 * xr;
+                im[d + J(q[0], q[1], q[2])] += w2 * xi;
+              }
+            }
+      }
+    }
+  }
+  std::vector<double> kct((size_t)2 * T * NM);
+  for (int n = 0; n <= p; ++n)
+    for (int m = 0; m <= n; ++m) {
+      const double f = m ? 2.0 : 1.0;
+      for (int j = 0; j < NM; ++j) {
+        kct[(2 * I(n, m)) * NM + j] = f * re[I(n, m) * NM + j];
+        kct[(2 * I(n, m) + 1) * NM + j] = -f * im[I(n, m) * NM + j];
+      }
+    }
+  return kct;
+}
+
+int make_eval_plan(const Built* B, int p, int wd, int mode, EvalPlan* out, hipStream_t s, Error* err) {
   out->nwbig = 0;
   out->widx = out->wbig = nullptr;
+  out->kct = nullptr;
+  out->mode = mode;
+  if (mode == EVAL_POLY) {
+    const std::vector<double> k = poly_table(p);
+    RPY_HIP(hipMalloc(&out->kct, sizeof(double) * k.size()));
+    RPY_HIP(hipMemcpy(out->kct, k.data(), sizeof(double) * k.size(), hipMemcpyHostToDevice));
+  }
   if (make_tiles(B, 64, &out->tiles, s, err) != 0) return -1;
   const int nbox = std::max(B->tree.nbox, 1);
   int *flag = nullptr, *off = nullptr, *tmp = nullptr;
@@ -323,15 +602,24 @@ void free_eval_plan(EvalPlan* ep) {
   if (ep->tiles.box) (void)hipFree(ep->tiles.box);
   if (ep->widx) (void)hipFree(ep->widx);
   if (ep->wbig) (void)hipFree(ep->wbig);
+  if (ep->kct) (void)hipFree(ep->kct);
   ep->tiles = Tiles{};
   ep->widx = ep->wbig = nullptr;
+  ep->kct = nullptr;
   ep->nwbig = 0;
 }
 
-int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int64_t* dw_bytes) {
+int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int64_t* dw_bytes, int64_t* pv_bytes) {
   const int64_t per = (int64_t)sizeof(double2) * 12 * nrc;
+  const int64_t nleaf = std::max(B->nleaf, 1);
   *dw_bytes = per * ncoef(p + 2) * std::max(ep.nwbig, 1);
-  return per * ncoef(p) * std::max(B->nleaf, 1);
+  if (ep.mode == EVAL_POLY) {
+    // component polynomials (in DL's buffer) and the density polynomials
+    *pv_bytes = (int64_t)sizeof(double) * 4 * nrc * mono_count(p) * nleaf;
+    return (int64_t)sizeof(double) * 3 * nrc * mono_count(p) * nleaf;
+  }
+  *pv_bytes = sizeof(double);
+  return per * ncoef(p) * nleaf;
 }
 
 hipError_t run_eval(const Launch& l, const EvalPlan& ep, int nrc, Exp e, double* u) {

@@ -21,6 +21,7 @@ struct Exp {
   double2* DL;  // evaluation sets of the leaves' local expansions (eval.hip)
   double2* DW;  // evaluation sets of the W-list multipoles that are evaluated
   double2* XP;  // S->L partial sums of split boxes [Built::nxshared][4 nrc][T]
+  double* PV;   // EVAL_POLY: monomial coefficients of the leaves' local expansions
 };
 
 // Per wave and pass of the S->M / S->L kernels (p2e.hip): bit k of `start`
@@ -126,17 +127,26 @@ hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const doubl
 // (.w = leaf ordinal); widx[box] = row of the box's evaluation sets among
 // the nwbig W-list multipoles that are evaluated (wbig lists those boxes),
 // -1 for the others.
+// Evaluation of the leaves' local expansions at the targets (Sec. 2 names
+// two approaches): EVAL_SETS differentiates each Laplace expansion in
+// coefficient space (12 harmonic sets per leaf and right-hand side) and
+// combines the sums at each target; EVAL_POLY pre-assembles each velocity
+// component into one polynomial per leaf and evaluates it (orders <= 21).
+enum { EVAL_SETS = 1, EVAL_POLY = 2 };
+constexpr int EVAL_POLY_MAX_ORDER = 21;
 struct EvalPlan {
   Tiles tiles{};
   int* widx = nullptr;
   int* wbig = nullptr;
   int nwbig = 0;
+  int mode = EVAL_SETS;
+  double* kct = nullptr;  // EVAL_POLY: monomial table of the regular harmonics
 };
-int make_eval_plan(const Built* B, int p, int wd, EvalPlan* out, hipStream_t s, Error* err);
+int make_eval_plan(const Built* B, int p, int wd, int mode, EvalPlan* out, hipStream_t s, Error* err);
 void free_eval_plan(EvalPlan* ep);
 // Bytes of the evaluation-set arrays for nrc right-hand sides: returns the
 // leaves' (Exp::DL), stores the W multipoles' (Exp::DW) in *dw_bytes.
-int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int64_t* dw_bytes);
+int64_t eval_sets_bytes(const Built* B, const EvalPlan& ep, int p, int nrc, int64_t* dw_bytes, int64_t* pv_bytes);
 // Writes the far-field velocities of every bead (assigns; sorted SoA).
 hipError_t run_eval(const Launch& l, const EvalPlan& ep, int nrc, Exp e, double* u);
 

@@ -10,8 +10,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <map>
-#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -208,8 +206,10 @@ namespace {
 // order alone, so each order is computed once per process (12 ms of host
 // work at p = 16, 32 ms at p = 21, 87 ms at p = 27) and every later plan
 // only uploads it.  The cache holds at most one entry per order (0..27;
-// 6 MB at p = 16 and 17 MB at p = 27, mostly the dense M2L kernels) and is
-// released at process exit.
+// 6 MB at p = 16 and 17 MB at p = 27, mostly the dense M2L kernels).
+// Entries are never freed: the cache is a fixed array of plain pointers, so
+// the library has no static object with a destructor and nothing of it runs
+// during process teardown (the memory returns to the system at exit).
 struct HostTables {
   std::vector<double2> oct, itab;
   std::vector<double> rot, zt, geo, sf, rsc;
@@ -217,7 +217,7 @@ struct HostTables {
   int rlen = 0, zlen = 0;
 };
 std::mutex g_tables_mu;
-std::map<int, std::shared_ptr<const HostTables>> g_tables;
+const HostTables* g_tables[MAX_ORDER + 1];
 
 int compute_tables(int p, HostTables* h, Error* err) {
   const int F1 = (p + 1) * (p + 1), F2 = (2 * p + 1) * (2 * p + 1);
@@ -331,18 +331,27 @@ int compute_tables(int p, HostTables* h, Error* err) {
 int make_tables(int p, Tables* tb, hipStream_t s, Error* err) {
   tb->p = p;
   tb->bytes = 0;
-  std::shared_ptr<const HostTables> hp;
+  if (p < 0 || p > MAX_ORDER) {
+    err->code = -1;
+    err->msg = "expansion order out of range";
+    return -1;
+  }
+  const HostTables* hp = nullptr;
   {
     std::lock_guard<std::mutex> lk(g_tables_mu);
-    auto it = g_tables.find(p);
-    if (it != g_tables.end()) hp = it->second;
+    hp = g_tables[p];
   }
   if (!hp) {
-    auto h = std::make_shared<HostTables>();
-    const int rc = compute_tables(p, h.get(), err);
-    if (rc != 0) return rc;
+    HostTables* h = new HostTables();
+    const int rc = compute_tables(p, h, err);
+    if (rc != 0) {
+      delete h;
+      return rc;
+    }
     std::lock_guard<std::mutex> lk(g_tables_mu);
-    hp = g_tables.emplace(p, std::move(h)).first->second;
+    if (g_tables[p]) delete h;  // another thread filled it meanwhile
+    else g_tables[p] = h;
+    hp = g_tables[p];
   }
   const HostTables& H = *hp;
   const auto &oct = H.oct, &itab = H.itab;

@@ -458,3 +458,51 @@ def test_mixed_precision_accuracy(orc, case):
     log(f"  p={st['order']} mixed vs direct {e_mix:.3e}, fp64 vs direct {e_fp64:.3e}, mixed vs fp64 {e_rel:.3e}")
     assert e_mix <= eps
     assert e_rel <= max(3e-7, 0.5 * eps)
+
+
+# The two evaluation approaches of Sec. 2 (after Theorem 2): derivative sets
+# per Laplace expansion (first) and one pre-assembled polynomial per velocity
+# component and leaf (second), each against the oracle FMM with the same
+# approach and against each other on the same plan.
+@pytest.mark.parametrize("case", [("uniform-p7", 7, 60, False), ("clustered-p12-WXO", 12, 40, True),
+                                  ("large-leaf-p16", 16, 324, True), ("clustered-p21-nrhs4", 21, 200, True)],
+                         ids=lambda c: c[0])
+def test_evaluation_approaches_match_oracle(orc, case):
+    name, p, s, clustered = case
+    if name == "uniform-p7":
+        w = W.uniform_cube(20_000, 2.0, 0.01, nrhs=2, seed=151)
+    elif name == "clustered-p12-WXO":
+        w = W.clustered(20_000, 12, 25.0, 1.0, 0.5, 1, seed=152)
+    elif name == "large-leaf-p16":
+        w = W.clustered(40_000, 20, 30.0, 1.0, 0.5, 1, seed=153)
+    else:
+        w = W.clustered(10_000, 8, 15.0, 0.8, 0.5, 4, seed=154)
+    wd = (p + 1) * (p + 2)
+    log(f"evaluation approaches {name} n={w.n} nrhs={w.nrhs} p={p} s={s}")
+    up, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, eval_mode="poly")
+    us, st2 = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, eval_mode="sets")
+    assert st["eval_mode"] == "poly" and st2["eval_mode"] == "sets"
+    if clustered:
+        assert all(st["list_len"][L] > 0 for L in "WXO")
+    ref2 = orc.fmm(w.pos, w.forces, w.a, w.eta, p, s, wd, eval_mode=1)
+    assert_close(up, ref2, 1e-12, 1e-11, orc, "polynomial evaluation vs oracle (second approach)")
+    assert_close(us, ref2, 1e-12, 1e-11, orc, "set evaluation vs oracle (second approach)")
+    assert_close(up, us, 1e-12, 1e-11, orc, "polynomial vs set evaluation")
+    um, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, eval_mode="poly",
+                       precision="mixed")
+    assert_close(um, up, 3e-7, 1e-5, orc, "mixed vs FP64 (polynomial evaluation)")
+
+
+def test_polynomial_evaluation_limits(orc):
+    import paper_1711_02976_amd as R
+    torch_cuda()
+    w = W.uniform_cube(2000, 1.0, 0.01, seed=155)
+    with pytest.raises(R.RpyError) as ei:
+        R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6, order=24, eval_mode="poly")
+    assert ei.value.status == R.RPY_EUNSUPPORTED
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-3, leaf_size=40)
+    try:
+        st = P.stats()
+        assert st["eval_mode"] == ("poly" if st["order"] <= 10 else "sets")
+    finally:
+        P.free()
