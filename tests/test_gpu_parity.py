@@ -157,9 +157,9 @@ def test_large_leaves_match_oracle_fmm(orc, case):
     _large_ref[name] = ref
     assert_close(u, ref, 1e-12, 1e-11, orc, "FP64 vs oracle FMM")
     # the mixed form on the same plan: FP32 pair sums and M->L against the
-    # FP64 GPU result
+    # FP64 GPU result, within half the accuracy setting (1e-6)
     um, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, precision="mixed")
-    assert_close(um, u, 3e-7, 1e-5, orc, "mixed vs FP64")
+    assert_close(um, u, 5e-7, 1e-5, orc, "mixed vs FP64")
 
 
 def test_fp64_matvec_is_bitwise_reproducible(orc):
@@ -258,7 +258,7 @@ def test_deep_overlap_mixed_against_fp64(orc):
     import paper_1711_02976_amd as R
     log(f"  depth={st['depth']} O={st['list_len']['O']}")
     assert st["list_len"]["O"] > 0
-    assert_close(um, ud, 3e-7, 1e-5, orc, "mixed vs FP64")
+    assert_close(um, ud, 5e-7, 1e-5, orc, "mixed vs FP64")
     ref = orc.fmm(w.pos, w.forces, w.a, w.eta, 12, 40, 182)
     assert_close(ud, ref, 1e-12, 1e-11, orc, "FP64 vs oracle FMM")
 
@@ -490,7 +490,7 @@ def test_evaluation_approaches_match_oracle(orc, case):
     assert_close(up, us, 1e-12, 1e-11, orc, "polynomial vs set evaluation")
     um, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, eval_mode="poly",
                        precision="mixed")
-    assert_close(um, up, 3e-7, 1e-5, orc, "mixed vs FP64 (polynomial evaluation)")
+    assert_close(um, up, 5e-7, 1e-5, orc, "mixed vs FP64 (polynomial evaluation)")
 
 
 def test_polynomial_evaluation_limits(orc):
