@@ -235,14 +235,16 @@ def test_si_units_small_beads(orc, precision, bound, a):
 
 def test_si_units_fmm_matches_oracle_fmm(orc):
     # the same scale through the whole FMM (tree, expansions, overlap list)
+    # (4000 beads in a cube of side 12a: leaves of 8 beads at depth 3 have
+    # side 1.5a < 2a, so non-adjacent leaves can hold overlapping pairs)
     g = np.random.default_rng(18)
     n, a, eta = 4000, 1e-10, 1e-3
-    pos = g.uniform(0.0, 40 * a, size=(n, 3))
+    pos = g.uniform(0.0, 12 * a, size=(n, 3))
     F = g.standard_normal((1, n, 3)) * 1e-12
     log(f"SI units FMM n={n} a={a}")
-    u, st = gpu_matvec(pos, F, a, eta, 1e-6, leaf_size=30, order=10, w_direct=132)
+    u, st = gpu_matvec(pos, F, a, eta, 1e-6, leaf_size=10, order=10, w_direct=132)
     assert st["list_len"]["O"] > 0
-    ref = orc.fmm(pos, F, a, eta, 10, 30, 132)
+    ref = orc.fmm(pos, F, a, eta, 10, 10, 132)
     assert_close(u, ref, 1e-12, 1e-11, orc, "vs oracle FMM")
 
 
