@@ -158,6 +158,25 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
  * stream reaches this call's end. */
 rpy_status rpy_matvec(rpy_plan_t* plan, int32_t nrhs, const double* forces, double* velocities);
 
+/* rpy_matvec for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, result and errors as rpy_matvec, and the same kernels,
+ * but the matvec workspace (expansions, staged forces, partial velocities,
+ * charges, evaluation sets) lives in a fixed device array of 128 MiB that
+ * the library holds on each device from load until the process ends; the
+ * call issues no hipMalloc, hipFree or other allocating routine.
+ *   - The plan's device must be current (RPY_EINVAL otherwise).
+ *   - Right-hand sides per pass are chosen as in rpy_matvec and halved
+ *     until the workspace fits; if one right-hand side per pass does not
+ *     fit (roughly above a few hundred thousand beads at p = 16) the call
+ *     returns RPY_ENOMEM and writes nothing.
+ *   - Every call on a device shares that device's array and leaves its
+ *     contents behind: calls that overlap in time on one device (plans on
+ *     different streams, or different host threads) race and give wrong
+ *     results; order them on one stream or synchronise between them.
+ *   - Per-phase timing (rpy_plan_set_timing) does not record these calls. */
+rpy_status rpy_matvec_noalloc(rpy_plan_t* plan, int32_t nrhs, const double* forces, double* velocities);
+
 /* Brownian displacement vectors (Sec. 1, the Ermak-McCammon step): the
  * random displacements have covariance 2 D dt, so each is sqrt(2 dt) D^{1/2} z
  * for a standard normal z.  This computes y = D^{1/2} z, D the plan's

@@ -66,7 +66,8 @@ class RpyError(RuntimeError):
 
 _lib = None
 
-EXPORTED = ("rpy_default_options", "rpy_plan", "rpy_plan_batched", "rpy_matvec", "rpy_sqrt_matvec", "rpy_plan_stats",
+EXPORTED = ("rpy_default_options", "rpy_plan", "rpy_plan_batched", "rpy_matvec", "rpy_matvec_noalloc",
+            "rpy_sqrt_matvec", "rpy_plan_stats",
             "rpy_plan_export", "rpy_plan_set_timing", "rpy_plan_timings", "rpy_plan_inject_error", "rpy_plan_free",
             "rpy_status_string", "rpy_last_error")
 
@@ -87,6 +88,8 @@ def lib():
         L.rpy_plan_batched.restype = C.c_int
         L.rpy_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
         L.rpy_matvec.restype = C.c_int
+        L.rpy_matvec_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+        L.rpy_matvec_noalloc.restype = C.c_int
         L.rpy_sqrt_matvec.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
                                       C.POINTER(rpy_sqrt_info_t)]
         L.rpy_sqrt_matvec.restype = C.c_int
@@ -156,6 +159,10 @@ def rpy_plan_batched(counts, positions_ptr, a, eta, eps, options=None):
 
 def rpy_matvec(plan, nrhs, forces_ptr, velocities_ptr):
     _check(lib().rpy_matvec(plan, int(nrhs), forces_ptr, velocities_ptr))
+
+
+def rpy_matvec_noalloc(plan, nrhs, forces_ptr, velocities_ptr):
+    _check(lib().rpy_matvec_noalloc(plan, int(nrhs), forces_ptr, velocities_ptr))
 
 
 def rpy_sqrt_matvec(plan, nrhs, z_ptr, y_ptr, tol, max_iter):

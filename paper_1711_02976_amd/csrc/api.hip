@@ -363,6 +363,41 @@ static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const Work& w
   return he;
 }
 
+// ---- fixed workspace of the allocation-free matvec ----------------------
+// rpy_matvec_noalloc runs the matvec with its workspace in this file-scope
+// device array instead of plan-owned allocations.  Each device that loads
+// the library holds its own copy for the life of the process.  Host code
+// never passes the array's name to a kernel: it resolves the device address
+// with hipGetSymbolAddress, once per device, and uses that pointer.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES];  // device address of `scratch`, per device
+
+// Address of `scratch` on the current device (resolved on first use).
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (he != hipSuccess) return he;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+__global__ void k_zero(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
 extern "C" {
 
 void rpy_default_options(rpy_options* opt) {
@@ -606,6 +641,68 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
       return fail(RPY_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(he));
     }
     r0 += c;
+  }
+  return RPY_OK;
+}
+
+rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces, double* velocities) {
+  if (!P) return fail(RPY_EINVAL, "plan is NULL");
+  if (P->sticky) return fail(RPY_EDEVICE, "plan is in an error state from an earlier HIP failure");
+  if (nrhs < 1) return fail(RPY_EINVAL, "nrhs < 1");
+  if (P->B.n == 0) return RPY_OK;
+  if (!forces || !velocities) return fail(RPY_EINVAL, "forces or velocities is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != P->device)
+    return fail(RPY_EINVAL, "the plan's device must be the current device");
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RPY_EUNSUPPORTED, "device ordinal beyond 63");
+  // right-hand sides per pass as in rpy_matvec, halved until the workspace
+  // fits the fixed scratch
+  int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
+  if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;
+  size_t sz[WS_N], tot = 0;
+  for (;;) {
+    ws_sizes(P, nrc, sz);
+    tot = 0;
+    for (int k = 0; k < WS_N; ++k) tot += align256(sz[k]);
+    if (tot <= NOALLOC_SCRATCH_BYTES || nrc == 1) break;
+    nrc /= 2;
+  }
+  if (tot > NOALLOC_SCRATCH_BYTES)
+    return fail(RPY_ENOMEM, "the matvec workspace of this plan (" + std::to_string(tot) +
+                                " bytes for one right-hand side per pass) exceeds the " +
+                                std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte fixed scratch of rpy_matvec_noalloc");
+  void* base = nullptr;
+  hipError_t he = scratch_address(dev, &base);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RPY_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(he));
+  }
+  Work w;
+  {
+    unsigned char* q = static_cast<unsigned char*>(base);
+    void** dst[WS_N] = {(void**)&w.M, (void**)&w.L, (void**)&w.sF, (void**)&w.u, (void**)&w.uf,
+                        (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV};
+    for (int k = 0; k < WS_N; ++k) {
+      *dst[k] = q;
+      q += align256(sz[k]);
+    }
+  }
+  // the 64 charge rows past the last bead are read with zero weight and must
+  // be finite: cleared by a kernel on every call (earlier calls leave other
+  // contents in the scratch)
+  const int64_t pad = (int64_t)64 * 4 * nrc;
+  k_zero<<<(unsigned)((pad + 255) / 256), 256, 0, P->stream>>>(w.Q + P->B.n * 4 * nrc, pad);
+  he = hipGetLastError();
+  rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
+  const int mixed = P->precision == RPY_PREC_MIXED;
+  for (int r0 = 0; he == hipSuccess && r0 < nrhs;) {
+    int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
+    he = matvec_pass(P, l, w, forces, nrhs, r0, c, mixed, velocities, true);
+    r0 += c;
+  }
+  if (he != hipSuccess) {
+    P->sticky = 1;
+    return fail(RPY_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(he));
   }
   return RPY_OK;
 }
