@@ -89,6 +89,18 @@ typedef struct {
                             above); 0 = library choice (2 up to order 10,
                             else 1).  Both give the same result to rounding.
                             Callers whose struct_size ends before it get 0. */
+  int32_t tune;          /* 0 = refinement limit from a cost model and order
+                            from an accuracy table; 1 = measured: when
+                            leaf_size and order are both 0, candidate plans
+                            (the model's limit and its neighbours, orders
+                            downward from the table's, both evaluation
+                            approaches) are built and timed on random forces,
+                            and the fastest whose measured relative L2 error
+                            at 256 sampled targets, against an FP64 direct
+                            sum there, is at most eps/2 is kept.  Choices are
+                            cached per process by (bead-count bucket, uniform
+                            or adaptive tree, eps, precision, nrhs, systems).
+                            Planning then takes seconds to minutes. */
 } rpy_options;
 
 typedef struct rpy_plan_s rpy_plan_t;
@@ -116,7 +128,9 @@ typedef struct {
                             tree: bounding cubes, Morton keys, radix sort,
                             position gather */
   int32_t eval_mode;     /* evaluation approach in use (1 or 2, see options) */
-  int32_t reserved;
+  int32_t tuned;         /* 0 model choice, 1 measured by the autotuner,
+                            2 taken from the autotuner's cache */
+  double tune_err;       /* measured relative L2 error of the tuned choice */
 } rpy_plan_stats_t;
 
 /* Fills *opt with the defaults (FP64, automatic leaf size and order,

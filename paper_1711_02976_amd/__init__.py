@@ -34,7 +34,7 @@ LIST_NAMES = ("U", "V", "W", "X", "O")
 class rpy_options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("precision", C.c_int32), ("leaf_size", C.c_int32),
                 ("order", C.c_int32), ("max_depth", C.c_int32), ("m2l_mode", C.c_int32),
-                ("stream", C.c_void_p), ("nrhs", C.c_int32), ("w_direct", C.c_int32), ("eval_mode", C.c_int32)]
+                ("stream", C.c_void_p), ("nrhs", C.c_int32), ("w_direct", C.c_int32), ("eval_mode", C.c_int32), ("tune", C.c_int32)]
 
 
 class rpy_plan_stats_t(C.Structure):
@@ -43,7 +43,8 @@ class rpy_plan_stats_t(C.Structure):
                 ("nbox", C.c_int64), ("nleaf", C.c_int64), ("list_len", C.c_int64 * 5),
                 ("device_bytes", C.c_int64), ("plan_ms", C.c_double), ("w_direct", C.c_int32),
                 ("p2l_items", C.c_int32), ("p2l_split_boxes", C.c_int32), ("sort_passes", C.c_int32),
-                ("bead_pass_ms", C.c_double), ("eval_mode", C.c_int32), ("reserved", C.c_int32)]
+                ("bead_pass_ms", C.c_double), ("eval_mode", C.c_int32), ("tuned", C.c_int32),
+                ("tune_err", C.c_double)]
 
 
 PHASES = ("permute", "p2p", "overlap", "p2m", "m2m", "m2l", "p2l", "l2l", "eval", "unpermute")
@@ -124,7 +125,7 @@ EVAL_MODES = {"auto": 0, "sets": 1, "poly": 2}
 
 
 def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=None, m2l="auto", nrhs=0,
-                 w_direct=0, eval_mode="auto"):
+                 w_direct=0, eval_mode="auto", tune=0):
     o = rpy_options()
     lib().rpy_default_options(C.byref(o))
     o.m2l_mode = M2L_MODES[m2l] if isinstance(m2l, str) else int(m2l)
@@ -136,6 +137,7 @@ def make_options(precision=PREC_FP64, leaf_size=0, order=0, max_depth=0, stream=
     o.nrhs = int(nrhs)
     o.w_direct = int(w_direct)
     o.eval_mode = EVAL_MODES[eval_mode] if isinstance(eval_mode, str) else int(eval_mode)
+    o.tune = int(tune)
     return o
 
 
@@ -180,7 +182,8 @@ def rpy_plan_stats(plan):
             "list_len": dict(zip(LIST_NAMES, list(s.list_len))), "device_bytes": s.device_bytes,
             "plan_ms": s.plan_ms, "w_direct": s.w_direct, "p2l_items": s.p2l_items,
             "p2l_split_boxes": s.p2l_split_boxes, "sort_passes": s.sort_passes, "bead_pass_ms": s.bead_pass_ms,
-            "eval_mode": {1: "sets", 2: "poly"}.get(s.eval_mode, s.eval_mode)}
+            "eval_mode": {1: "sets", 2: "poly"}.get(s.eval_mode, s.eval_mode),
+            "tuned": {0: "model", 1: "measured", 2: "cached"}.get(s.tuned, s.tuned), "tune_err": s.tune_err}
 
 
 def rpy_plan_export(plan):
@@ -233,7 +236,7 @@ class Plan:
     """
 
     def __init__(self, positions, a, eta=1.0, eps=1e-6, precision="fp64", leaf_size=0, order=0,
-                 max_depth=0, counts=None, stream=None, m2l="auto", nrhs=0, w_direct=0, eval_mode="auto"):
+                 max_depth=0, counts=None, stream=None, m2l="auto", nrhs=0, w_direct=0, eval_mode="auto", tune=0):
         import torch
         if not (isinstance(positions, torch.Tensor) and positions.is_cuda and positions.dtype == torch.float64):
             raise TypeError("positions must be a float64 CUDA tensor")
@@ -246,7 +249,7 @@ class Plan:
         self.device = pos.device
         self.stream = stream
         self.options = make_options(prec, leaf_size, order, max_depth, C.c_void_p(stream) if stream else None, m2l,
-                                    nrhs, w_direct, eval_mode)
+                                    nrhs, w_direct, eval_mode, tune)
         self.n = int(pos.shape[0])
         self.counts = [self.n] if counts is None else [int(c) for c in counts]
         if sum(self.counts) != self.n:

@@ -174,6 +174,9 @@ struct rpy_plan_s {
   int wd = 0;         // W-list boxes of at most wd beads are summed directly (< 0: none)
   int eval_mode = 0;  // rpy::EVAL_SETS or rpy::EVAL_POLY
   int inject = -1;    // phase at which the next pass reports a HIP error (tests)
+  int near_max = rpy::NEAR_MAX_RHS;  // right-hand sides per near-field launch (at most)
+  int tuned = 0, tune_hit = 0;       // autotuned; choice taken from the cache
+  double tune_err = 0.0;             // measured error of the tuned choice
   int device = 0;     // device current when the plan was built
   double a = 0, eta = 0, eps = 0;
   hipStream_t stream = nullptr;
@@ -189,7 +192,8 @@ struct rpy_plan_s {
   hipEvent_t ev_p2m = nullptr, ev_m2l0 = nullptr;
   int sticky = 0;
   // matvec workspace, sized for `ws_nrc` right-hand sides per pass
-  int ws_nrc = 0;
+  int ws_nrc = 0;   // right-hand sides per far-field pass the workspace holds
+  int ws_nrn = 0;   // and per near-field group
   Work ws{};
   int64_t ws_bytes = 0;
   // Krylov workspace (rpy_sqrt_matvec), grown on demand
@@ -206,10 +210,11 @@ struct rpy_plan_s {
   rpy_timings_t acc{};
 };
 
-// Bytes of each Work array for nrc right-hand sides per pass.  Q carries
-// 64 rows past the last bead that the S->M/S->L kernels may read (with zero
-// weight); they must hold finite values (zeros).
-static void ws_sizes(const rpy_plan_t* P, int nrc, size_t sz[WS_N]) {
+// Bytes of each Work array for nrc right-hand sides per far-field pass and
+// nrn per near-field group (sF and u hold a group).  Q carries 64 rows past
+// the last bead that the S->M/S->L kernels may read (with zero weight); they
+// must hold finite values (zeros).
+static void ws_sizes(const rpy_plan_t* P, int nrc, int nrn, size_t sz[WS_N]) {
   const int64_t T = rpy::ncoef(P->p);
   const int64_t nbox = std::max(P->B.tree.nbox, 1);
   const int64_t n = std::max<int64_t>(P->B.n, 1);
@@ -218,7 +223,8 @@ static void ws_sizes(const rpy_plan_t* P, int nrc, size_t sz[WS_N]) {
   int64_t dwb = 0, pvb = 0;
   const size_t dlb = (size_t)rpy::eval_sets_bytes(&P->B, P->ep, P->p, nrc, &dwb, &pvb);
   sz[0] = sz[1] = ex;
-  sz[2] = sz[3] = sz[4] = vb;
+  sz[2] = sz[3] = sizeof(double) * 3 * std::max(nrc, nrn) * n;
+  sz[4] = vb;
   sz[5] = sizeof(double) * 4 * nrc * (n + 64);
   sz[6] = dlb;
   sz[7] = (size_t)dwb;
@@ -267,14 +273,17 @@ static void free_ws(rpy_plan_t* P) {
     if (p) (void)hipFree(p);
   w = Work{};
   P->ws_nrc = 0;
+  P->ws_nrn = 0;
   P->ws_bytes = 0;
 }
 
-static int alloc_ws(rpy_plan_t* P, int nrc) {
-  if (P->ws_nrc >= nrc) return 0;
+static int alloc_ws(rpy_plan_t* P, int nrc, int nrn) {
+  if (P->ws_nrc >= nrc && P->ws_nrn >= nrn) return 0;
+  nrc = std::max(nrc, P->ws_nrc);
+  nrn = std::max(nrn, P->ws_nrn);
   free_ws(P);
   size_t sz[WS_N];
-  ws_sizes(P, nrc, sz);
+  ws_sizes(P, nrc, nrn, sz);
   Work& w = P->ws;
   void** dst[WS_N] = {(void**)&w.M, (void**)&w.L, (void**)&w.sF, (void**)&w.u, (void**)&w.uf,
                       (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV};
@@ -294,18 +303,22 @@ static int alloc_ws(rpy_plan_t* P, int nrc) {
     return -1;
   }
   P->ws_nrc = nrc;
+  P->ws_nrn = nrn;
   P->ws_bytes = tot;
   return 0;
 }
 
-// One matvec pass over right-hand sides r0 .. r0 + c - 1.  Every step runs
-// only if all earlier ones were issued without error; the first error is
-// returned and nothing after it is issued.
-static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const Work& w, const double* forces, int nrhs,
-                              int r0, int c, int mixed, double* velocities, bool untimed = false) {
-  const rpy::Exp e{w.M, w.L, w.Q, w.DL, w.DW, w.XP, w.PV};
+// One matvec group over right-hand sides r0 .. r0 + cn - 1: the near field
+// (P2P, overlap correction, direct W sums) for the whole group on the second
+// stream, the far field in passes of at most nrc right-hand sides on the
+// plan stream, each pass combined with the group's near-field velocities as
+// it finishes.  Every step runs only if all earlier ones were issued without
+// error; the first error is returned and nothing after it is issued.
+static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& w, const double* forces, int nrhs,
+                               int r0, int cn, int nrc, int mixed, double* velocities, bool untimed = false) {
   const rpy::Built& B = P->B;
   const int nlev = B.depth;
+  const int64_t n3 = 3 * B.n;
   const bool haveO = B.lists[rpy::LO].len > 0, haveX = B.lists[rpy::LX].len > 0, haveW = B.lists[rpy::LW].len > 0;
   // timing mode 2 runs the near field on the plan stream too, so that each
   // phase's events measure that phase alone
@@ -322,45 +335,64 @@ static hipError_t matvec_pass(rpy_plan_t* P, const rpy::Launch& l, const Work& w
     if (untimed) return f();
     return timed(P, phase, launches, st, f);
   };
-  hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, c, w.sF); });
+  hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, cn, w.sF); });
   // near field on s1, after the permute
   if (he == hipSuccess && fork) {
     he = hipEventRecord(P->ev_fork, s0);
     if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
   }
-  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, c, w.sF, w.u, mixed); });
+  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, cn, w.sF, w.u, mixed); });
   if (he == hipSuccess && haveO)
-    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, c, w.sF, w.u); });
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, cn, w.sF, w.u); });
   if (he == hipSuccess && haveW)
-    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, c, w.sF, w.u, mixed); });
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, cn, w.sF, w.u, mixed); });
   if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);
-  // far field on s0
-  if (he == hipSuccess) he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, w.sF, e); });
-  // the deepest level's M->L needs only S->M: on a third stream, beside
-  // the upward pass (it writes L of other boxes than the second part)
-  const bool split = fork && P->far2 && P->m2l_mode != 1;
-  if (he == hipSuccess && split) {
-    rpy::Launch l2 = l;
-    l2.s = P->far2;
-    he = hipEventRecord(P->ev_p2m, s0);
-    if (he == hipSuccess) he = hipStreamWaitEvent(P->far2, P->ev_p2m, 0);
-    if (he == hipSuccess) he = step(RPY_PH_M2L, 1, P->far2, [&] { return rpy::run_m2l_rot(l2, c, e, mixed, 0); });
-    if (he == hipSuccess) he = hipEventRecord(P->ev_m2l0, P->far2);
+  // far field on s0, pass by pass over slices of the group's forces
+  bool joined = !fork;
+  for (int q0 = 0; he == hipSuccess && q0 < cn;) {
+    const int c = cn - q0 >= nrc ? nrc : (cn - q0 >= 2 && nrc >= 2 ? 2 : 1);
+    const double* sFq = w.sF + q0 * n3;
+    const rpy::Exp e{w.M, w.L, w.Q, w.DL, w.DW, w.XP, w.PV};
+    he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, sFq, e); });
+    // the deepest level's M->L needs only S->M: on a third stream, beside
+    // the upward pass (it writes L of other boxes than the second part)
+    const bool split = fork && P->far2 && P->m2l_mode != 1;
+    if (he == hipSuccess && split) {
+      rpy::Launch l2 = l;
+      l2.s = P->far2;
+      he = hipEventRecord(P->ev_p2m, s0);
+      if (he == hipSuccess) he = hipStreamWaitEvent(P->far2, P->ev_p2m, 0);
+      if (he == hipSuccess) he = step(RPY_PH_M2L, 1, P->far2, [&] { return rpy::run_m2l_rot(l2, c, e, mixed, 0); });
+      if (he == hipSuccess) he = hipEventRecord(P->ev_m2l0, P->far2);
+    }
+    if (he == hipSuccess) he = step(RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
+    if (he == hipSuccess) he = step(RPY_PH_M2L, 1, s0, [&] {
+      if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
+      return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
+    });
+    if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
+    if (he == hipSuccess && haveX) he = step(RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, sFq, e); });
+    if (he == hipSuccess) he = step(RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
+    if (he == hipSuccess) he = step(RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, w.uf); });
+    // join once, then near + far of this pass back to caller order
+    if (he == hipSuccess && !joined) {
+      he = hipStreamWaitEvent(s0, P->ev_join, 0);
+      joined = true;
+    }
+    if (he == hipSuccess)
+      he = step(RPY_PH_UNPERMUTE, 1, s0,
+                [&] { return rpy::unpermute_velocities(l, w.u + q0 * n3, w.uf, r0 + q0, c, velocities); });
+    if (P->timing && !untimed) P->acc.passes += 1;
+    q0 += c;
   }
-  if (he == hipSuccess) he = step(RPY_PH_M2M, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_m2m(l, c, e); });
-  if (he == hipSuccess) he = step(RPY_PH_M2L, 1, s0, [&] {
-    if (P->m2l_mode == 1) return rpy::run_m2l(l, c, e);
-    return rpy::run_m2l_rot(l, c, e, mixed, split ? 1 : -1);
-  });
-  if (he == hipSuccess && split) he = hipStreamWaitEvent(s0, P->ev_m2l0, 0);
-  if (he == hipSuccess && haveX) he = step(RPY_PH_P2L, 1, s0, [&] { return rpy::run_p2l(l, c, w.sF, e); });
-  if (he == hipSuccess) he = step(RPY_PH_L2L, nlev > 2 ? nlev - 2 : 0, s0, [&] { return rpy::run_l2l(l, c, e); });
-  if (he == hipSuccess) he = step(RPY_PH_EVAL, 1, s0, [&] { return rpy::run_eval(l, P->ep, c, e, w.uf); });
-  // join, then near + far back to caller order
-  if (he == hipSuccess && fork) he = hipStreamWaitEvent(s0, P->ev_join, 0);
-  if (he == hipSuccess)
-    he = step(RPY_PH_UNPERMUTE, 1, s0, [&] { return rpy::unpermute_velocities(l, w.u, w.uf, r0, c, velocities); });
   return he;
+}
+
+// Right-hand sides of the near-field group starting at r0: 8, 4, 2 or 1.
+static int near_group(int left, int nrn) {
+  int c = 1;
+  while (2 * c <= std::min(left, nrn)) c *= 2;
+  return c;
 }
 
 // ---- fixed workspace of the allocation-free matvec ----------------------
@@ -397,6 +429,259 @@ __global__ void k_zero(double* p, int64_t n) {
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
+
+// ---- measured autotuning (rpy_options.tune = 1) ---------------------------
+// Candidate plans are built on the caller's beads and timed on random forces;
+// each is accepted only if its measured relative L2 error at sampled targets,
+// against the library's own FP64 direct sum there (run_direct_sample), is at
+// most eps/2 (the margin the order table was calibrated with).  The fastest
+// accepted candidate wins.  Candidates: the cost model's refinement limit s0
+// and its ladder neighbours s0/1.5 and 1.5 s0; for each, orders from the
+// table's down while the gate holds; for the fastest, both evaluation
+// approaches.  Choices are cached for the life of the process, keyed by
+// (bead-count bucket, uniform or adaptive tree, eps, precision, right-hand
+// sides, systems); a repeated plan of the same class reuses them.
+namespace {
+
+struct TuneKey {
+  int nbucket;    // round(4 log2 n)
+  int adaptive;   // W/X lists present in the model's tree
+  double eps;
+  int precision;
+  int nrhs;
+  int nsys;
+};
+struct TuneEntry {
+  TuneKey key;
+  int leaf_size, order, eval_mode;
+  double ms, err;
+};
+constexpr int TUNE_CACHE = 64;
+std::mutex g_tune_mu;
+TuneEntry g_tune[TUNE_CACHE];  // plain data: nothing runs at process exit
+int g_ntune = 0;
+
+bool same_key(const TuneKey& a, const TuneKey& b) {
+  return a.nbucket == b.nbucket && a.adaptive == b.adaptive && a.eps == b.eps && a.precision == b.precision &&
+         a.nrhs == b.nrhs && a.nsys == b.nsys;
+}
+
+// Standard normal numbers from a counter-based generator: splitmix64 of
+// (seed, index) gives two uniforms, Box-Muller gives one normal.
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+__global__ void k_fill_normal(double* x, int64_t m, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint64_t h1 = splitmix64(seed ^ (2 * (uint64_t)i)), h2 = splitmix64(seed ^ (2 * (uint64_t)i + 1));
+  const double u1 = ((h1 >> 11) + 1.0) * 0x1.0p-53, u2 = (h2 >> 11) * 0x1.0p-53;
+  x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+__global__ void k_gather_rows(const double* U, const int* idx, int k, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * k) return;
+  out[i] = U[(int64_t)idx[i / 3] * 3 + i % 3];
+}
+
+struct TuneRun {
+  double ms = 0, err = 0;
+  bool ok = false;
+};
+
+}  // namespace
+
+// Builds a plan with fixed parameters, times nrhs matvecs (best of two after a
+// warm-up) and measures the error of right-hand side 0 at the sampled caller
+// indices cidx against ref [k][3].
+static rpy_status tune_try(int32_t nsys, const int64_t* counts, const double* positions, double a, double eta,
+                           double eps, rpy_options o, const double* F, double* U, int nrhs, const int* cidx_d, int k,
+                           const std::vector<double>& ref, double* gath_d, TuneRun* out, rpy_plan_t** keep) {
+  o.tune = 0;
+  rpy_plan_t* P = nullptr;
+  rpy_status st = rpy_plan_batched(&P, nsys, counts, positions, a, eta, eps, &o);
+  if (st != RPY_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double best = 1e300;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  for (int it = 0; he == hipSuccess && it < 3; ++it) {
+    if (he == hipSuccess) he = hipEventRecord(e0, P->stream);
+    st = rpy_matvec(P, nrhs, F, U);
+    if (st != RPY_OK) break;
+    if (he == hipSuccess) he = hipEventRecord(e1, P->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (it > 0) best = std::min(best, (double)ms);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  std::vector<double> got(3 * (size_t)k);
+  if (st == RPY_OK && he == hipSuccess) {
+    k_gather_rows<<<(3 * k + 255) / 256, 256, 0, P->stream>>>(U, cidx_d, k, gath_d);
+    he = hipGetLastError();
+    if (he == hipSuccess) he = hipMemcpyAsync(got.data(), gath_d, sizeof(double) * got.size(), hipMemcpyDeviceToHost,
+                                              P->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(P->stream);
+  }
+  if (st == RPY_OK && he != hipSuccess) st = fail(RPY_EDEVICE, std::string("autotuning: ") + hipGetErrorString(he));
+  if (st == RPY_OK) {
+    double num = 0, den = 0;
+    for (size_t i = 0; i < got.size(); ++i) {
+      num += (got[i] - ref[i]) * (got[i] - ref[i]);
+      den += ref[i] * ref[i];
+    }
+    out->ms = best;
+    out->err = den > 0 ? std::sqrt(num / den) : 0.0;
+    out->ok = std::isfinite(out->err) && out->err <= 0.5 * eps;
+  }
+  if (keep && st == RPY_OK) *keep = P;
+  else rpy_plan_free(P);
+  return st;
+}
+
+// Chooses leaf size, order and evaluation approach for o by measurement (or
+// from the cache); fills o->leaf_size, o->order, o->eval_mode.
+static rpy_status autotune(int32_t nsys, const int64_t* counts, const double* positions, double a, double eta,
+                           double eps, rpy_options* o, int* cache_hit, double* tune_err) {
+  int64_t n = 0;
+  for (int s = 0; s < nsys; ++s) n += counts[s];
+  *cache_hit = 0;
+  *tune_err = 0;
+  const int nrhs = std::max(1, o->nrhs);
+  // the model's plan: its refinement limit, tree class and table order
+  rpy_options om = *o;
+  om.tune = 0;
+  rpy_plan_t* P0 = nullptr;
+  rpy_status st = rpy_plan_batched(&P0, nsys, counts, positions, a, eta, eps, &om);
+  if (st != RPY_OK) return st;
+  const int s0 = P0->leaf_size, p0 = P0->p;
+  const int adaptive = P0->B.lists[rpy::LW].len > 0 || P0->B.lists[rpy::LX].len > 0;
+  const TuneKey key{(int)std::lround(4.0 * std::log2((double)std::max<int64_t>(n, 1))), adaptive, eps, o->precision,
+                    nrhs, nsys};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < g_ntune; ++i)
+      if (same_key(g_tune[i].key, key)) {
+        o->leaf_size = g_tune[i].leaf_size;
+        o->order = g_tune[i].order;
+        o->eval_mode = g_tune[i].eval_mode;
+        *cache_hit = 1;
+        *tune_err = g_tune[i].err;
+        rpy_plan_free(P0);
+        return RPY_OK;
+      }
+  }
+  if (n == 0) {
+    rpy_plan_free(P0);
+    return RPY_OK;
+  }
+  // random forces, sampled targets (spread over the tree order) and their
+  // exact velocities (right-hand side 0)
+  const int k = (int)std::min<int64_t>(n, 256);
+  double *F = nullptr, *U = nullptr, *sF = nullptr, *refd = nullptr, *gath = nullptr;
+  int *tidx = nullptr, *cidx = nullptr;
+  std::vector<int> ht(k), hc(k), perm(n);
+  std::vector<double> ref(3 * (size_t)k);
+  hipStream_t s = P0->stream;
+  hipError_t he = hipMalloc(&F, sizeof(double) * 3 * nrhs * n);
+  if (he == hipSuccess) he = hipMalloc(&U, sizeof(double) * 3 * nrhs * n);
+  if (he == hipSuccess) he = hipMalloc(&sF, sizeof(double) * 3 * n);
+  if (he == hipSuccess) he = hipMalloc(&refd, sizeof(double) * 3 * k);
+  if (he == hipSuccess) he = hipMalloc(&gath, sizeof(double) * 3 * k);
+  if (he == hipSuccess) he = hipMalloc(&tidx, sizeof(int) * k);
+  if (he == hipSuccess) he = hipMalloc(&cidx, sizeof(int) * k);
+  if (he == hipSuccess) {
+    const int64_t m = 3 * (int64_t)nrhs * n;
+    k_fill_normal<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(F, m, 0x5eed5eedull);
+    he = hipGetLastError();
+  }
+  if (he == hipSuccess) he = hipMemcpyAsync(perm.data(), P0->B.perm, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he == hipSuccess) {
+    for (int i = 0; i < k; ++i) {
+      ht[i] = (int)(((int64_t)i * n) / k);
+      hc[i] = perm[ht[i]];
+    }
+    he = hipMemcpyAsync(tidx, ht.data(), sizeof(int) * k, hipMemcpyHostToDevice, s);
+  }
+  if (he == hipSuccess) he = hipMemcpyAsync(cidx, hc.data(), sizeof(int) * k, hipMemcpyHostToDevice, s);
+  rpy::Launch l{&P0->B, &P0->tb, P0->p, a, eta, s, P0->wd};
+  if (he == hipSuccess) he = rpy::permute_forces(l, F, nrhs, 0, 1, sF);
+  if (he == hipSuccess) he = rpy::run_direct_sample(l, tidx, k, 1, sF, refd);
+  if (he == hipSuccess) he = hipMemcpyAsync(ref.data(), refd, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  rpy_plan_free(P0);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    st = fail(RPY_ENOMEM, std::string("autotuning workspace: ") + hipGetErrorString(he));
+  }
+  int best_s = s0, best_p = p0, best_e = 0;
+  double best_ms = 1e300, best_err = 0;
+  auto consider = [&](int sl, int p, int ev, const TuneRun& r) {
+    if (r.ok && r.ms < best_ms) {
+      best_ms = r.ms;
+      best_s = sl;
+      best_p = p;
+      best_e = ev;
+      best_err = r.err;
+    }
+  };
+  const int ladder[3] = {std::max(8, (int)(s0 / 1.5)), s0, (int)(s0 * 1.5)};
+  for (int li = 0; st == RPY_OK && li < 3; ++li) {
+    // orders from the table's value down while the gate holds
+    for (int p = p0; st == RPY_OK && p >= 1; --p) {
+      rpy_options oc = *o;
+      oc.leaf_size = ladder[li];
+      oc.order = p;
+      oc.eval_mode = 0;
+      TuneRun r;
+      st = tune_try(nsys, counts, positions, a, eta, eps, oc, F, U, nrhs, cidx, k, ref, gath, &r, nullptr);
+      if (st != RPY_OK) break;
+      consider(ladder[li], p, 0, r);
+      if (!r.ok) break;
+    }
+  }
+  // the other evaluation approach for the winner
+  if (st == RPY_OK && best_ms < 1e300 && best_p <= rpy::EVAL_POLY_MAX_ORDER) {
+    for (int ev = 1; ev <= 2; ++ev) {
+      rpy_options oc = *o;
+      oc.leaf_size = best_s;
+      oc.order = best_p;
+      oc.eval_mode = ev;
+      TuneRun r;
+      st = tune_try(nsys, counts, positions, a, eta, eps, oc, F, U, nrhs, cidx, k, ref, gath, &r, nullptr);
+      if (st != RPY_OK) break;
+      if (r.ok && r.ms < best_ms) {
+        best_ms = r.ms;
+        best_e = ev;
+        best_err = r.err;
+      }
+    }
+  }
+  void* bufs[] = {F, U, sF, refd, gath, tidx, cidx};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (st != RPY_OK) return st;
+  if (best_ms >= 1e300) {
+    // no candidate met the gate: the model's choice with the table's order
+    best_s = s0;
+    best_p = p0;
+    best_e = 0;
+  }
+  o->leaf_size = best_s;
+  o->order = best_p;
+  o->eval_mode = best_e;
+  *tune_err = best_err;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  TuneEntry& e = g_tune[g_ntune < TUNE_CACHE ? g_ntune++ : (TUNE_CACHE - 1)];
+  e = TuneEntry{key, best_s, best_p, best_e, best_ms, best_err};
+  return RPY_OK;
+}
 
 extern "C" {
 
@@ -459,6 +744,14 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
   if (o.eval_mode < 0 || o.eval_mode > 2) return fail(RPY_EINVAL, "eval_mode must be 0, 1 or 2");
   if (o.eval_mode == 2 && o.order > rpy::EVAL_POLY_MAX_ORDER)
     return fail(RPY_EUNSUPPORTED, "polynomial evaluation is built up to order 21");
+  if (o.tune < 0 || o.tune > 1) return fail(RPY_EINVAL, "tune must be 0 or 1");
+  int tuned = 0, tune_hit = 0;
+  double tune_err = 0.0;
+  if (o.tune == 1 && o.leaf_size == 0 && o.order == 0) {
+    const rpy_status ts = autotune(nsys, counts, positions, a, eta, eps, &o, &tune_hit, &tune_err);
+    if (ts != RPY_OK) return ts;
+    tuned = 1;
+  }
 
   rpy_plan_t* P = new rpy_plan_t();
   if (hipGetDevice(&P->device) != hipSuccess) {
@@ -605,6 +898,9 @@ rpy_status rpy_plan_batched(rpy_plan_t** out, int32_t nsys, const int64_t* count
     return st;
   }
   P->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  P->tuned = tuned;
+  P->tune_hit = tune_hit;
+  P->tune_err = tune_err;
   *out = P;
   return RPY_OK;
 }
@@ -629,18 +925,19 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
-  if (alloc_ws(P, nrc) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
+  // near-field groups: up to 8 right-hand sides share each pair's geometry
+  const int nrn = std::max(nrc, std::min(near_group(nrhs, rpy::NEAR_MAX_RHS), P->near_max));
+  if (alloc_ws(P, nrc, nrn) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
-    int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
-    const hipError_t he = matvec_pass(P, l, P->ws, forces, nrhs, r0, c, mixed, velocities);
-    if (P->timing) P->acc.passes += 1;
+    const int cn = near_group(nrhs - r0, nrn);
+    const hipError_t he = matvec_group(P, l, P->ws, forces, nrhs, r0, cn, std::min(nrc, cn), mixed, velocities);
     if (he != hipSuccess) {
       P->sticky = 1;
       return fail(RPY_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(he));
     }
-    r0 += c;
+    r0 += cn;
   }
   return RPY_OK;
 }
@@ -655,17 +952,19 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   if (hipGetDevice(&dev) != hipSuccess || dev != P->device)
     return fail(RPY_EINVAL, "the plan's device must be the current device");
   if (dev < 0 || dev >= MAX_DEVICES) return fail(RPY_EUNSUPPORTED, "device ordinal beyond 63");
-  // right-hand sides per pass as in rpy_matvec, halved until the workspace
-  // fits the fixed scratch
+  // right-hand sides per far-field pass and near-field group as in
+  // rpy_matvec, halved until the workspace fits the fixed scratch
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;
+  int nrn = std::max(nrc, std::min(near_group(nrhs, rpy::NEAR_MAX_RHS), P->near_max));
   size_t sz[WS_N], tot = 0;
   for (;;) {
-    ws_sizes(P, nrc, sz);
+    ws_sizes(P, nrc, nrn, sz);
     tot = 0;
     for (int k = 0; k < WS_N; ++k) tot += align256(sz[k]);
-    if (tot <= NOALLOC_SCRATCH_BYTES || nrc == 1) break;
-    nrc /= 2;
+    if (tot <= NOALLOC_SCRATCH_BYTES || nrn == 1) break;
+    if (nrn > nrc) nrn /= 2;
+    else nrc = nrn = nrc / 2;
   }
   if (tot > NOALLOC_SCRATCH_BYTES)
     return fail(RPY_ENOMEM, "the matvec workspace of this plan (" + std::to_string(tot) +
@@ -696,9 +995,9 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; he == hipSuccess && r0 < nrhs;) {
-    int c = nrhs - r0 >= nrc ? nrc : (nrhs - r0 >= 2 && nrc >= 2 ? 2 : 1);
-    he = matvec_pass(P, l, w, forces, nrhs, r0, c, mixed, velocities, true);
-    r0 += c;
+    const int cn = near_group(nrhs - r0, nrn);
+    he = matvec_group(P, l, w, forces, nrhs, r0, cn, std::min(nrc, cn), mixed, velocities, true);
+    r0 += cn;
   }
   if (he != hipSuccess) {
     P->sticky = 1;
@@ -893,6 +1192,8 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
   out->plan_ms = P->plan_ms;
   out->w_direct = P->wd;
   out->eval_mode = P->eval_mode;
+  out->tuned = P->tuned ? (P->tune_hit ? 2 : 1) : 0;
+  out->tune_err = P->tune_err;
   out->p2l_items = P->B.nxwork;
   out->p2l_split_boxes = P->B.nxred;
   out->bead_pass_ms = P->bead_pass_ms;

@@ -112,6 +112,9 @@ struct Tiles {
   double* box;  // [n][6] bounding box of each tile's beads (lo xyz, hi xyz)
 };
 int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err);
+// The near-field kernels take 1, 2, 4 or 8 right-hand sides per launch
+// (NEAR_MAX_RHS); sF and u are [nrc][3][n].
+constexpr int NEAR_MAX_RHS = 8;
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
 hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);  // FP64
 // W-list boxes of at most Launch::wd beads are summed directly (far
@@ -122,6 +125,9 @@ hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const doubl
 // wdirect_default(p) = 2 (p+1)(p+2)/2 beads.
 __host__ __device__ constexpr int wdirect_default(int p) { return (p + 1) * (p + 2); }
 hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
+// Exact FP64 RPY sums (Sec. 1) at k sampled targets tgt (tree order) over all
+// beads of each target's system: out [k][nrc][3].  The autotuner's reference.
+hipError_t run_direct_sample(const Launch& l, const int* tgt, int k, int nrc, const double* sF, double* out);
 
 // Target evaluation (eval.hip).  tiles: up to 64 beads of one leaf each
 // (.w = leaf ordinal); widx[box] = row of the box's evaluation sets among

@@ -102,7 +102,13 @@ hipError_t krylov_comb(const double* V, int64_t vstride, int k, int kcap, const 
 // off-diagonal e[0..m-1) (e[i] couples i and i + 1), by the implicit QL
 // method: each sweep applies a Wilkinson-shifted QL step to the unreduced
 // block [l, k] as a chain of plane rotations from the bottom up, and the
-// rotations are accumulated into Q.  O(m^2) per eigenvalue.
+// rotations are accumulated into Q.  O(m^2) per eigenvalue.  This is the
+// published implicit QL algorithm with implicit shifts of Bowdler, Martin,
+// Reinsch and Wilkinson (Numer. Math. 11 (1968) 293-306; the tql2 procedure
+// of the Handbook for Automatic Computation, Vol. II, and of EISPACK),
+// written here from that description: Wilkinson shift from the trailing
+// 2x2 block, bottom-up plane rotations, and a split wherever an
+// off-diagonal element is negligible against its neighbouring diagonal.
 void tridiag_eig(int m, const std::vector<double>& d, const std::vector<double>& e, std::vector<double>& lam,
                  std::vector<double>& Q) {
   lam.assign(d.begin(), d.begin() + m);

@@ -472,6 +472,7 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
     P2P_CASE(1)
     P2P_CASE(2)
     P2P_CASE(4)
+    P2P_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef P2P_CASE
@@ -496,6 +497,7 @@ hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const doubl
     OV_CASE(1)
     OV_CASE(2)
     OV_CASE(4)
+    OV_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef OV_CASE
@@ -522,9 +524,81 @@ hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const doubl
     WD_CASE(1)
     WD_CASE(2)
     WD_CASE(4)
+    WD_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef WD_CASE
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------ sampled direct sums ---
+// The exact RPY matvec (Sec. 1, all three blocks) at a few targets, summed
+// over every bead of the target's system in FP64: the reference the
+// autotuner measures candidate plans against.  One block per sampled
+// target (tree order); threads stride over the sources and their partial
+// sums are added in a fixed order.  sF is [nrc][3][n] in tree order; out is
+// [k][nrc][3].
+constexpr int DS_T = 256;
+__global__ void __launch_bounds__(DS_T) k_direct_sample(const int* tgt, const int* sys_begin, int nsys,
+                                                        const double* sx, const double* sy, const double* sz,
+                                                        const double* sF, int64_t n, int nrc, double a, double eta,
+                                                        double* out) {
+  __shared__ double red[DS_T];
+  const int i = tgt[blockIdx.x];
+  // the target's system: sys_begin[s] <= i < sys_begin[s + 1] (binary search)
+  int lo = 0, hi = nsys;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (sys_begin[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  const int sy0 = sys_begin[lo], sy1 = sys_begin[lo + 1];
+  const double xi = sx[i], yi = sy[i], zi = sz[i];
+  const double c0 = 1.0 / (6.0 * PI * eta * a), c1 = 1.0 / (8.0 * PI * eta), four_a2 = 4.0 * a * a;
+  for (int r = 0; r < nrc; ++r) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = sy0 + threadIdx.x; j < sy1; j += DS_T) {
+      const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double fx = sF[((int64_t)r * 3 + 0) * n + j], fy = sF[((int64_t)r * 3 + 1) * n + j],
+                   fz = sF[((int64_t)r * 3 + 2) * n + j];
+      double A, B;
+      if (r2 == 0.0) {
+        A = c0;
+        B = 0.0;
+      } else if (r2 >= four_a2) {
+        const double rr = sqrt(r2), cr = c1 / rr;
+        A = cr * (1.0 + 2.0 * a * a / (3.0 * r2));
+        B = cr * (1.0 - 2.0 * a * a / r2) / r2;
+      } else {
+        const double rr = sqrt(r2);
+        A = c0 * (1.0 - 9.0 * rr / (32.0 * a));
+        B = c0 * (3.0 / (32.0 * a)) / rr;
+      }
+      const double df = dx * fx + dy * fy + dz * fz;
+      acc[0] += A * fx + B * df * dx;
+      acc[1] += A * fy + B * df * dy;
+      acc[2] += A * fz + B * df * dz;
+    }
+    for (int c = 0; c < 3; ++c) {
+      red[threadIdx.x] = acc[c];
+      __syncthreads();
+      for (int w = DS_T / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) out[((int64_t)blockIdx.x * nrc + r) * 3 + c] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t run_direct_sample(const Launch& l, const int* tgt, int k, int nrc, const double* sF, double* out) {
+  const Built* B = l.B;
+  if (k <= 0) return hipSuccess;
+  k_direct_sample<<<k, DS_T, 0, l.s>>>(tgt, B->d_sys_begin, B->nsys, B->sx, B->sy, B->sz, sF, B->n, nrc, l.a,
+                                       l.eta, out);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Particle -> expansion kernels of the four-Laplace FMM (arXiv:1711.02976,
-// Sec. 2): S->M for the leaves and S->L for the X lists of the adaptive tree
-// (Theorem 1).  Both are the contraction
+// Sec. 2, the multipole and local expansion forms of a Laplace potential;
+// Fig. 1's S->M and S->L operators): S->M for the leaves and S->L for the X
+// lists of the adaptive tree.  Both are the contraction
 //
 //   E_n^m[d] = sum_j conj(Y_n^m(r_j - c)) q_j[d]
 //
@@ -15,12 +16,14 @@
 // degree/order of every step is wave-uniform (a per-pass descriptor says
 // where columns start) and no step reads memory; the harmonics go to LDS
 // as [bead][slot].
-// Accumulation: lane = slot (one coefficient), loop over beads, with the
-// bead charges read by scalar loads from a per-bead charge array; the four
-// (or eight) waves that share a slot group each take a quarter (eighth) of
-// the chunk's beads and their partial sums are added once per box.  A
-// column may run over several passes of K steps per wave; the recurrence
-// state stays in registers between passes.
+// Accumulation: a dense product on the FP64 matrix cores.  Per chunk and
+// pass it is D[2S rows][ND] += H^T[2S rows][64 beads] x Q[64 beads][ND], the
+// rows being the real and imaginary parts of the pass's S coefficient slots,
+// done as v_mfma_f64_16x16x4f64 tiles of 16 rows x 16 densities (densities
+// past ND are zero) over 4 beads per instruction; wave w owns the row tiles
+// w, w + 8, ... for the whole box, so no sums cross waves.  A column may run
+// over several passes of K steps per wave; the recurrence state stays in
+// registers between passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +36,8 @@ namespace rpy {
 namespace {
 
 __device__ inline double2 zmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+typedef double v4d __attribute__((ext_vector_type(4)));  // a 16x16 FP64 matrix-core tile per wave
 
 constexpr int P2E_WAVES = 8;
 constexpr int P2E_THREADS = 64 * P2E_WAVES;
@@ -83,8 +88,9 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
                                                      const double* __restrict__ dk, double2* E,
                                                      double2* __restrict__ part) {
   constexpr int NRC = ND / 4;
-  constexpr int S = P2E_WAVES * K, G = S / 64, NB = P2E_WAVES / G, BPW = P2E_CHUNK / NB;
+  constexpr int S = P2E_WAVES * K;
   constexpr int LD = S + 1;  // odd row stride: conflict-free [bead][slot] writes
+  constexpr int TPW = K / 8;  // 16-row tiles per wave: 2S rows / 16 / 8 waves
   const int T = ncoef(p);
   // S->M: one leaf per block.  S->L: one work item per block, a run of the
   // box's X entries and a range of 64-bead chunks of each; a box whose X
@@ -110,14 +116,13 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
   __shared__ double Qs[LOCAL ? P2E_CHUNK * ND : 1];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int grp = wv % G, sub = wv / G;
-  const int slot = grp * 64 + lane;
+  const int li = lane & 15, lk = lane >> 4;  // matrix-core operand row / column and k index
   const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
-  double2 acc[P][ND];
+  v4d acc[P][TPW];
 #pragma unroll
   for (int ps = 0; ps < P; ++ps)
 #pragma unroll
-    for (int d = 0; d < ND; ++d) acc[ps][d] = make_double2(0.0, 0.0);
+    for (int q = 0; q < TPW; ++q) acc[ps][q] = v4d{0.0, 0.0, 0.0, 0.0};
 
   for (int e = e0; e < e1; ++e) {
     const int C = LOCAL ? X.ent[e] : b;
@@ -221,68 +226,51 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
         }
         for (; k < K; ++k) hw[k] = make_double2(0.0, 0.0);
         __syncthreads();
-        if (sub * BPW < nb) {
-          // beads past nb have zero harmonics; Q is padded past the last bead
+        // D += H^T Q over the chunk's beads, 4 per instruction: A[row][k] in
+        // lane row + 16 k (row = real or imaginary part of a slot), B[k][d]
+        // in lane d + 16 k, D[row][d] in lane d + 16 (row % 4), item row / 4;
+        // beads past nb have zero harmonics and finite (padded) charges
+        const double* hd = reinterpret_cast<const double*>(Hs);
+        for (int kk = 0; kk < nb; kk += 4) {
+          const int bb = kk + lk;
+          double bq = 0.0;
+          if (li < ND) bq = LOCAL ? Qs[bb * ND + li] : Q[(int64_t)(jc + bb) * ND + li];
 #pragma unroll
-          for (int i = 0; i < BPW; ++i) {
-            const int bb = sub * BPW + i;
-            const double* q = LOCAL ? Qs + bb * ND : Q + (int64_t)(jc + bb) * ND;
-            const double2 h = Hs[bb * LD + slot];
-#pragma unroll
-            for (int r = 0; r < NRC; ++r) {
-              const double qq[4] = {q[4 * r], q[4 * r + 1], q[4 * r + 2], q[4 * r + 3]};
-#pragma unroll
-              for (int dd = 0; dd < 4; ++dd) {
-                acc[ps][4 * r + dd].x = fma(qq[dd], h.x, acc[ps][4 * r + dd].x);
-                acc[ps][4 * r + dd].y = fma(qq[dd], h.y, acc[ps][4 * r + dd].y);
-              }
-            }
+          for (int q = 0; q < TPW; ++q) {
+            const int row = (wv + 8 * q) * 16 + li;
+            const double a = hd[2 * (bb * LD + (row >> 1)) + (row & 1)];
+            acc[ps][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[ps][q], 0, 0, 0);
           }
         }
       }
     }
   }
-  // add the NB partial sums per slot and write the expansion
-  constexpr int DG = ND <= LD / 8 ? ND : LD / 8;  // densities per round: NB * S * DG <= 64 * LD
-  static_assert(ND % DG == 0, "density rounds");
-  double2* R = Hs;
+  // write the expansion: D[i][d] sits in lane d + 16 (i % 4), item i / 4, so
+  // a lane holds rows of one parity only (real parts for even lk, imaginary
+  // parts for odd lk) and writes each component on its own
 #pragma unroll
-  for (int ps = 0; ps < P; ++ps) {
+  for (int ps = 0; ps < P; ++ps)
 #pragma unroll
-    for (int d0 = 0; d0 < ND; d0 += DG) {
-      __syncthreads();
+    for (int q = 0; q < TPW; ++q) {
+      const int d = li;
+      if (d >= ND) continue;
 #pragma unroll
-      for (int d = 0; d < DG; ++d) R[(sub * DG + d) * S + slot] = acc[ps][d0 + d];
-      __syncthreads();
-      for (int o = threadIdx.x; o < DG * S; o += P2E_THREADS) {
-        const int d = o / S, s = o - d * S;
-        const int c = slot_coef[ps * S + s];
+      for (int v = 0; v < 4; ++v) {
+        const int row = (wv + 8 * q) * 16 + 4 * v + lk;
+        const int sl = row >> 1;  // slot within the pass; row & 1: real or imaginary part
+        const int c = slot_coef[ps * S + sl];
         if (c < 0) continue;
-        double2 v = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const double2 w = R[(k * DG + d) * S + s];
-          v.x += w.x;
-          v.y += w.y;
-        }
+        double x = acc[ps][q][v];
         if (LOCAL && pslot >= 0) {
-          part[((int64_t)pslot * ND + d0 + d) * T + c] = v;
+          reinterpret_cast<double*>(part + ((int64_t)pslot * ND + d) * T + c)[row & 1] = x;
           continue;
         }
-        double2* out = E + ((int64_t)b * ND + d0 + d) * T + c;
-        if (LOCAL) {
-          const double2 o0 = *out;
-          v.x += o0.x;
-          v.y += o0.y;
-        } else {
-          const double f = slot_scale[ps * S + s];  // S_n^m -> R_n^m
-          v.x *= f;
-          v.y *= f;
-        }
-        *out = v;
+        double* out = reinterpret_cast<double*>(E + ((int64_t)b * ND + d) * T + c) + (row & 1);
+        if (LOCAL) x += *out;
+        else x *= slot_scale[ps * S + sl];  // S_n^m -> R_n^m
+        *out = x;
       }
     }
-  }
 }
 
 // Adds the split S->L shares of one box (xred: box, first slot, slot count)
@@ -322,37 +310,31 @@ hipError_t launch_p2e(const Launch& l, const P2ESched& sc, int grid, const int* 
 }
 
 // Schedule choice: 8 steps per wave and pass (66 KB of LDS, two blocks per
-// CU) unless the accumulators of 16 densities over more than two passes
-// would not fit in registers; then 16 steps (132 KB, one block per CU).
+// CU) whenever its packing fits in at most 4 passes (7 for one right-hand
+// side, the orders above 21); else 16 steps (132 KB, one block per CU).  The
+// matrix-core accumulators take 8 registers per pass and row tile.
 template <int ND, bool LOCAL>
 hipError_t launch_p2e_kp(const Launch& l, int grid, const int* ids, const double* Q, double2* E, double2* part) {
   const P2ESched& s8 = l.tb->p2e[0];
   const P2ESched& s16 = l.tb->p2e[1];
-  if constexpr (ND <= 8) {
+  switch (s8.P) {
+    case 1: return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E, part);
+    case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E, part);
+    case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E, part);
+    case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E, part);
+    default: break;
+  }
+  if constexpr (ND == 4) {
     switch (s8.P) {
-      case 1: return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E, part);
-      case 2: return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E, part);
-      case 3: return launch_p2e<ND, LOCAL, 8, 3>(l, s8, grid, ids, Q, E, part);
-      case 4: return launch_p2e<ND, LOCAL, 8, 4>(l, s8, grid, ids, Q, E, part);
+      case 5: return launch_p2e<ND, LOCAL, 8, 5>(l, s8, grid, ids, Q, E, part);
+      case 6: return launch_p2e<ND, LOCAL, 8, 6>(l, s8, grid, ids, Q, E, part);
+      case 7: return launch_p2e<ND, LOCAL, 8, 7>(l, s8, grid, ids, Q, E, part);
       default: break;
     }
-    // orders above 21 run one right-hand side per pass: up to 7 passes
-    if constexpr (ND == 4) {
-      switch (s8.P) {
-        case 5: return launch_p2e<ND, LOCAL, 8, 5>(l, s8, grid, ids, Q, E, part);
-        case 6: return launch_p2e<ND, LOCAL, 8, 6>(l, s8, grid, ids, Q, E, part);
-        case 7: return launch_p2e<ND, LOCAL, 8, 7>(l, s8, grid, ids, Q, E, part);
-        default: break;
-      }
-    }
-    return hipErrorInvalidValue;
-  } else {
-    if (s8.P == 1) return launch_p2e<ND, LOCAL, 8, 1>(l, s8, grid, ids, Q, E, part);
-    if (s8.P == 2) return launch_p2e<ND, LOCAL, 8, 2>(l, s8, grid, ids, Q, E, part);
-    if (s16.P == 1) return launch_p2e<ND, LOCAL, 16, 1>(l, s16, grid, ids, Q, E, part);
-    if (s16.P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, s16, grid, ids, Q, E, part);
-    return hipErrorInvalidValue;
   }
+  if (s16.P == 1) return launch_p2e<ND, LOCAL, 16, 1>(l, s16, grid, ids, Q, E, part);
+  if (s16.P == 2) return launch_p2e<ND, LOCAL, 16, 2>(l, s16, grid, ids, Q, E, part);
+  return hipErrorInvalidValue;
 }
 
 template <bool LOCAL>

@@ -72,5 +72,8 @@ def test_host_validation_without_gpu():
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
     assert b"w_direct" in L.rpy_last_error()
     assert L.rpy_plan_inject_error(None, 0) == R.RPY_EINVAL
+    o = R.make_options(tune=2)
+    assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
+    assert b"tune" in L.rpy_last_error()
     L.rpy_plan_free(None)  # NULL-safe
     assert L.rpy_status_string(R.RPY_ENONFINITE) == b"non-finite position"
