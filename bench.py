@@ -317,10 +317,10 @@ def run(args):
 
 
 PMC_KERNELS = {  # rocprofv3 kernel-name prefix -> (phase, precision form, source file)
-    "rpy::k_p2p<1, true>": ("p2p", "mixed", "nearfield.hip"),
-    "rpy::k_p2p<1, false>": ("p2p", "fp64", "nearfield.hip"),
-    "rpy::k_m2l_rot<4, float": ("m2l", "mixed", "m2l_rot.hip"),
-    "rpy::k_m2l_rot<4, double": ("m2l", "fp64", "m2l_rot.hip"),
+    "rpy::k_p2p<8, true>": ("p2p", "mixed", "nearfield.hip"),
+    "rpy::k_p2p<8, false>": ("p2p", "fp64", "nearfield.hip"),
+    "rpy::k_m2l_rot<16, float": ("m2l", "mixed", "m2l_rot.hip"),
+    "rpy::k_m2l_rot<16, double": ("m2l", "fp64", "m2l_rot.hip"),
 }
 
 

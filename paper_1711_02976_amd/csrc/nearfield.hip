@@ -215,6 +215,16 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
             B[q] = ov ? Bo : B[q];
           }
         }
+        // with several right-hand sides, B d is formed once per pair (3
+        // multiplies) so that each right-hand side costs 9 operations:
+        // t = d.F, u += A F + t (B d)
+        R bdx[4], bdy[4], bdz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bdx[q] = NRC >= 4 ? B[q] * dx[q] : dx[q];
+          bdy[q] = NRC >= 4 ? B[q] * dy[q] : dy[q];
+          bdz[q] = NRC >= 4 ? B[q] * dz[q] : dz[q];
+        }
 #pragma unroll
         for (int r = 0; r < NRC; ++r) {
           const V4 FX = *reinterpret_cast<const V4*>(&fs[3 * r][s0]), FY = *reinterpret_cast<const V4*>(&fs[3 * r + 1][s0]),
@@ -222,10 +232,11 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
           const R fx[4] = {FX.x, FX.y, FX.z, FX.w}, fy[4] = {FY.x, FY.y, FY.z, FY.w}, fz[4] = {FZ.x, FZ.y, FZ.z, FZ.w};
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const R sdf = B[q] * fma(dx[q], fx[q], fma(dy[q], fy[q], dz[q] * fz[q]));
-            ar[r][0] = fma(A[q], fx[q], fma(sdf, dx[q], ar[r][0]));
-            ar[r][1] = fma(A[q], fy[q], fma(sdf, dy[q], ar[r][1]));
-            ar[r][2] = fma(A[q], fz[q], fma(sdf, dz[q], ar[r][2]));
+            const R dF = fma(dx[q], fx[q], fma(dy[q], fy[q], dz[q] * fz[q]));
+            const R t = NRC >= 4 ? dF : B[q] * dF;
+            ar[r][0] = fma(A[q], fx[q], fma(t, bdx[q], ar[r][0]));
+            ar[r][1] = fma(A[q], fy[q], fma(t, bdy[q], ar[r][1]));
+            ar[r][2] = fma(A[q], fz[q], fma(t, bdz[q], ar[r][2]));
           }
         }
       }
