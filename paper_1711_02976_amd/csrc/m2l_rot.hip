@@ -90,17 +90,19 @@ __device__ inline void rot_row(const R* __restrict__ a, const R* xr, const R* xi
 }
 
 // Stores (SR yr + i SI yi) times e (if PH) to col[mp] and advances e by (bx, by).
+// The phase e^{i m a} is advanced by recurrence in the kernel's precision: in
+// FP32 its error grows like m ulp, and it multiplies coefficients of degree
+// n >= m, which the V-list separation makes smaller by a factor of at least
+// 0.43^n than the degree-0 term.
 template <bool PH, int SR, int SI, class R>
-__device__ inline void put_row(typename Cx<R>::T* col, int mp, int ld, R yr, R yi, double& fr, double& fi, double bx,
-                               double by) {
+__device__ inline void put_row(typename Cx<R>::T* col, int mp, int ld, R yr, R yi, R& fr, R& fi, R bx, R by) {
   typename Cx<R>::T o;
   if (SR < 0) yr = -yr;
   if (SI < 0) yi = -yi;
   if (PH) {
-    const R er = (R)fr, ei = (R)fi;
-    o.x = yr * er - yi * ei;
-    o.y = yr * ei + yi * er;
-    const double tr = fr * bx - fi * by;
+    o.x = yr * fr - yi * fi;
+    o.y = yr * fi + yi * fr;
+    const R tr = fr * bx - fi * by;
     fi = fr * by + fi * bx;
     fr = tr;
   } else {
@@ -114,10 +116,10 @@ __device__ inline void put_row(typename Cx<R>::T* col, int mp, int ld, R yr, R y
 // e = (bx, by) when PH (else 1); SR = SI = 1 gives R, SR = (-1)^N and
 // SI = -(-1)^N give the inverse rotation S R S on the same table.
 template <int N, bool PH, int SR, int SI, class R>
-__device__ inline void rot_apply(const R* __restrict__ A, const R* xr, const R* xi, double bx, double by,
+__device__ inline void rot_apply(const R* __restrict__ A, const R* xr, const R* xi, R bx, R by,
                                  typename Cx<R>::T* col, int ld) {
   constexpr int K = N + 1;
-  double fr = 1.0, fi = 0.0;
+  R fr = 1, fi = 0;
 #pragma unroll 1
   for (int mp = 0; mp < K - 1; mp += 2) {
     R yr, yi;
@@ -154,20 +156,19 @@ __device__ void first_half(int c, int ld, const ColData& cd, const R* __restrict
   C* col = X + t0 * ld + c;
   R xr[K], xi[K];
   {
-    const double ax = cd.e1x[c], ay = cd.e1y[c];
-    double er = 1.0, ei = 0.0;
+    const R ax = (R)cd.e1x[c], ay = (R)cd.e1y[c];
+    R er = 1, ei = 0;
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       const C v = col[m * ld];
-      const R fr = (R)er, fi = (R)ei;
-      xr[m] = v.x * fr - v.y * fi;
-      xi[m] = v.x * fi + v.y * fr;
-      const double tr = er * ax - ei * ay;
+      xr[m] = v.x * er - v.y * ei;
+      xi[m] = v.x * ei + v.y * er;
+      const R tr = er * ax - ei * ay;
       ei = er * ay + ei * ax;
       er = tr;
     }
   }
-  rot_apply<N, true, 1, 1, R>(A, xr, xi, cd.e2x[c], cd.e2y[c], col, ld);
+  rot_apply<N, true, 1, 1, R>(A, xr, xi, (R)cd.e2x[c], (R)cd.e2y[c], col, ld);
   load_col<N, R>(col, ld, xr, xi);
   rot_apply<N, false, SG, -SG, R>(A, xr, xi, 0.0, 0.0, col, ld);
 }
@@ -176,19 +177,19 @@ __device__ void first_half(int c, int ld, const ColData& cd, const R* __restrict
 template <int KK, class R>
 __device__ void ztrans(int l, int c, int ld, const ColData& cd, const R* __restrict__ H, typename Cx<R>::T* X) {
   using C = typename Cx<R>::T;
-  const double ri = cd.rinv[c];
-  double s = 1.0;
+  const R ri = (R)cd.rinv[c];
+  R s = 1;
   for (int j = 0; j < l; ++j) s *= ri;
   R vr[KK], vi[KK];
 #pragma unroll
   for (int j = 0; j < KK; ++j) {
     const int n = l + j;
     C v = X[(n * (n + 1) / 2 + l) * ld + c];
-    vr[j] = v.x * (R)s;
-    vi[j] = v.y * (R)s;
+    vr[j] = v.x * s;
+    vi[j] = v.y * s;
     s *= ri;
   }
-  double so = 1.0;
+  R so = 1;
   for (int j = 0; j <= l; ++j) so *= ri;
 #pragma unroll 2
   for (int kk = 0; kk < KK; ++kk) {
@@ -201,8 +202,8 @@ __device__ void ztrans(int l, int c, int ld, const ColData& cd, const R* __restr
     }
     const int k = l + kk;
     C o;
-    o.x = ar * (R)so;
-    o.y = ai * (R)so;
+    o.x = ar * so;
+    o.y = ai * so;
     X[(k * (k + 1) / 2 + l) * ld + c] = o;
     so *= ri;
   }
@@ -217,9 +218,9 @@ __device__ void second_half(int c, int ld, const ColData& cd, const R* __restric
   C* col = X + t0 * ld + c;
   R xr[K], xi[K];
   load_col<N, R>(col, ld, xr, xi);
-  rot_apply<N, true, 1, 1, R>(A, xr, xi, cd.e2x[c], -cd.e2y[c], col, ld);
+  rot_apply<N, true, 1, 1, R>(A, xr, xi, (R)cd.e2x[c], -(R)cd.e2y[c], col, ld);
   load_col<N, R>(col, ld, xr, xi);
-  rot_apply<N, true, SG, -SG, R>(A, xr, xi, cd.e1x[c], -cd.e1y[c], col, ld);
+  rot_apply<N, true, SG, -SG, R>(A, xr, xi, (R)cd.e1x[c], -(R)cd.e1y[c], col, ld);
 }
 
 // Degree (order) cases compiled into a kernel: 0..16, plus 17..21 when the
@@ -233,9 +234,10 @@ __device__ void second_half(int c, int ld, const ColData& cd, const R* __restric
 
 // PM: highest degree compiled in (16, 21 or 27).  MINW: waves per SIMD the
 // register allocation must allow (4 lets two blocks share a CU when their
-// LDS fits).
+// LDS fits).  A block translates ND of the box's nd_all densities, starting
+// at density ND * blockIdx.y.
 template <int ND, class R, int PM, int MINW>
-__global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, List V, RotSched sched,
+__global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, int nd_all, Tree t, List V, RotSched sched,
                                                 const R* __restrict__ rot, const R* __restrict__ zt, int rot_len,
                                                 const double* __restrict__ geo, const double* __restrict__ sf,
                                                 const double2* __restrict__ M, double2* __restrict__ L,
@@ -249,6 +251,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b = bmap[blockIdx.x];
   if (b < 0) return;  // whole block, before any barrier
+  const int d0 = ND * blockIdx.y;
   C* X = reinterpret_cast<C*>(smem);
   ColData cd;
   {
@@ -313,7 +316,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
         const int c = 4 * g, S = cd.src[c];
         C o[4];
         if (S >= 0) {
-          const double2* src = M + ((int64_t)S * ND + (c % ND)) * T + f;
+          const double2* src = M + ((int64_t)S * nd_all + d0 + (c % ND)) * T + f;
           double2 v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) v[k] = src[k * T];
@@ -408,7 +411,7 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, Tree t, Lis
     __syncthreads();
   }
   // paper normalisation -> stored normalisation (times s_k^l)
-  double2* Lb = L + (int64_t)b * ND * T;
+  double2* Lb = L + ((int64_t)b * nd_all + d0) * T;
 #pragma unroll
   for (int r = 0; r < NACC; ++r) {
     const int i = tid + r * RT;
@@ -444,9 +447,11 @@ static size_t rot_smem_bytes(int p, int nc, size_t real) {
   return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * sizeof(double) + sizeof(int));
 }
 
+// ND densities per block, nsplit blocks per target box (nsplit ND densities
+// per box in M and L).
 template <class R, int ND, int PM, int MINW>
 static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const RotSched& sc, const R* rot,
-                            const R* zt, int part) {
+                            const R* zt, int part, int nsplit = 1) {
   const Built* B = l.B;
   auto kern = k_m2l_rot<ND, R, PM, MINW>;
   hipError_t he = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -455,8 +460,10 @@ static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const Ro
   if (!B->m2l_map || B->m2l_part[2] < B->tree.nbox) return hipErrorInvalidValue;
   const int b0 = part == 1 ? B->m2l_part[1] : 0, b1 = part == 0 ? B->m2l_part[1] : B->m2l_part[2];
   if (b1 <= b0) return hipSuccess;
-  kern<<<b1 - b0, RT, shm, l.s>>>(l.p, nc, B->tree, B->lists[LV], sc, rot, zt, l.tb->rot_len, l.tb->geo,
-                                   l.tb->sfac, e.M, e.L, B->m2l_map + b0);
+  // the map runs are whole multiples of 8 blocks, so every density group of
+  // a box lands on the same XCD
+  kern<<<dim3(b1 - b0, nsplit), RT, shm, l.s>>>(l.p, nc, ND * nsplit, B->tree, B->lists[LV], sc, rot, zt,
+                                                 l.tb->rot_len, l.tb->geo, l.tb->sfac, e.M, e.L, B->m2l_map + b0);
   return hipGetLastError();
 }
 
@@ -466,9 +473,10 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
   if (l.B->tree.nbox == 0) return hipSuccess;
   // 64 columns per batch, halved while the LDS (160 KB per CU) cannot hold
-  // them.  Up to degree 16 in FP32 with one right-hand side, 60 columns let
-  // two blocks share a CU (registers are then capped for four waves per SIMD).
-  const bool lo = p <= 16, two = lo && sizeof(R) == 4 && nrc == 1;
+  // them.  Up to degree 16 in FP32, 60 columns let two blocks share a CU
+  // (registers are then capped for four waves per SIMD); each block then
+  // takes the four densities of one right-hand side.
+  const bool lo = p <= 16, two = lo && sizeof(R) == 4;
   int nc = two ? 60 : 64;
   while (nc > 8 && rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc /= 2;
   const size_t shm = rot_smem_bytes(p, nc, sizeof(R));
@@ -476,10 +484,10 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   const RotSched sc = make_sched(p);
   // orders above 21 (the 9-digit setting) run one right-hand side per pass
   if (p > MAX_ORDER_MULTI) return nrc == 1 ? launch_nd<R, 4, 27, 1>(l, e, nc, shm, sc, rot, zt, part) : hipErrorInvalidValue;
+  if constexpr (sizeof(R) == 4)
+    if (two && (nrc == 1 || nrc == 2 || nrc == 4)) return launch_nd<R, 4, 16, 4>(l, e, nc, shm, sc, rot, zt, part, nrc);
   switch (nrc) {
     case 1:
-      if constexpr (sizeof(R) == 4)
-        if (two) return launch_nd<R, 4, 16, 4>(l, e, nc, shm, sc, rot, zt, part);
       return lo ? launch_nd<R, 4, 16, 1>(l, e, nc, shm, sc, rot, zt, part) : launch_nd<R, 4, 21, 1>(l, e, nc, shm, sc, rot, zt, part);
     case 2:
       return lo ? launch_nd<R, 8, 16, 1>(l, e, nc, shm, sc, rot, zt, part) : launch_nd<R, 8, 21, 1>(l, e, nc, shm, sc, rot, zt, part);

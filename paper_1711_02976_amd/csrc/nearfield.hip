@@ -21,6 +21,17 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr int P2P_T = 128;
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Blocks are dealt to the 8 XCDs round-robin (block i to XCD i mod 8), each
+// with its own L2.  Tiles are in leaf (Morton) order, and neighbouring tiles
+// stage mostly the same source leaves, so XCD x takes the x-th contiguous
+// run of tiles (runs differ by at most one tile): block i handles tile
+// x q + min(x, r) + i / 8 with x = i mod 8, q = G / 8, r = G mod 8 for a
+// grid of G blocks, a permutation of 0 .. G - 1.
+__device__ inline int xcd_tile(int i, int G) {
+  const int x = i & 7, q = G >> 3, r = G & 7;
+  return x * q + min(x, r) + (i >> 3);
+}
 }  // namespace
 
 // ---------------------------------------------------------------- tiles ---
@@ -153,7 +164,7 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   __shared__ alignas(32) R ys[P2P_T];
   __shared__ alignas(32) R zs[P2P_T];
   __shared__ alignas(32) R fs[NRC * 3][P2P_T];
-  const int4 tl = tiles[blockIdx.x];
+  const int4 tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
   const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
