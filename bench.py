@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "beads·matvecs/s at 1e-6 rel-L2 vs FP64 direct; mixed/batched vs FP64 FMM"
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak
+PEAK_MFMA_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
+PEAK_MFMA_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {"cube-2k": 1, "cube-1M": 2, "blobs-4M": 3, "batched-64": 4, "cube-15M": 5, "sphere-8M": 6}
@@ -223,11 +225,13 @@ def run(args):
 
     def rates(q, is_mixed):
         """Live rates of one form from the HIP events of the timed region:
-        P2P flop/s against the vector peak of its precision, by the
-        measurement's per-pair count (16 flops of geometry per launch and 12
-        per right-hand side) and by this kernel's own count; M2L flop/s of
-        the rotation operator (20 S flops per V pair and density) against
-        the same peak (no MFMA instruction is issued)."""
+        P2P flop/s by the measurement's per-pair count (16 flops of geometry
+        per launch and 12 per right-hand side), in total, for the launches
+        on the matrix cores (groups of 16 right-hand sides, against the
+        matrix-core peak of the precision) and for those on the vector units
+        (against the vector peak, also by the vector kernel's own count);
+        M2L flop/s of the rotation operator (20 S flops per V pair and
+        density) against the vector peak (no MFMA instruction is issued)."""
         tm = q["timings"]
         steps = max(args.steps, 1)
         L_p2p = tm["launches"]["p2p"] / steps
@@ -237,7 +241,13 @@ def run(args):
         S = (p + 1) * (p + 2) * (2 * p + 3) // 6
         peak = PEAK_FP32_TFLOPS if is_mixed else PEAK_FP64_TFLOPS
         f_p2p = pairs * (16 * L_p2p + 12 * w.nrhs)
-        f_p2p_kernel = pairs * (20 * L_p2p + 18 * w.nrhs)
+        L_mc = tm.get("p2p_mc_launches", 0) / steps
+        t_mc = tm.get("p2p_mc_ms", 0.0) / steps * 1e-3
+        L_vec, t_vec, rhs_vec = L_p2p - L_mc, t_p2p - t_mc, w.nrhs - 16 * L_mc
+        f_mc = pairs * (16 + 12 * 16) * L_mc
+        f_vec = pairs * (16 * L_vec + 12 * rhs_vec)
+        f_p2p_kernel = pairs * (20 * L_vec + 18 * rhs_vec)
+        peak_mc = PEAK_MFMA_FP32_TFLOPS if is_mixed else PEAK_MFMA_FP64_TFLOPS
         t_m2l = tm["ms"]["m2l"] / steps * 1e-3
         f_m2l = npv * 4 * w.nrhs * 20 * S
         out = {"p2p": {"launches_per_matvec": L_p2p, "ms_per_matvec": round(t_p2p * 1e3, 4),
@@ -245,8 +255,20 @@ def run(args):
                        "pairs": pairs, "flops_per_matvec": f_p2p,
                        "achieved_tflops": round(f_p2p / t_p2p / 1e12, 3) if t_p2p > 0 else None,
                        "frac": round(f_p2p / t_p2p / 1e12 / peak, 4) if t_p2p > 0 else None,
-                       "kernel_count_tflops": round(f_p2p_kernel / t_p2p / 1e12, 3) if t_p2p > 0 else None,
                        "peak_tflops": peak},
+               "p2p_mc": {"launches_per_matvec": L_mc, "ms_per_matvec": round(t_mc * 1e3, 4),
+                          "avg_launch_ms": round(t_mc * 1e3 / L_mc, 4) if L_mc else None,
+                          "flops_per_matvec": f_mc,
+                          "achieved_tflops": round(f_mc / t_mc / 1e12, 3) if t_mc > 0 else None,
+                          "frac": round(f_mc / t_mc / 1e12 / peak_mc, 4) if t_mc > 0 else None,
+                          "peak_tflops": peak_mc},
+               "p2p_vec": {"launches_per_matvec": L_vec, "ms_per_matvec": round(t_vec * 1e3, 4),
+                           "avg_launch_ms": round(t_vec * 1e3 / L_vec, 4) if L_vec else None,
+                           "flops_per_matvec": f_vec,
+                           "achieved_tflops": round(f_vec / t_vec / 1e12, 3) if t_vec > 0 else None,
+                           "frac": round(f_vec / t_vec / 1e12 / peak, 4) if t_vec > 0 else None,
+                           "kernel_count_tflops": round(f_p2p_kernel / t_vec / 1e12, 3) if t_vec > 0 else None,
+                           "peak_tflops": peak},
                "m2l": {"ms_per_matvec": round(t_m2l * 1e3, 4), "v_pairs": npv, "flops_per_matvec": f_m2l,
                        "achieved_tflops": round(f_m2l / t_m2l / 1e12, 3) if t_m2l > 0 else None,
                        "frac": round(f_m2l / t_m2l / 1e12 / peak, 4) if t_m2l > 0 else None,
@@ -260,19 +282,28 @@ def run(args):
         return out
 
     rr = rates(r, mixed)
-    dom = max(("p2p", "m2l"), key=lambda k: rr[k]["ms_per_matvec"])
+    # the dominant kernel: P2P on the matrix cores, P2P on the vector units or M->L
+    dom = max(("p2p_mc", "p2p_vec", "m2l"), key=lambda k: rr[k]["ms_per_matvec"])
     d = rr[dom]
-    if dom == "p2p":
+    count = "per ordered pair: 16 flops + 1 rsqrt per launch, 12 flops per right-hand side"
+    if dom == "p2p_mc":
+        launches = max(d["launches_per_matvec"], 1)
+        roof = {"bound": "mfma", "kernel": "k_p2p_mfma", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
+                "unit": "TFLOP/s", "frac": d["frac"],
+                "traffic": traffic_for("nearfield.hip", f"p2p_mc:{args.workload}:{best}"),
+                "avg_launch_ms": d["avg_launch_ms"], "algorithmic_flops_per_launch": d["flops_per_matvec"] / launches,
+                "count": count + " (16 right-hand sides per launch)"}
+    elif dom == "p2p_vec":
         launches = max(d["launches_per_matvec"], 1)
         roof = {"bound": "alu", "kernel": "k_p2p", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
                 "unit": "TFLOP/s", "frac": d["frac"],
                 "traffic": traffic_for("nearfield.hip", f"p2p:{args.workload}:{best}"),
                 "avg_launch_ms": d["avg_launch_ms"], "algorithmic_flops_per_launch": d["flops_per_matvec"] / launches,
-                "count": "per ordered pair: 16 flops + 1 rsqrt per launch, 12 flops per right-hand side",
-                "kernel_count_achieved": d["kernel_count_tflops"]}
+                "count": count, "kernel_count_achieved": d["kernel_count_tflops"]}
     else:
         roof = {"bound": "alu", "kernel": "k_m2l_rot", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
-                "unit": "TFLOP/s", "frac": d["frac"], "traffic": None,
+                "unit": "TFLOP/s", "frac": d["frac"],
+                "traffic": traffic_for("m2l_rot.hip", f"m2l:{args.workload}:{best}"),
                 "algorithmic_flops_per_matvec": d["flops_per_matvec"],
                 "count": "per V pair and density: 20 S flops, S = sum_n (n+1)^2"}
     tm = r["timings"]
@@ -316,11 +347,13 @@ def run(args):
     return 0
 
 
-PMC_KERNELS = {  # rocprofv3 kernel-name prefix -> (phase, precision form, source file)
-    "rpy::k_p2p<8, true>": ("p2p", "mixed", "nearfield.hip"),
-    "rpy::k_p2p<8, false>": ("p2p", "fp64", "nearfield.hip"),
-    "rpy::k_m2l_rot<16, float": ("m2l", "mixed", "m2l_rot.hip"),
-    "rpy::k_m2l_rot<16, double": ("m2l", "fp64", "m2l_rot.hip"),
+PMC_KERNELS = {  # rocprofv3 kernel-name pattern -> (phase, precision form, source file)
+    r"rpy::k_p2p_mfma<true>": ("p2p_mc", "mixed", "nearfield.hip"),
+    r"rpy::k_p2p_mfma<false>": ("p2p_mc", "fp64", "nearfield.hip"),
+    r"rpy::k_p2p<\d+, true>": ("p2p", "mixed", "nearfield.hip"),
+    r"rpy::k_p2p<\d+, false>": ("p2p", "fp64", "nearfield.hip"),
+    r"rpy::k_m2l_rot<\d+, float": ("m2l", "mixed", "m2l_rot.hip"),
+    r"rpy::k_m2l_rot<\d+, double": ("m2l", "fp64", "m2l_rot.hip"),
 }
 
 
@@ -348,8 +381,9 @@ def pmc_summary(args):
     kw = copy_bytes / (1024.0 * mean(cw[("__amd_rocclr_copyBuffer", "WRITE_SIZE")]))
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     rec = json.load(open(path)) if os.path.exists(path) else {}
-    for prefix, (phase, form, src) in PMC_KERNELS.items():
-        names = sorted({k[0] for k in f if k[0].startswith(prefix)})
+    for pat, (phase, form, src) in PMC_KERNELS.items():
+        # the most dispatched kernel of the pattern
+        names = sorted({k[0] for k in f if re.match(pat, k[0])}, key=lambda k: -len(f[(k, "FETCH_SIZE")]))
         if not names:
             continue
         name = names[0]

@@ -268,6 +268,9 @@ typedef struct {
   double ms[RPY_NPHASE];         /* accumulated GPU time per phase (HIP events) */
   int64_t launches[RPY_NPHASE];  /* kernel launches per phase */
   int64_t passes;                /* matvec passes (right-hand-side chunks) timed */
+  double p2p_mc_ms;              /* part of ms[RPY_PH_P2P] spent in P2P launches on the matrix
+                                    cores (near-field groups of 16 right-hand sides) */
+  int64_t p2p_mc_launches;       /* those launches (also counted in launches[RPY_PH_P2P]) */
 } rpy_timings_t;
 
 /* Per-phase timing with HIP events: 0 off, 1 on (phases keep their normal

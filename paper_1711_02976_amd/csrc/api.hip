@@ -244,22 +244,29 @@ static hipEvent_t get_event(rpy_plan_t* P) {
 }
 
 // Runs one phase, bracketed by events on its stream when timing is on.
+// mc: the step is a P2P launch on the matrix cores, also accumulated on its
+// own (events keyed phase + TIMED_MC)
+constexpr int TIMED_MC = 0x100;
 template <class F>
-static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, F&& f) {
+static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, F&& f, bool mc = false) {
   if (!P->timing) return f();
   hipEvent_t a = get_event(P), b = get_event(P);
   if (a) (void)hipEventRecord(a, st);
   hipError_t e = f();
   if (b) (void)hipEventRecord(b, st);
-  if (a && b) P->ev_pending.push_back({phase, {a, b}});
+  if (a && b) P->ev_pending.push_back({phase + (mc ? TIMED_MC : 0), {a, b}});
   P->acc.launches[phase] += launches;
+  if (mc) P->acc.p2p_mc_launches += launches;
   return e;
 }
 
 static void fold_events(rpy_plan_t* P) {
   for (auto& pe : P->ev_pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) P->acc.ms[pe.first] += ms;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      P->acc.ms[pe.first & (TIMED_MC - 1)] += ms;
+      if (pe.first & TIMED_MC) P->acc.p2p_mc_ms += ms;
+    }
     P->ev_pool.push_back(pe.second.first);
     P->ev_pool.push_back(pe.second.second);
   }
@@ -327,13 +334,13 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
   rpy::Launch ln = l;
   ln.s = s1;
   // a phase named by rpy_plan_inject_error reports an error instead of running
-  auto step = [&](int phase, int launches, hipStream_t st, auto&& f) -> hipError_t {
+  auto step = [&](int phase, int launches, hipStream_t st, auto&& f, bool mc = false) -> hipError_t {
     if (P->inject == phase) {
       P->inject = -1;
       return hipErrorLaunchFailure;
     }
     if (untimed) return f();
-    return timed(P, phase, launches, st, f);
+    return timed(P, phase, launches, st, f, mc);
   };
   hipError_t he = step(RPY_PH_PERMUTE, 1, s0, [&] { return rpy::permute_forces(l, forces, nrhs, r0, cn, w.sF); });
   // near field on s1, after the permute
@@ -341,7 +348,9 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
     he = hipEventRecord(P->ev_fork, s0);
     if (he == hipSuccess) he = hipStreamWaitEvent(s1, P->ev_fork, 0);
   }
-  if (he == hipSuccess) he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, cn, w.sF, w.u, mixed); });
+  if (he == hipSuccess)
+    he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, cn, w.sF, w.u, mixed); },
+              cn == rpy::NEAR_MAX_RHS);
   if (he == hipSuccess && haveO)
     he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, cn, w.sF, w.u); });
   if (he == hipSuccess && haveW)
@@ -388,10 +397,13 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
   return he;
 }
 
-// Right-hand sides of the near-field group starting at r0: 8, 4, 2 or 1.
+// Right-hand sides of the near-field group with `left` still to do and
+// groups of at most nrn: 16 (the P2P on the matrix cores), else 8, 4, 2 or 1.
 static int near_group(int left, int nrn) {
+  const int m = std::min(left, nrn);
+  if (m >= rpy::NEAR_MAX_RHS) return rpy::NEAR_MAX_RHS;
   int c = 1;
-  while (2 * c <= std::min(left, nrn)) c *= 2;
+  while (2 * c <= std::min(m, rpy::NEAR_VEC_RHS)) c *= 2;
   return c;
 }
 

@@ -17,6 +17,17 @@ constexpr int STACK = 192;           // private DFS stack of the list kernels
 __host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
 
+// Blocks are dealt to the 8 XCDs round-robin (block i to XCD i mod 8), each
+// with its own L2.  Work items in leaf (Morton) order share most of their
+// inputs with their neighbours, so XCD x takes the x-th contiguous run of
+// items (runs differ by at most one): block i handles item
+// x q + min(x, r) + i / 8 with x = i mod 8, q = G / 8, r = G mod 8 for a
+// grid of G blocks, a permutation of 0 .. G - 1.
+__device__ inline int xcd_run(int i, int G) {
+  const int x = i & 7, q = G >> 3, r = G & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 // Device view of the octree.  Boxes are numbered by (level, system, Morton
 // key); begin/end index the sorted bead order.
 struct Tree {

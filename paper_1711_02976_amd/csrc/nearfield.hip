@@ -22,16 +22,6 @@ constexpr double PI = 3.14159265358979323846;
 constexpr int P2P_T = 128;
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Blocks are dealt to the 8 XCDs round-robin (block i to XCD i mod 8), each
-// with its own L2.  Tiles are in leaf (Morton) order, and neighbouring tiles
-// stage mostly the same source leaves, so XCD x takes the x-th contiguous
-// run of tiles (runs differ by at most one tile): block i handles tile
-// x q + min(x, r) + i / 8 with x = i mod 8, q = G / 8, r = G mod 8 for a
-// grid of G blocks, a permutation of 0 .. G - 1.
-__device__ inline int xcd_tile(int i, int G) {
-  const int x = i & 7, q = G >> 3, r = G & 7;
-  return x * q + min(x, r) + (i >> 3);
-}
 }  // namespace
 
 // ---------------------------------------------------------------- tiles ---
@@ -164,7 +154,7 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   __shared__ alignas(32) R ys[P2P_T];
   __shared__ alignas(32) R zs[P2P_T];
   __shared__ alignas(32) R fs[NRC * 3][P2P_T];
-  const int4 tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+  const int4 tl = tiles[xcd_run(blockIdx.x, gridDim.x)];
   const int b = tl.x;
   const bool valid = (int)threadIdx.x < tl.z;
   const bool wlive = (int)(threadIdx.x & ~63u) < tl.z;  // this wave holds a target of the tile
@@ -258,6 +248,145 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
   if (valid)
     for (int r = 0; r < NRC; ++r)
       for (int c = 0; c < 3; ++c) u[((int64_t)r * 3 + c) * n + i] = c1 * acc[r][c];
+}
+
+// ------------------------------------------- P2P on the matrix cores ----
+// With 16 right-hand sides the P2P of a target tile is a product
+//   U[3 x targets][16] += M[3 x targets][3 x sources] F[3 x sources][16]
+// whose 3x3 blocks M_ij = A_ij I + B_ij d d^T (the RPY block of Sec. 1, with
+// the overlap branch for r < 2a) are formed on the fly.  A wave owns 16
+// targets; per step of 4 sources each lane forms one pair (target lane % 16,
+// source lane / 16) and the six distinct entries of its block, which are
+// exactly the A operands of 16x16x4 matrix-core products in that lane:
+// D_a += M_ab F_b for a, b in {x, y, z}, nine products per step, with F_b
+// (source, right-hand side) as the B operand.  The FP32 form uses
+// v_mfma_f32_16x16x4f32 and adds D into FP64 sums after each staged chunk of
+// sources (as the vector kernel does); the FP64 form uses
+// v_mfma_f64_16x16x4f64 and keeps the sums in D.
+namespace {
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+constexpr int MF_W = 8;         // waves per block: 16 targets each, P2P_T per tile
+constexpr int MF_R = 16;        // right-hand sides per launch (the product's N)
+__device__ inline v4f_t mfma16(float a, float b, v4f_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline v4d_t mfma16(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+// Row (target within the wave's 16) of item v of a 16x16 result in lane l;
+// the column (right-hand side) is l % 16 in both forms.
+__device__ inline int mf_row(float, int l, int v) { return 4 * (l >> 4) + v; }
+__device__ inline int mf_row(double, int l, int v) { return 4 * v + (l >> 4); }
+}  // namespace
+
+template <bool MIXED>
+__global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree t, List U, const double* sx,
+                                                       const double* sy, const double* sz, const double* sF,
+                                                       int64_t n,
+                                                       PairK<typename std::conditional<MIXED, float, double>::type> k,
+                                                       double S, double c1, double* u) {
+  using R = typename std::conditional<MIXED, float, double>::type;
+  using R4 = typename std::conditional<MIXED, float4, double4>::type;
+  using VD = typename std::conditional<MIXED, v4f_t, v4d_t>::type;
+  __shared__ R4 ps[P2P_T];          // positions (x, y, z, -)
+  __shared__ R fs[3][P2P_T][MF_R];  // [component][source][right-hand side]
+  const int4 tl = tiles[xcd_run(blockIdx.x, gridDim.x)];
+  const int b = tl.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int t0 = 16 * __builtin_amdgcn_readfirstlane(tid >> 6);  // the wave's first target in the tile
+  const bool wlive = t0 < tl.z;
+  const int ti = lane & 15, sk = lane >> 4;  // lane's target row and source within a step
+  // rows past the tile take its last target (finite values, never stored)
+  const int i = tl.y + max(0, min(t0 + ti, tl.z - 1));
+  const double ox = t.cx[b], oy = t.cy[b], oz = t.cz[b];
+  const R xi = (R)((sx[i] - ox) * S), yi = (R)((sy[i] - oy) * S), zi = (R)((sz[i] - oz) * S);
+  VD D[3];
+  double acc[3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    D[c] = VD{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[c][v] = 0.0;
+  }
+  const int e0 = __builtin_amdgcn_readfirstlane(U.off[b]), e1 = __builtin_amdgcn_readfirstlane(U.off[b + 1]);
+  for (int e = e0; e < e1; ++e) {
+    const int C = __builtin_amdgcn_readfirstlane(U.ent[e]);
+    const int j1 = __builtin_amdgcn_readfirstlane(t.end[C]);
+    for (int jc = __builtin_amdgcn_readfirstlane(t.begin[C]); jc < j1; jc += P2P_T) {
+      const int ns = min(P2P_T, j1 - jc);
+      // padded to a multiple of 4 sources with inert ones (zero force at 1e30)
+      const int ns4 = (ns + 3) & ~3;
+      __syncthreads();
+      if (tid < ns) {
+        const int j = jc + tid;
+        ps[tid] = R4{(R)((sx[j] - ox) * S), (R)((sy[j] - oy) * S), (R)((sz[j] - oz) * S), (R)0};
+      } else if (tid < ns4) {
+        ps[tid] = R4{(R)1e30, (R)1e30, (R)1e30, (R)0};
+      }
+      // forces: sF row q = 3 r + c, read along the sources (coalesced)
+      for (int q = tid; q < 3 * MF_R * P2P_T; q += 64 * MF_W) {
+        const int row = q / P2P_T, sj = q - row * P2P_T;
+        if (sj < ns4) fs[row % 3][sj][row / 3] = sj < ns ? (R)sF[(int64_t)row * n + jc + sj] : (R)0;
+      }
+      __syncthreads();
+      if (wlive) {
+        R m[6], f[3];
+        for (int s0 = 0; s0 < ns4; s0 += 4) {
+          const int j = s0 + sk;
+          const R4 p = ps[j];
+          {  // the pair block, as in k_p2p: six distinct entries xx, yy, zz, xy, xz, yz
+            const R dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+            const R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, k.r2min)));
+            const R rinv = rinv_of(r2);
+            const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
+            R A = fma(k.a3, ri3, rinv);
+            R B = ri3 * fma(-k.a2, ri2, (R)1);
+            if (__builtin_expect(__any(r2 < k.four_a2), 0)) {
+              const bool ov = r2 < k.four_a2;
+              const R Ao = fma(-k.ock9, (r2 - k.r2min) * rinv, k.oc), Bo = k.ob * rinv;
+              A = ov ? Ao : A;
+              B = ov ? Bo : B;
+            }
+            const R bx = B * dx, by = B * dy, bz = B * dz;
+            m[0] = fma(bx, dx, A);
+            m[1] = fma(by, dy, A);
+            m[2] = fma(bz, dz, A);
+            m[3] = bx * dy;
+            m[4] = bx * dz;
+            m[5] = by * dz;
+          }
+          f[0] = fs[0][j][ti];
+          f[1] = fs[1][j][ti];
+          f[2] = fs[2][j][ti];
+          D[0] = mfma16(m[0], f[0], D[0]);
+          D[1] = mfma16(m[3], f[0], D[1]);
+          D[2] = mfma16(m[4], f[0], D[2]);
+          D[0] = mfma16(m[3], f[1], D[0]);
+          D[1] = mfma16(m[1], f[1], D[1]);
+          D[2] = mfma16(m[5], f[1], D[2]);
+          D[0] = mfma16(m[4], f[2], D[0]);
+          D[1] = mfma16(m[5], f[2], D[1]);
+          D[2] = mfma16(m[2], f[2], D[2]);
+        }
+        if (MIXED) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[c][v] += (double)D[c][v];
+            D[c] = VD{0, 0, 0, 0};
+          }
+        }
+      }
+    }
+  }
+  if (!wlive) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = mf_row(R(0), lane, v);
+      if (t0 + row < tl.z) {
+        const double x = MIXED ? acc[c][v] : (double)D[c][v];
+        u[((int64_t)ti * 3 + c) * n + tl.y + t0 + row] = c1 * x;
+      }
+    }
 }
 
 // ---------------------------------------------------- W list, direct ----
@@ -495,6 +624,14 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
     P2P_CASE(2)
     P2P_CASE(4)
     P2P_CASE(8)
+    case MF_R:
+      if (mixed)
+        k_p2p_mfma<true><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n,
+                                                         q.kf, q.S, q.c1S, u);
+      else
+        k_p2p_mfma<false><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF,
+                                                          B->n, q.kd, q.S, q.c1S, u);
+      break;
     default: return hipErrorInvalidValue;
   }
 #undef P2P_CASE
@@ -508,6 +645,11 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
 hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u) {
   const Built* B = l.B;
   if (tiles.n == 0 || B->lists[LO].len == 0) return hipSuccess;
+  if (nrc > NEAR_VEC_RHS) {  // launches of 8 right-hand sides, then the rest
+    const hipError_t he = run_overlap(l, tiles, NEAR_VEC_RHS, sF, u);
+    const int64_t off = (int64_t)NEAR_VEC_RHS * 3 * B->n;
+    return he != hipSuccess ? he : run_overlap(l, tiles, nrc - NEAR_VEC_RHS, sF + off, u + off);
+  }
   const PairLaunch q = pair_launch(l.a, l.eta);
   const double four_a2 = 4.0 * l.a * l.a;
 #define OV_CASE(NR)                                                                                                 \
@@ -531,6 +673,11 @@ hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const doubl
 hipError_t run_wdirect(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   const Built* B = l.B;
   if (tiles.n == 0 || B->lists[LW].len == 0 || l.wd < 0) return hipSuccess;
+  if (nrc > NEAR_VEC_RHS) {  // launches of 8 right-hand sides, then the rest
+    const hipError_t he = run_wdirect(l, tiles, NEAR_VEC_RHS, sF, u, mixed);
+    const int64_t off = (int64_t)NEAR_VEC_RHS * 3 * B->n;
+    return he != hipSuccess ? he : run_wdirect(l, tiles, nrc - NEAR_VEC_RHS, sF + off, u + off, mixed);
+  }
   const PairLaunch q = pair_launch(l.a, l.eta);
   const int wmax = l.wd;
 #define WD_CASE(NR)                                                                                                 \

@@ -162,6 +162,51 @@ def test_large_leaves_match_oracle_fmm(orc, case):
     assert_close(um, u, 5e-7, 1e-5, orc, "mixed vs FP64")
 
 
+# 16 right-hand sides per near-field group: the P2P runs on the matrix cores
+# (9 16x16x4 products per 4-source step, pair blocks formed per lane); the
+# right-hand sides past 16 form groups of 8, 4, 2 or 1 on the vector units.
+# A single leaf is the direct sum: every tile of 128 targets (the last one
+# ragged, so some waves hold fewer than 16 targets and some none), with self
+# terms and overlapping pairs.
+@pytest.mark.parametrize("nrhs", [16, 20, 24, 26])
+def test_matrix_core_p2p_single_leaf_is_direct(orc, nrhs):
+    w = W.uniform_cube(3000, 1.0, 0.02, nrhs=nrhs, seed=52)
+    log(f"single leaf n=3000 nrhs={nrhs} (matrix-core P2P)")
+    ref = orc.rpy_direct(w.pos, w.forces, w.a, w.eta)
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, leaf_size=10_000)
+    assert st["nleaf"] == 1
+    assert_close(u, ref, 1e-12, 1e-11, orc, "FP64 vs direct")
+    um, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, leaf_size=10_000, precision="mixed")
+    assert_close(um, ref, 1e-6, 1e-5, orc, "mixed vs direct")
+
+
+# The whole FMM with a near-field group of 16 right-hand sides against the
+# oracle FMM: large uniform leaves (20 rhs: groups of 16 and 4), and a
+# clustered set with overlapping pairs outside U, W and X lists and 16 rhs
+# (overlap and direct W sums then run as two launches of 8).
+def _matrix_core_cases():
+    return [
+        ("uniform-s324-p12-nrhs20", W.uniform_cube(12_000, 2.0, 0.01, nrhs=20, seed=115), 12, 324, False),
+        ("clustered-s200-p10-nrhs16", W.clustered(20_000, 20, 30.0, 1.0, 0.5, 16, seed=116), 10, 200, True),
+    ]
+
+
+@pytest.mark.parametrize("case", _matrix_core_cases(), ids=lambda c: c[0])
+def test_matrix_core_p2p_fmm_matches_oracle_fmm(orc, case):
+    name, w, p, s, adaptive = case
+    wd = (p + 1) * (p + 2)
+    log(f"matrix-core P2P parity {name} n={w.n} nrhs={w.nrhs} p={p} s={s}")
+    u, st = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd)
+    L = st["list_len"]
+    log(f"  depth={st['depth']} nleaf={st['nleaf']} lists {L}")
+    if adaptive:
+        assert L["W"] > 0 and L["X"] > 0 and L["O"] > 0
+    ref = orc.fmm(w.pos, w.forces, w.a, w.eta, p, s, wd)
+    assert_close(u, ref, 1e-12, 1e-11, orc, "FP64 vs oracle FMM")
+    um, _ = gpu_matvec(w.pos, w.forces, w.a, w.eta, 1e-6, order=p, leaf_size=s, w_direct=wd, precision="mixed")
+    assert_close(um, u, 5e-7, 1e-5, orc, "mixed vs FP64")
+
+
 def test_fp64_matvec_is_bitwise_reproducible(orc):
     """FP64 matvecs on an adaptive tree with split S->L work are bitwise
     equal from call to call and from plan to plan (the split shares are
@@ -308,6 +353,25 @@ def test_multi_rhs_equals_separate_calls(orc):
         for r in range(11):
             ur = P.matvec(F[r]).cpu().numpy()
             assert orc.rel_l2(ur, U[r]) <= 1e-14
+        torch.cuda.synchronize()
+    finally:
+        P.free()
+
+
+def test_twenty_rhs_equal_separate_calls(orc):
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    # 20 right-hand sides: near-field groups of 16 (matrix cores) and 4;
+    # single calls run the vector kernels, so the sums differ in order only
+    w = W.uniform_cube(4000, 1.0, 0.01, nrhs=20, seed=82)
+    log("nrhs=20 vs 20 single calls")
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6, leaf_size=40)
+    try:
+        F = to_dev(w.forces)
+        U = P.matvec(F).cpu().numpy()
+        for r in range(20):
+            ur = P.matvec(F[r]).cpu().numpy()
+            assert orc.rel_l2(ur, U[r]) <= 1e-13
         torch.cuda.synchronize()
     finally:
         P.free()
