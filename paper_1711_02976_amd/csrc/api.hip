@@ -162,8 +162,9 @@ struct Work {
   double2* DW = nullptr;  // evaluation sets (evaluated W-list multipoles)
   double2* XP = nullptr;  // S->L partial sums of boxes split over several work items
   double* PV = nullptr;   // polynomial evaluation: the leaves' density polynomials
+  float2* M32 = nullptr;  // mixed form: multipoles as the FP32 M->L reads them
 };
-constexpr int WS_N = 10;  // arrays of Work, in the order above
+constexpr int WS_N = 11;  // arrays of Work, in the order above
 
 struct rpy_plan_s {
   rpy::Built B;
@@ -230,6 +231,7 @@ static void ws_sizes(const rpy_plan_t* P, int nrc, int nrn, size_t sz[WS_N]) {
   sz[7] = (size_t)dwb;
   sz[8] = sizeof(double2) * std::max<int64_t>(P->B.nxshared, 1) * 4 * nrc * T;
   sz[9] = (size_t)pvb;
+  sz[10] = P->precision == RPY_PREC_MIXED ? sizeof(float2) * nbox * 4 * nrc * T : 256;
 }
 
 static hipEvent_t get_event(rpy_plan_t* P) {
@@ -275,7 +277,7 @@ static void fold_events(rpy_plan_t* P) {
 
 static void free_ws(rpy_plan_t* P) {
   Work& w = P->ws;
-  void* ps[] = {w.M, w.L, w.sF, w.u, w.uf, w.Q, w.DL, w.DW, w.XP, w.PV};
+  void* ps[] = {w.M, w.L, w.sF, w.u, w.uf, w.Q, w.DL, w.DW, w.XP, w.PV, w.M32};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   w = Work{};
@@ -293,7 +295,8 @@ static int alloc_ws(rpy_plan_t* P, int nrc, int nrn) {
   ws_sizes(P, nrc, nrn, sz);
   Work& w = P->ws;
   void** dst[WS_N] = {(void**)&w.M, (void**)&w.L, (void**)&w.sF, (void**)&w.u, (void**)&w.uf,
-                      (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV};
+                      (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV,
+                      (void**)&w.M32};
   int64_t tot = 0;
   for (int k = 0; k < WS_N; ++k) {
     if (hipMalloc(dst[k], sz[k]) != hipSuccess) {
@@ -361,7 +364,7 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
   for (int q0 = 0; he == hipSuccess && q0 < cn;) {
     const int c = cn - q0 >= nrc ? nrc : (cn - q0 >= 2 && nrc >= 2 ? 2 : 1);
     const double* sFq = w.sF + q0 * n3;
-    const rpy::Exp e{w.M, w.L, w.Q, w.DL, w.DW, w.XP, w.PV};
+    const rpy::Exp e{w.M, w.L, w.Q, w.DL, w.DW, w.XP, w.PV, w.M32};
     he = step(RPY_PH_P2M, 1, s0, [&] { return rpy::run_p2m(l, c, sFq, e); });
     // the deepest level's M->L needs only S->M: on a third stream, beside
     // the upward pass (it writes L of other boxes than the second part)
@@ -992,7 +995,8 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   {
     unsigned char* q = static_cast<unsigned char*>(base);
     void** dst[WS_N] = {(void**)&w.M, (void**)&w.L, (void**)&w.sF, (void**)&w.u, (void**)&w.uf,
-                        (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV};
+                        (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV,
+                        (void**)&w.M32};
     for (int k = 0; k < WS_N; ++k) {
       *dst[k] = q;
       q += align256(sz[k]);

@@ -22,6 +22,7 @@ struct Exp {
   double2* DW;  // evaluation sets of the W-list multipoles that are evaluated
   double2* XP;  // S->L partial sums of split boxes [Built::nxshared][4 nrc][T]
   double* PV;   // EVAL_POLY: monomial coefficients of the leaves' local expansions
+  float2* M32;  // FP32 M->L: multipoles in the paper's normalisation, [nbox][4 nrc][T]
 };
 
 // Per wave and pass of the S->M / S->L kernels (p2e.hip): bit k of `start`

@@ -240,8 +240,8 @@ template <int ND, class R, int PM, int MINW>
 __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, int nd_all, Tree t, List V, RotSched sched,
                                                 const R* __restrict__ rot, const R* __restrict__ zt, int rot_len,
                                                 const double* __restrict__ geo, const double* __restrict__ sf,
-                                                const double2* __restrict__ M, double2* __restrict__ L,
-                                                const int* __restrict__ bmap) {
+                                                const double2* __restrict__ M, const float2* __restrict__ M32,
+                                                double2* __restrict__ L, const int* __restrict__ bmap) {
   using C = typename Cx<R>::T;
   constexpr int NACC = (ND * ncoef(PM) + RT - 1) / RT;
   extern __shared__ double2 smem[];
@@ -315,7 +315,21 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, int nd_all,
         const int g = it / T, f = it - (it / T) * T;
         const int c = 4 * g, S = cd.src[c];
         C o[4];
-        if (S >= 0) {
+        if (S >= 0 && sizeof(R) == 4) {
+          // FP32: multipoles already scaled and rounded (k_m2l_prep)
+          const float2* src = M32 + ((int64_t)S * nd_all + d0 + (c % ND)) * T + f;
+          float2 v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = src[k * T];
+          const float w0 = (float)cd.wx[c], w1 = (float)cd.wy[c], w2 = (float)cd.wz[c];
+          v[3].x += w0 * v[0].x + w1 * v[1].x + w2 * v[2].x;
+          v[3].y += w0 * v[0].y + w1 * v[1].y + w2 * v[2].y;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            o[k].x = (R)v[k].x;
+            o[k].y = (R)v[k].y;
+          }
+        } else if (S >= 0) {
           const double2* src = M + ((int64_t)S * nd_all + d0 + (c % ND)) * T + f;
           double2 v[4];
 #pragma unroll
@@ -463,8 +477,21 @@ static hipError_t launch_nd(const Launch& l, Exp e, int nc, size_t shm, const Ro
   // the map runs are whole multiples of 8 blocks, so every density group of
   // a box lands on the same XCD
   kern<<<dim3(b1 - b0, nsplit), RT, shm, l.s>>>(l.p, nc, ND * nsplit, B->tree, B->lists[LV], sc, rot, zt,
-                                                 l.tb->rot_len, l.tb->geo, l.tb->sfac, e.M, e.L, B->m2l_map + b0);
+                                                 l.tb->rot_len, l.tb->geo, l.tb->sfac, e.M, e.M32, e.L,
+                                                 B->m2l_map + b0);
   return hipGetLastError();
+}
+
+// The FP32 M->L reads the multipoles of its source boxes in the paper's
+// normalisation, scaled and rounded once per pass here instead of per
+// V-list entry: boxes [b0, b1), all nd densities.
+__global__ void k_m2l_prep(int T, int nd, int64_t b0, int64_t b1, const double* __restrict__ sf,
+                           const double2* __restrict__ M, float2* __restrict__ M32) {
+  const int64_t i = b0 * nd * T + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b1 * nd * T) return;
+  const double s = sf[i % T];
+  const double2 v = M[i];
+  M32[i] = make_float2((float)(v.x * s), (float)(v.y * s));
 }
 
 template <class R>
@@ -472,6 +499,20 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
   const int p = l.p;
   if (p < 0 || p > MAX_ORDER) return hipErrorInvalidValue;
   if (l.B->tree.nbox == 0) return hipSuccess;
+  if (sizeof(R) == 4) {
+    // sources of the deepest level's targets (part 0) are on that level, those
+    // of the other targets (part 1) above it
+    if (!e.M32) return hipErrorInvalidValue;
+    const Built* B = l.B;
+    const int64_t deep = B->level_start.empty() ? 0 : B->level_start[B->depth];
+    const int64_t b0 = part == 1 ? 0 : (part == 0 ? deep : 0), b1 = part == 1 ? deep : B->tree.nbox;
+    const int T = ncoef(p), nd = 4 * nrc;
+    const int64_t cnt = (b1 - b0) * nd * T;
+    if (cnt > 0)
+      k_m2l_prep<<<(unsigned)((cnt + 255) / 256), 256, 0, l.s>>>(T, nd, b0, b1, l.tb->sfac, e.M, e.M32);
+    const hipError_t he = hipGetLastError();
+    if (he != hipSuccess) return he;
+  }
   // 64 columns per batch, halved while the LDS (160 KB per CU) cannot hold
   // them.  Up to degree 16 in FP32, 60 columns let two blocks share a CU
   // (registers are then capped for four waves per SIMD); each block then
