@@ -128,7 +128,9 @@ def run(args):
         w0 = W.config(cid, scale=1e-3)  # bead and rhs counts of the full workload, cheaply
         n_full, r_full = round(w0.n * 1e3), w0.nrhs
         k = int(min(12000, max(200, 6e9 / (n_full * (1 + 0.25 * r_full)))))
-    w = W.config(cid, nsample=k)
+    # a batch samples per system (about k targets in all)
+    nsys = len(W.config(cid, scale=1e-3).counts)
+    w = W.config(cid, nsample=max(1, k // nsys))
     if args.eps:
         import dataclasses
         w = dataclasses.replace(w, eps=args.eps)
@@ -204,17 +206,49 @@ def run(args):
         import oracle
         oracle.lib()
         k = len(w.sample)
+        # each sampled target summed over every bead of its own system
+        bounds = np.concatenate([[0], np.cumsum(w.counts)])
+        ref = np.zeros((w.nrhs, k, 3))
+        pairs = 0
         t0 = time.perf_counter()
-        ref = oracle.rpy_direct(w.pos, w.forces, w.a, w.eta, targets=w.sample)
+        for s0, s1 in zip(bounds[:-1], bounds[1:]):
+            sel = np.where((w.sample >= s0) & (w.sample < s1))[0]
+            if len(sel):
+                ref[:, sel] = oracle.rpy_direct(w.pos[s0:s1], w.forces[:, s0:s1], w.a, w.eta,
+                                                targets=w.sample[sel] - s0)
+                pairs += len(sel) * int(s1 - s0)
         tc = time.perf_counter() - t0
+        full_pairs = float(np.sum(np.asarray(w.counts, dtype=np.float64) ** 2))
         cpu = {"value": k * w.nrhs / tc, "unit": "beads*matvecs/s", "cores": oracle.max_threads(),
                "cpu_model": cpu_model(), "kind": "oracle",
-               "sample": f"direct O(N^2) FP64 sum for {k} sampled targets of {w.n} (all sources, "
-                         f"nrhs={w.nrhs}), {tc:.2f} s; value = targets*rhs/s",
-               "pairs_per_s": k * w.n / tc,
-               "full_matvec_s_extrapolated": tc * w.n / k}
+               "sample": f"direct O(N^2) FP64 sum for {k} sampled targets of {w.n} (all sources of the "
+                         f"target's system, nrhs={w.nrhs}), {tc:.2f} s; value = targets*rhs/s",
+               "pairs_per_s": pairs / tc,
+               "full_matvec_s_extrapolated": tc * full_pairs / pairs}
         for prec, r in results.items():
             errs[prec] = oracle.rel_l2(r["u"], ref)
+
+    # Optional: the oracle's FMM (same order, leaf size and W-direct threshold
+    # as the GPU plan) on the first --oracle-fmm systems of the workload (all
+    # of a single-system workload), on the host's cores.  Not part of the
+    # default run (minutes of CPU time).
+    fmm_cpu = None
+    if args.oracle_fmm > 0:
+        import oracle
+        oracle.lib()
+        st = results[args.precisions[-1]]["stats"]
+        bounds = np.concatenate([[0], np.cumsum(w.counts)])[:args.oracle_fmm + 1]
+        t0 = time.perf_counter()
+        for s0, s1 in zip(bounds[:-1], bounds[1:]):
+            oracle.fmm(w.pos[s0:s1], w.forces[:, s0:s1], w.a, w.eta, st["order"], st["leaf_size"], st["w_direct"],
+                       max_depth=w.max_depth)
+        tf = time.perf_counter() - t0
+        nb = int(bounds[-1])
+        fmm_cpu = {"value": nb * w.nrhs / tf, "unit": "beads*matvecs/s", "seconds": round(tf, 2),
+                   "cores": oracle.max_threads(), "cpu_model": cpu_model(), "kind": "oracle FMM",
+                   "sample": f"{len(bounds) - 1} of {len(w.counts)} system(s), {nb} of {w.n} beads, nrhs={w.nrhs}, "
+                             f"p={st['order']}, s={st['leaf_size']}, W-direct {st['w_direct']}"}
+        progress(f"{w.name}: oracle FMM {tf:.1f} s on {fmm_cpu['cores']} threads")
 
     # Headline: the fastest form that meets the accuracy gate.
     ok = [p for p in results if (not errs) or errs[p] <= w.eps]
@@ -339,6 +373,7 @@ def run(args):
                                   if "fp64" in results and "mixed" in results else None),
         "roofline": roof,
         "cpu_baseline": cpu,
+        **({"cpu_oracle_fmm": fmm_cpu} if fmm_cpu else {}),
     }
     print(json.dumps(line), flush=True)
     if errs and errs[best] > w.eps:
@@ -434,6 +469,8 @@ def main():
                     help="sampled targets of the oracle's direct sum (CPU baseline and accuracy gate); 0: a "
                          "sample of about 6e9 pair evaluations times right-hand sides, at least 200 targets")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (profiling runs)")
+    ap.add_argument("--oracle-fmm", type=int, default=0, metavar="SYSTEMS",
+                    help="also time the oracle's FMM (same order and leaf size) on the first SYSTEMS systems")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),

@@ -19,13 +19,18 @@ __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
 
 // Blocks are dealt to the 8 XCDs round-robin (block i to XCD i mod 8), each
 // with its own L2.  Work items in leaf (Morton) order share most of their
-// inputs with their neighbours, so XCD x takes the x-th contiguous run of
-// items (runs differ by at most one): block i handles item
-// x q + min(x, r) + i / 8 with x = i mod 8, q = G / 8, r = G mod 8 for a
-// grid of G blocks, a permutation of 0 .. G - 1.
+// inputs with their neighbours, so items are dealt in chunks of XCD_CHUNK
+// consecutive ones: XCD x takes chunks x, x + 8, x + 16, ... (its k-th block
+// the item (8 (k / XCD_CHUNK) + x) XCD_CHUNK + k mod XCD_CHUNK), which keeps
+// neighbouring items in one L2 and, chunk by chunk, the XCDs' work even when
+// it varies along the item order (clustered beads).  Blocks past the last
+// whole round of 8 chunks take their own index.  A permutation of 0 .. G - 1.
+constexpr int XCD_CHUNK = 16;
 __device__ inline int xcd_run(int i, int G) {
-  const int x = i & 7, q = G >> 3, r = G & 7;
-  return x * q + (x < r ? x : r) + (i >> 3);
+  const int full = G / (8 * XCD_CHUNK) * (8 * XCD_CHUNK);
+  if (i >= full) return i;
+  const int x = i & 7, k = i >> 3;
+  return (8 * (k / XCD_CHUNK) + x) * XCD_CHUNK + k % XCD_CHUNK;
 }
 
 // Device view of the octree.  Boxes are numbered by (level, system, Morton

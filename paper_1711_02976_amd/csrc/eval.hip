@@ -216,9 +216,8 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4*
                                                    const double2* __restrict__ DL, const double2* __restrict__ DW,
                                                    double C1, double* __restrict__ u) {
   // consecutive tiles (mostly of one leaf) share a block, hence a CU and its
-  // scalar cache, and walk the same set coefficients at about the same time;
-  // consecutive blocks share an XCD (and its L2)
-  const int ti = xcd_run(blockIdx.x, gridDim.x) * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // scalar cache, and walk the same set coefficients at about the same time
+  const int ti = blockIdx.x * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (ti >= ntiles) return;
   const int4 tl = tiles[ti];
   const int b = tl.x, lane = threadIdx.x & 63;
@@ -386,7 +385,7 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_poly_apply(int p, const 
                                                                    const double* __restrict__ DP,
                                                                    const double2* __restrict__ DW, double C1,
                                                                    double* __restrict__ u) {
-  const int ti = xcd_run(blockIdx.x, gridDim.x) * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ti = blockIdx.x * EV_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (ti >= ntiles) return;
   const int4 tl = tiles[ti];
   const int b = tl.x, lane = threadIdx.x & 63;

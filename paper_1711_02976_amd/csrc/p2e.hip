@@ -91,6 +91,13 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
   constexpr int S = P2E_WAVES * K;
   constexpr int LD = S + 1;  // odd row stride: conflict-free [bead][slot] writes
   constexpr int TPW = K / 8;  // 16-row tiles per wave: 2S rows / 16 / 8 waves
+  // One right-hand side (4 densities) fills only a quarter of a 16-column
+  // matrix-core tile: it accumulates on the vector units instead, lane =
+  // slot of one of G = S / 64 slot groups, the waves split into NB = 8 / G
+  // bead subsets of BPW beads whose partial sums are added at the end.
+  constexpr bool VEC = ND == 4;
+  constexpr int G = S / 64, NB = P2E_WAVES / G, BPW = P2E_CHUNK / NB;
+  static_assert(!VEC || NB * ND * S <= P2E_CHUNK * LD, "partial sums fit in the harmonics' LDS");
   const int T = ncoef(p);
   // S->M: one leaf per block.  S->L: one work item per block, a run of the
   // box's X entries and a range of 64-bead chunks of each; a box whose X
@@ -117,12 +124,18 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;  // matrix-core operand row / column and k index
+  const int grp = wv % G, sub = wv / G, slot = grp * 64 + lane;  // vector accumulation
   const double cx = t.cx[b], cy = t.cy[b], cz = t.cz[b], ih = 1.0 / t.h[b];
-  v4d acc[P][TPW];
+  v4d acc[VEC ? 1 : P][VEC ? 1 : TPW];
+  double2 vacc[VEC ? P : 1][VEC ? ND : 1];
 #pragma unroll
-  for (int ps = 0; ps < P; ++ps)
+  for (int ps = 0; ps < (VEC ? 0 : P); ++ps)
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[ps][q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ps = 0; ps < (VEC ? P : 0); ++ps)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) vacc[ps][d] = make_double2(0.0, 0.0);
 
   for (int e = e0; e < e1; ++e) {
     const int C = LOCAL ? X.ent[e] : b;
@@ -230,20 +243,77 @@ __global__ void __launch_bounds__(P2E_THREADS) k_p2e(int p, const int* ids, cons
         // lane row + 16 k (row = real or imaginary part of a slot), B[k][d]
         // in lane d + 16 k, D[row][d] in lane d + 16 (row % 4), item row / 4;
         // beads past nb have zero harmonics and finite (padded) charges
-        const double* hd = reinterpret_cast<const double*>(Hs);
-        for (int kk = 0; kk < nb; kk += 4) {
-          const int bb = kk + lk;
-          double bq = 0.0;
-          if (li < ND) bq = LOCAL ? Qs[bb * ND + li] : Q[(int64_t)(jc + bb) * ND + li];
+        if constexpr (VEC) {
+          // beads past nb have zero harmonics; Q is padded past the last bead
+          if (sub * BPW < nb) {
 #pragma unroll
-          for (int q = 0; q < TPW; ++q) {
-            const int row = (wv + 8 * q) * 16 + li;
-            const double a = hd[2 * (bb * LD + (row >> 1)) + (row & 1)];
-            acc[ps][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[ps][q], 0, 0, 0);
+            for (int i = 0; i < BPW; ++i) {
+              const int bb = sub * BPW + i;
+              const double* q = LOCAL ? Qs + bb * ND : Q + (int64_t)(jc + bb) * ND;
+              const double2 h = Hs[bb * LD + slot];
+#pragma unroll
+              for (int dd = 0; dd < ND; ++dd) {
+                const double qd = q[dd];
+                vacc[ps][dd].x = fma(qd, h.x, vacc[ps][dd].x);
+                vacc[ps][dd].y = fma(qd, h.y, vacc[ps][dd].y);
+              }
+            }
+          }
+        } else {
+          const double* hd = reinterpret_cast<const double*>(Hs);
+          for (int kk = 0; kk < nb; kk += 4) {
+            const int bb = kk + lk;
+            double bq = 0.0;
+            if (li < ND) bq = LOCAL ? Qs[bb * ND + li] : Q[(int64_t)(jc + bb) * ND + li];
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+              const int row = (wv + 8 * q) * 16 + li;
+              const double a = hd[2 * (bb * LD + (row >> 1)) + (row & 1)];
+              acc[ps][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[ps][q], 0, 0, 0);
+            }
           }
         }
       }
     }
+  }
+  if constexpr (VEC) {
+    // add the NB partial sums per slot (through LDS) and write the expansion
+    double2* Rs = Hs;
+#pragma unroll
+    for (int ps = 0; ps < P; ++ps) {
+      __syncthreads();
+#pragma unroll
+      for (int d = 0; d < ND; ++d) Rs[(sub * ND + d) * S + slot] = vacc[ps][d];
+      __syncthreads();
+      for (int o = threadIdx.x; o < ND * S; o += P2E_THREADS) {
+        const int d = o / S, sl = o - d * S;
+        const int c = slot_coef[ps * S + sl];
+        if (c < 0) continue;
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const double2 w = Rs[(k * ND + d) * S + sl];
+          v.x += w.x;
+          v.y += w.y;
+        }
+        if (LOCAL && pslot >= 0) {
+          part[((int64_t)pslot * ND + d) * T + c] = v;
+          continue;
+        }
+        double2* out = E + ((int64_t)b * ND + d) * T + c;
+        if (LOCAL) {
+          const double2 o0 = *out;
+          v.x += o0.x;
+          v.y += o0.y;
+        } else {
+          const double f = slot_scale[ps * S + sl];  // S_n^m -> R_n^m
+          v.x *= f;
+          v.y *= f;
+        }
+        *out = v;
+      }
+    }
+    return;
   }
   // write the expansion: D[i][d] sits in lane d + 16 (i % 4), item i / 4, so
   // a lane holds rows of one parity only (real parts for even lk, imaginary

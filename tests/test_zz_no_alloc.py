@@ -67,6 +67,28 @@ def test_noalloc_matches_matvec(orc):
         PB.free()
 
 
+def test_noalloc_matrix_core_group(orc):
+    # 20 right-hand sides in the mixed form: a near-field group of 16 on the
+    # matrix cores and one of 4 on the vector units, from the scratch; the
+    # workspace fits, so the grouping and the results equal rpy_matvec's
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    w = W.uniform_cube(6_000, 1.0, 0.01, nrhs=20, seed=134)
+    log(f"noalloc: n={w.n} nrhs={w.nrhs} mixed")
+    P = _plan(R, w, leaf_size=200, order=16, precision="mixed")
+    try:
+        F = to_dev(w.forces)
+        ref = P.matvec(F).cpu().numpy()
+        U = torch.full_like(F, float("nan"))
+        torch.cuda.synchronize()
+        _noalloc(R, P, F, U)
+        torch.cuda.synchronize()
+        assert np.array_equal(U.cpu().numpy(), ref)
+        assert orc.rel_l2(ref, orc.rpy_direct(w.pos, w.forces, w.a, w.eta)) <= 1e-6
+    finally:
+        P.free()
+
+
 def test_noalloc_refuses_oversized_plan(orc):
     import paper_1711_02976_amd as R
     torch = torch_cuda()
