@@ -100,18 +100,25 @@ def cpu_model():
     return "unknown"
 
 
+def source_sha(kernel_file):
+    """Hash of a kernel's source file and the headers every kernel includes."""
+    h = hashlib.sha256()
+    for f in (kernel_file, "common.h", "fmm.h"):
+        h.update(open(os.path.join(ROOT, "paper_1711_02976_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_for(kernel_file, launches_key):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current source of the kernel; else None."""
+    taken on the current source of the kernel (and the shared headers); else
+    None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(launches_key)
     if not rec:
         return None
-    src = os.path.join(ROOT, "paper_1711_02976_amd", "csrc", kernel_file)
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha") != sha:
+    if rec.get("source_sha") != source_sha(kernel_file):
         return None
     return rec.get("bytes_per_launch")
 
@@ -426,11 +433,11 @@ def pmc_summary(args):
             continue
         fb = mean(f[(name, "FETCH_SIZE")]) * 1024.0 * kf
         wb = mean(w[(name, "WRITE_SIZE")]) * 1024.0 * kw
-        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1711_02976_amd", "csrc", src), "rb").read())
+        sha = source_sha(src)
         rec[f"{phase}:{args.workload}:{form}"] = {
             "kernel": name, "fetch_bytes": round(fb), "write_bytes": round(wb),
             "bytes_per_launch": round(fb + wb), "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
-            "source_sha": sha.hexdigest()[:16]}
+            "source_sha": sha}
     json.dump(rec, open(path, "w"), indent=1, sort_keys=True)
     print(json.dumps(rec, indent=1, sort_keys=True))
     return 0
