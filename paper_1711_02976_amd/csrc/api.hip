@@ -940,7 +940,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
-  // near-field groups: up to 8 right-hand sides share each pair's geometry
+  // near-field groups: 16 (matrix cores) or up to 8 right-hand sides share each pair's geometry
   const int nrn = std::max(nrc, std::min(near_group(nrhs, rpy::NEAR_MAX_RHS), P->near_max));
   if (alloc_ws(P, nrc, nrn) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
