@@ -136,10 +136,18 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const double c_leaf = 27.0 * T / T21;
   const double c_x = 0.075 * T / T21, c_w = 0.09 * T / T21;
   const double far = B.lists[rpy::LV].len * c_v + nbox * c_box + nleaf * c_leaf + xpairs * c_x + weval * c_w;
-  // passes of 4 right-hand sides, then 2 and 1, as rpy_matvec runs them
+  // near-field groups as rpy_matvec runs them (16 on the matrix cores, then
+  // 8, 4, 2, 1 on the vector units), in units of a one-rhs launch (measured
+  // on cube-15M: 16 rhs 5.5, 8 rhs 3.9, 4 rhs 2.3, 2 rhs 1.5)
   const int r = std::max(nrhs, 1);
-  const int n4 = r / 4, n2 = (r % 4) / 2, n1 = r % 2;
-  const double near_passes = n4 * 2.3 + n2 * 1.5 + n1;
+  double near_passes = 0.0;
+  for (int left = r; left > 0;) {
+    int g = left >= rpy::NEAR_MAX_RHS ? rpy::NEAR_MAX_RHS : 1;
+    if (g == 1)
+      while (2 * g <= std::min(left, rpy::NEAR_VEC_RHS)) g *= 2;
+    near_passes += g == rpy::NEAR_MAX_RHS ? 5.5 : g == 8 ? 3.9 : g == 4 ? 2.3 : g == 2 ? 1.5 : 1.0;
+    left -= g;
+  }
   out->near_ns = pairs * c_pair * near_passes;
   out->ns = out->near_ns + 4.0 * r * far;
   out->same_lo = lo;

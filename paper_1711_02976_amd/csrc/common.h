@@ -25,7 +25,7 @@ __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) / 2; }
 // neighbouring items in one L2 and, chunk by chunk, the XCDs' work even when
 // it varies along the item order (clustered beads).  Blocks past the last
 // whole round of 8 chunks take their own index.  A permutation of 0 .. G - 1.
-constexpr int XCD_CHUNK = 16;
+constexpr int XCD_CHUNK = 128;
 __device__ inline int xcd_run(int i, int G) {
   const int full = G / (8 * XCD_CHUNK) * (8 * XCD_CHUNK);
   if (i >= full) return i;
