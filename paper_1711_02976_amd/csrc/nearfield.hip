@@ -7,7 +7,9 @@
 // One block of P2P_T threads per target tile (a leaf, or a P2P_T-bead slice
 // of a large leaf); each lane owns one target and keeps 3 * nrc sums in
 // registers; source beads of each U-list leaf are staged through LDS
-// (positions and forces, SoA) and read back as wave-wide broadcasts.
+// (positions and forces, SoA) and read back as wave-wide broadcasts.  With
+// 16 right-hand sides the P2P runs on the matrix cores instead (k_p2p_mfma,
+// 16 targets per wave, the 3x3 pair blocks as product operands).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

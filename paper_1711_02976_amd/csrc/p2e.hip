@@ -21,7 +21,9 @@
 // rows being the real and imaginary parts of the pass's S coefficient slots,
 // done as v_mfma_f64_16x16x4f64 tiles of 16 rows x 16 densities (densities
 // past ND are zero) over 4 beads per instruction; wave w owns the row tiles
-// w, w + 8, ... for the whole box, so no sums cross waves.  A column may run
+// w, w + 8, ... for the whole box, so no sums cross waves.  One right-hand
+// side (ND = 4) would leave three quarters of each tile empty and
+// accumulates on the vector units instead (see k_p2e).  A column may run
 // over several passes of K steps per wave; the recurrence state stays in
 // registers between passes.
 #include <hip/hip_runtime.h>
