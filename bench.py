@@ -268,9 +268,10 @@ def run(args):
         """Live rates of one form from the HIP events of the timed region:
         P2P flop/s by the measurement's per-pair count (16 flops of geometry
         per launch and 12 per right-hand side), in total, for the launches
-        on the matrix cores (groups of 16 right-hand sides, against the
-        matrix-core peak of the precision) and for those on the vector units
-        (against the vector peak, also by the vector kernel's own count);
+        on the matrix cores (16 right-hand sides there plus up to 8 on the
+        vector units of the same launch, against the matrix-core peak of the
+        precision) and for those on the vector units alone (against the
+        vector peak, also by the vector kernel's own count);
         M2L flop/s of the rotation operator (20 S flops per V pair and
         density) against the vector peak (no MFMA instruction is issued)."""
         tm = q["timings"]
@@ -284,8 +285,9 @@ def run(args):
         f_p2p = pairs * (16 * L_p2p + 12 * w.nrhs)
         L_mc = tm.get("p2p_mc_launches", 0) / steps
         t_mc = tm.get("p2p_mc_ms", 0.0) / steps * 1e-3
-        L_vec, t_vec, rhs_vec = L_p2p - L_mc, t_p2p - t_mc, w.nrhs - 16 * L_mc
-        f_mc = pairs * (16 + 12 * 16) * L_mc
+        rhs_mc = tm.get("p2p_mc_rhs", 0) / steps
+        L_vec, t_vec, rhs_vec = L_p2p - L_mc, t_p2p - t_mc, w.nrhs - rhs_mc
+        f_mc = pairs * (16 * L_mc + 12 * rhs_mc)
         f_vec = pairs * (16 * L_vec + 12 * rhs_vec)
         f_p2p_kernel = pairs * (20 * L_vec + 18 * rhs_vec)
         peak_mc = PEAK_MFMA_FP32_TFLOPS if is_mixed else PEAK_MFMA_FP64_TFLOPS
@@ -297,7 +299,8 @@ def run(args):
                        "achieved_tflops": round(f_p2p / t_p2p / 1e12, 3) if t_p2p > 0 else None,
                        "frac": round(f_p2p / t_p2p / 1e12 / peak, 4) if t_p2p > 0 else None,
                        "peak_tflops": peak},
-               "p2p_mc": {"launches_per_matvec": L_mc, "ms_per_matvec": round(t_mc * 1e3, 4),
+               "p2p_mc": {"launches_per_matvec": L_mc, "rhs_per_matvec": rhs_mc,
+                          "ms_per_matvec": round(t_mc * 1e3, 4),
                           "avg_launch_ms": round(t_mc * 1e3 / L_mc, 4) if L_mc else None,
                           "flops_per_matvec": f_mc,
                           "achieved_tflops": round(f_mc / t_mc / 1e12, 3) if t_mc > 0 else None,
@@ -333,7 +336,8 @@ def run(args):
                 "unit": "TFLOP/s", "frac": d["frac"],
                 "traffic": traffic_for("nearfield.hip", f"p2p_mc:{args.workload}:{best}"),
                 "avg_launch_ms": d["avg_launch_ms"], "algorithmic_flops_per_launch": d["flops_per_matvec"] / launches,
-                "count": count + " (16 right-hand sides per launch)"}
+                "count": count + f" ({d['rhs_per_matvec'] / launches:g} right-hand sides per launch, "
+                                 "16 of them on the matrix cores)"}
     elif dom == "p2p_vec":
         launches = max(d["launches_per_matvec"], 1)
         roof = {"bound": "alu", "kernel": "k_p2p", "achieved": d["achieved_tflops"], "peak": d["peak_tflops"],
@@ -390,8 +394,8 @@ def run(args):
 
 
 PMC_KERNELS = {  # rocprofv3 kernel-name pattern -> (phase, precision form, source file)
-    r"rpy::k_p2p_mfma<true>": ("p2p_mc", "mixed", "nearfield.hip"),
-    r"rpy::k_p2p_mfma<false>": ("p2p_mc", "fp64", "nearfield.hip"),
+    r"rpy::k_p2p_mfma<true": ("p2p_mc", "mixed", "nearfield.hip"),
+    r"rpy::k_p2p_mfma<false": ("p2p_mc", "fp64", "nearfield.hip"),
     r"rpy::k_p2p<\d+, true>": ("p2p", "mixed", "nearfield.hip"),
     r"rpy::k_p2p<\d+, false>": ("p2p", "fp64", "nearfield.hip"),
     r"rpy::k_m2l_rot<\d+, float": ("m2l", "mixed", "m2l_rot.hip"),

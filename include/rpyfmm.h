@@ -269,8 +269,11 @@ typedef struct {
   int64_t launches[RPY_NPHASE];  /* kernel launches per phase */
   int64_t passes;                /* matvec passes (right-hand-side chunks) timed */
   double p2p_mc_ms;              /* part of ms[RPY_PH_P2P] spent in P2P launches on the matrix
-                                    cores (near-field groups of 16 right-hand sides) */
+                                    cores (near-field groups of 16 right-hand sides there; in
+                                    the FP64 form plus up to 8 on the vector units of the same
+                                    launch) */
   int64_t p2p_mc_launches;       /* those launches (also counted in launches[RPY_PH_P2P]) */
+  int64_t p2p_mc_rhs;            /* right-hand sides those launches carried, summed */
 } rpy_timings_t;
 
 /* Per-phase timing with HIP events: 0 off, 1 on (phases keep their normal

@@ -52,7 +52,8 @@ PHASES = ("permute", "p2p", "overlap", "p2m", "m2m", "m2l", "p2l", "l2l", "eval"
 
 class rpy_timings_t(C.Structure):
     _fields_ = [("ms", C.c_double * len(PHASES)), ("launches", C.c_int64 * len(PHASES)), ("passes", C.c_int64),
-                ("p2p_mc_ms", C.c_double), ("p2p_mc_launches", C.c_int64)]
+                ("p2p_mc_ms", C.c_double), ("p2p_mc_launches", C.c_int64),
+                ("p2p_mc_rhs", C.c_int64)]
 
 
 class rpy_sqrt_info_t(C.Structure):
@@ -215,7 +216,8 @@ def rpy_plan_timings(plan):
     t = rpy_timings_t()
     _check(lib().rpy_plan_timings(plan, C.byref(t)))
     return {"ms": dict(zip(PHASES, list(t.ms))), "launches": dict(zip(PHASES, list(t.launches))),
-            "passes": t.passes, "p2p_mc_ms": t.p2p_mc_ms, "p2p_mc_launches": t.p2p_mc_launches}
+            "passes": t.passes, "p2p_mc_ms": t.p2p_mc_ms, "p2p_mc_launches": t.p2p_mc_launches,
+            "p2p_mc_rhs": t.p2p_mc_rhs}
 
 
 def rpy_plan_inject_error(plan, phase):

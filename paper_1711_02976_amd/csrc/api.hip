@@ -75,6 +75,33 @@ int order_for_eps(double eps, bool adaptive) {
 //     (target bead, W box) (O(p^2)).
 // The overlap correction is not modelled: trial trees have no O list.  Also
 // returns the range of refinement limits that produce this same tree.
+// Right-hand sides of the near-field group with `left` still to do and
+// groups of at most nrn: 16 on the matrix cores, else 8, 4, 2 or 1 on the
+// vector units.  In the FP64 form the group of 16 also takes x = 1, 2, 4 or
+// 8 more on the vector units of the same launch (unless 32 or more remain,
+// so that more of them reach the matrix cores): on cube-15M, 16 + 4 run in
+// 1.22 s against 0.95 + 0.36 s as two launches.  In the mixed form the
+// extra registers halve the matrix-core kernel's occupancy and 16 + 4 take
+// 0.82 s against 0.51 + 0.20 s, so its groups of 16 stay alone.
+static int vec_group(int m) {
+  int c = 1;
+  while (2 * c <= std::min(m, rpy::NEAR_VEC_RHS)) c *= 2;
+  return c;
+}
+static int near_group(int left, int nrn, bool mixed) {
+  const int m = std::min(left, nrn);
+  if (m < rpy::NEAR_MC_RHS) return vec_group(m);
+  if (mixed || m == rpy::NEAR_MC_RHS || left >= 2 * rpy::NEAR_MC_RHS) return rpy::NEAR_MC_RHS;
+  return rpy::NEAR_MC_RHS + vec_group(m - rpy::NEAR_MC_RHS);
+}
+// The largest group of a matvec of nrhs right-hand sides (its workspace).
+static int near_group_max(int nrhs, bool mixed) {
+  int g = 1;
+  for (int left = nrhs; left > 0; left -= near_group(left, rpy::NEAR_MAX_RHS, mixed))
+    g = std::max(g, near_group(left, rpy::NEAR_MAX_RHS, mixed));
+  return g;
+}
+
 struct TreeCost {
   double ns = 0;
   double near_ns = 0;  // the P2P and direct-W part of ns
@@ -136,16 +163,16 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const double c_leaf = 27.0 * T / T21;
   const double c_x = 0.075 * T / T21, c_w = 0.09 * T / T21;
   const double far = B.lists[rpy::LV].len * c_v + nbox * c_box + nleaf * c_leaf + xpairs * c_x + weval * c_w;
-  // near-field groups as rpy_matvec runs them (16 on the matrix cores, then
-  // 8, 4, 2, 1 on the vector units), in units of a one-rhs launch (measured
-  // on cube-15M: 16 rhs 5.5, 8 rhs 3.9, 4 rhs 2.3, 2 rhs 1.5)
+  // near-field groups as rpy_matvec runs them, in units of a one-rhs launch
+  // (measured on cube-15M: 16 rhs on the matrix cores 5.5, 16 + 4 in the
+  // FP64 form 7.1; on the vector units 8 rhs 3.9, 4 rhs 2.3, 2 rhs 1.5)
   const int r = std::max(nrhs, 1);
   double near_passes = 0.0;
   for (int left = r; left > 0;) {
-    int g = left >= rpy::NEAR_MAX_RHS ? rpy::NEAR_MAX_RHS : 1;
-    if (g == 1)
-      while (2 * g <= std::min(left, rpy::NEAR_VEC_RHS)) g *= 2;
-    near_passes += g == rpy::NEAR_MAX_RHS ? 5.5 : g == 8 ? 3.9 : g == 4 ? 2.3 : g == 2 ? 1.5 : 1.0;
+    const int g = near_group(left, rpy::NEAR_MAX_RHS, mixed);
+    const int x = g >= rpy::NEAR_MC_RHS ? g - rpy::NEAR_MC_RHS : g;
+    const double vec = x == 8 ? 3.9 : x == 4 ? 2.3 : x == 2 ? 1.5 : x == 1 ? 1.0 : 0.0;
+    near_passes += g >= rpy::NEAR_MC_RHS ? 5.5 + 0.65 * vec : vec;
     left -= g;
   }
   out->near_ns = pairs * c_pair * near_passes;
@@ -254,11 +281,12 @@ static hipEvent_t get_event(rpy_plan_t* P) {
 }
 
 // Runs one phase, bracketed by events on its stream when timing is on.
-// mc: the step is a P2P launch on the matrix cores, also accumulated on its
-// own (events keyed phase + TIMED_MC)
+// mc > 0: the step is a P2P launch on the matrix cores carrying mc
+// right-hand sides, also accumulated on its own (events keyed phase +
+// TIMED_MC)
 constexpr int TIMED_MC = 0x100;
 template <class F>
-static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, F&& f, bool mc = false) {
+static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, F&& f, int mc = 0) {
   if (!P->timing) return f();
   hipEvent_t a = get_event(P), b = get_event(P);
   if (a) (void)hipEventRecord(a, st);
@@ -266,7 +294,10 @@ static hipError_t timed(rpy_plan_t* P, int phase, int launches, hipStream_t st, 
   if (b) (void)hipEventRecord(b, st);
   if (a && b) P->ev_pending.push_back({phase + (mc ? TIMED_MC : 0), {a, b}});
   P->acc.launches[phase] += launches;
-  if (mc) P->acc.p2p_mc_launches += launches;
+  if (mc) {
+    P->acc.p2p_mc_launches += launches;
+    P->acc.p2p_mc_rhs += (int64_t)launches * mc;
+  }
   return e;
 }
 
@@ -345,7 +376,7 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
   rpy::Launch ln = l;
   ln.s = s1;
   // a phase named by rpy_plan_inject_error reports an error instead of running
-  auto step = [&](int phase, int launches, hipStream_t st, auto&& f, bool mc = false) -> hipError_t {
+  auto step = [&](int phase, int launches, hipStream_t st, auto&& f, int mc = 0) -> hipError_t {
     if (P->inject == phase) {
       P->inject = -1;
       return hipErrorLaunchFailure;
@@ -361,7 +392,7 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
   }
   if (he == hipSuccess)
     he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, cn, w.sF, w.u, mixed); },
-              cn == rpy::NEAR_MAX_RHS);
+              cn >= rpy::NEAR_MC_RHS ? cn : 0);
   if (he == hipSuccess && haveO)
     he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, cn, w.sF, w.u); });
   if (he == hipSuccess && haveW)
@@ -406,16 +437,6 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
     q0 += c;
   }
   return he;
-}
-
-// Right-hand sides of the near-field group with `left` still to do and
-// groups of at most nrn: 16 (the P2P on the matrix cores), else 8, 4, 2 or 1.
-static int near_group(int left, int nrn) {
-  const int m = std::min(left, nrn);
-  if (m >= rpy::NEAR_MAX_RHS) return rpy::NEAR_MAX_RHS;
-  int c = 1;
-  while (2 * c <= std::min(m, rpy::NEAR_VEC_RHS)) c *= 2;
-  return c;
 }
 
 // ---- fixed workspace of the allocation-free matvec ----------------------
@@ -949,12 +970,12 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   // near-field groups: 16 (matrix cores) or up to 8 right-hand sides share each pair's geometry
-  const int nrn = std::max(nrc, std::min(near_group(nrhs, rpy::NEAR_MAX_RHS), P->near_max));
+  const int nrn = std::max(nrc, std::min(near_group_max(nrhs, P->precision == RPY_PREC_MIXED), P->near_max));
   if (alloc_ws(P, nrc, nrn) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; r0 < nrhs;) {
-    const int cn = near_group(nrhs - r0, nrn);
+    const int cn = near_group(nrhs - r0, nrn, mixed);
     const hipError_t he = matvec_group(P, l, P->ws, forces, nrhs, r0, cn, std::min(nrc, cn), mixed, velocities);
     if (he != hipSuccess) {
       P->sticky = 1;
@@ -979,7 +1000,7 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   // rpy_matvec, halved until the workspace fits the fixed scratch
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;
-  int nrn = std::max(nrc, std::min(near_group(nrhs, rpy::NEAR_MAX_RHS), P->near_max));
+  int nrn = std::max(nrc, std::min(near_group_max(nrhs, P->precision == RPY_PREC_MIXED), P->near_max));
   size_t sz[WS_N], tot = 0;
   for (;;) {
     ws_sizes(P, nrc, nrn, sz);
@@ -1019,7 +1040,7 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
   const int mixed = P->precision == RPY_PREC_MIXED;
   for (int r0 = 0; he == hipSuccess && r0 < nrhs;) {
-    const int cn = near_group(nrhs - r0, nrn);
+    const int cn = near_group(nrhs - r0, nrn, mixed);
     he = matvec_group(P, l, w, forces, nrhs, r0, cn, std::min(nrc, cn), mixed, velocities, true);
     r0 += cn;
   }

@@ -114,11 +114,14 @@ struct Tiles {
 };
 int make_tiles(const Built* B, int tile, Tiles* out, hipStream_t s, Error* err);
 // The near-field kernels take 1, 2, 4 or 8 right-hand sides per launch on
-// the vector units (NEAR_VEC_RHS), or 16 (NEAR_MAX_RHS): the P2P then runs
-// on the matrix cores and the overlap and direct W sums as two launches of
-// 8; sF and u are [nrc][3][n].
+// the vector units (NEAR_VEC_RHS), or 16 + x with x in {0, 1, 2, 4, 8} (x > 0
+// in the FP64 form only): the P2P then runs 16 of them on the matrix cores
+// (NEAR_MC_RHS) and x on the vector units of the same launch, and the
+// overlap and direct W sums as launches of 8 and the rest; sF and u are
+// [nrc][3][n].
 constexpr int NEAR_VEC_RHS = 8;
-constexpr int NEAR_MAX_RHS = 16;
+constexpr int NEAR_MC_RHS = 16;
+constexpr int NEAR_MAX_RHS = NEAR_MC_RHS + NEAR_VEC_RHS;
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
 hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);  // FP64
 // W-list boxes of at most Launch::wd beads are summed directly (far

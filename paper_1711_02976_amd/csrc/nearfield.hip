@@ -8,8 +8,9 @@
 // of a large leaf); each lane owns one target and keeps 3 * nrc sums in
 // registers; source beads of each U-list leaf are staged through LDS
 // (positions and forces, SoA) and read back as wave-wide broadcasts.  With
-// 16 right-hand sides the P2P runs on the matrix cores instead (k_p2p_mfma,
-// 16 targets per wave, the 3x3 pair blocks as product operands).
+// 16 right-hand sides (in the FP64 form plus up to 8 more on the vector units
+// of the same launch) the P2P runs on the matrix cores instead (k_p2p_mfma, 16 targets
+// per wave, the 3x3 pair blocks as product operands).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -265,11 +266,20 @@ __global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U
 // v_mfma_f32_16x16x4f32 and adds D into FP64 sums after each staged chunk of
 // sources (as the vector kernel does); the FP64 form uses
 // v_mfma_f64_16x16x4f64 and keeps the sums in D.
+// In the FP64 form XR = 1, 2, 4 or 8 further right-hand sides ride in the
+// same launch on the vector units: each lane applies its pair block to them
+// (nine multiply-adds per right-hand side), so the pair geometry is formed
+// once for 16 + XR right-hand sides.  Their per-lane partial sums are added
+// over the four source lanes of a target after each staged chunk, and lane
+// (t, k) keeps the FP64 sums of the right-hand sides k, k + 4.  (The mixed
+// form runs its extra right-hand sides in the vector kernel: there the
+// registers they take cost the matrix-core loop more than the shared
+// geometry saves.)
 namespace {
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 constexpr int MF_W = 8;         // waves per block: 16 targets each, P2P_T per tile
-constexpr int MF_R = 16;        // right-hand sides per launch (the product's N)
+constexpr int MF_R = NEAR_MC_RHS;  // right-hand sides on the matrix cores (the product's N)
 __device__ inline v4f_t mfma16(float a, float b, v4f_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 __device__ inline v4d_t mfma16(double a, double b, v4d_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 // Row (target within the wave's 16) of item v of a 16x16 result in lane l;
@@ -278,7 +288,7 @@ __device__ inline int mf_row(float, int l, int v) { return 4 * (l >> 4) + v; }
 __device__ inline int mf_row(double, int l, int v) { return 4 * v + (l >> 4); }
 }  // namespace
 
-template <bool MIXED>
+template <bool MIXED, int XR>
 __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree t, List U, const double* sx,
                                                        const double* sy, const double* sz, const double* sF,
                                                        int64_t n,
@@ -287,8 +297,10 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
   using R = typename std::conditional<MIXED, float, double>::type;
   using R4 = typename std::conditional<MIXED, float4, double4>::type;
   using VD = typename std::conditional<MIXED, v4f_t, v4d_t>::type;
+  constexpr int XS = XR > 0 ? XR : 1, XH = (XR + 3) / 4 > 0 ? (XR + 3) / 4 : 1;
   __shared__ R4 ps[P2P_T];          // positions (x, y, z, -)
   __shared__ R fs[3][P2P_T][MF_R];  // [component][source][right-hand side]
+  __shared__ alignas(16) R fx[3][P2P_T][XS];  // the XR vector-unit right-hand sides
   const int4 tl = tiles[xcd_run(blockIdx.x, gridDim.x)];
   const int b = tl.x;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -307,6 +319,10 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[c][v] = 0.0;
   }
+  R xa[XS][3];      // this lane's pair sums of the vector-unit right-hand sides (one chunk)
+  double xacc[XH][3];  // FP64 sums of right-hand sides sk + 4 h for target ti
+#pragma unroll
+  for (int h = 0; h < XH; ++h) xacc[h][0] = xacc[h][1] = xacc[h][2] = 0.0;
   const int e0 = __builtin_amdgcn_readfirstlane(U.off[b]), e1 = __builtin_amdgcn_readfirstlane(U.off[b + 1]);
   for (int e = e0; e < e1; ++e) {
     const int C = __builtin_amdgcn_readfirstlane(U.ent[e]);
@@ -323,13 +339,19 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
         ps[tid] = R4{(R)1e30, (R)1e30, (R)1e30, (R)0};
       }
       // forces: sF row q = 3 r + c, read along the sources (coalesced)
-      for (int q = tid; q < 3 * MF_R * P2P_T; q += 64 * MF_W) {
+      for (int q = tid; q < 3 * (MF_R + XR) * P2P_T; q += 64 * MF_W) {
         const int row = q / P2P_T, sj = q - row * P2P_T;
-        if (sj < ns4) fs[row % 3][sj][row / 3] = sj < ns ? (R)sF[(int64_t)row * n + jc + sj] : (R)0;
+        if (sj < ns4) {
+          const R v = sj < ns ? (R)sF[(int64_t)row * n + jc + sj] : (R)0;
+          if (row < 3 * MF_R) fs[row % 3][sj][row / 3] = v;
+          else fx[(row - 3 * MF_R) % 3][sj][(row - 3 * MF_R) / 3] = v;
+        }
       }
       __syncthreads();
       if (wlive) {
         R m[6], f[3];
+#pragma unroll
+        for (int x = 0; x < XS; ++x) xa[x][0] = xa[x][1] = xa[x][2] = (R)0;
         for (int s0 = 0; s0 < ns4; s0 += 4) {
           const int j = s0 + sk;
           const R4 p = ps[j];
@@ -366,6 +388,13 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
           D[0] = mfma16(m[4], f[2], D[0]);
           D[1] = mfma16(m[5], f[2], D[1]);
           D[2] = mfma16(m[2], f[2], D[2]);
+#pragma unroll
+          for (int x = 0; x < XR; ++x) {
+            const R gx = fx[0][j][x], gy = fx[1][j][x], gz = fx[2][j][x];
+            xa[x][0] = fma(m[0], gx, fma(m[3], gy, fma(m[4], gz, xa[x][0])));
+            xa[x][1] = fma(m[3], gx, fma(m[1], gy, fma(m[5], gz, xa[x][1])));
+            xa[x][2] = fma(m[4], gx, fma(m[5], gy, fma(m[2], gz, xa[x][2])));
+          }
         }
         if (MIXED) {
 #pragma unroll
@@ -375,6 +404,17 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
             D[c] = VD{0, 0, 0, 0};
           }
         }
+        // the chunk's sums over the four source lanes of each target; lane
+        // sk keeps right-hand sides sk, sk + 4
+#pragma unroll
+        for (int x = 0; x < XR; ++x)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            R v = xa[x][c];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (sk == (x & 3)) xacc[x >> 2][c] += (double)v;
+          }
       }
     }
   }
@@ -388,6 +428,14 @@ __global__ void __launch_bounds__(64 * MF_W) k_p2p_mfma(const int4* tiles, Tree 
         const double x = MIXED ? acc[c][v] : (double)D[c][v];
         u[((int64_t)ti * 3 + c) * n + tl.y + t0 + row] = c1 * x;
       }
+    }
+  if (t0 + ti < tl.z)
+#pragma unroll
+    for (int h = 0; h < XH; ++h) {
+      const int x = sk + 4 * h;
+      if (x < XR)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u[((int64_t)(MF_R + x) * 3 + c) * n + tl.y + t0 + ti] = c1 * xacc[h][c];
     }
 }
 
@@ -628,15 +676,27 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
     P2P_CASE(8)
     case MF_R:
       if (mixed)
-        k_p2p_mfma<true><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF, B->n,
-                                                         q.kf, q.S, q.c1S, u);
+        k_p2p_mfma<true, 0><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF,
+                                                            B->n, q.kf, q.S, q.c1S, u);
       else
-        k_p2p_mfma<false><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF,
-                                                          B->n, q.kd, q.S, q.c1S, u);
+        k_p2p_mfma<false, 0><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF,
+                                                             B->n, q.kd, q.S, q.c1S, u);
       break;
+    // 16 + XR: the FP64 form only
+#define MF_CASE(XR)                                                                                                \
+  case MF_R + XR:                                                                                                  \
+    if (mixed) return hipErrorInvalidValue;                                                                        \
+    k_p2p_mfma<false, XR><<<tiles.n, 64 * MF_W, 0, l.s>>>(tiles.t, B->tree, B->lists[LU], B->sx, B->sy, B->sz, sF,   \
+                                                          B->n, q.kd, q.S, q.c1S, u);                              \
+    break;
+    MF_CASE(1)
+    MF_CASE(2)
+    MF_CASE(4)
+    MF_CASE(8)
     default: return hipErrorInvalidValue;
   }
 #undef P2P_CASE
+#undef MF_CASE
   return hipGetLastError();
 }
 

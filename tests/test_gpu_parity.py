@@ -167,8 +167,11 @@ def test_large_leaves_match_oracle_fmm(orc, case):
 # right-hand sides past 16 form groups of 8, 4, 2 or 1 on the vector units.
 # A single leaf is the direct sum: every tile of 128 targets (the last one
 # ragged, so some waves hold fewer than 16 targets and some none), with self
-# terms and overlapping pairs.
-@pytest.mark.parametrize("nrhs", [16, 20, 24, 26])
+# terms and overlapping pairs.  In the FP64 form 16 + x right-hand sides take
+# x = 1, 2, 4 or 8 of them on the vector units of the matrix-core launch, and
+# 26 and 40 run 16 + 8 then 2, and 16 then 16 + 8; the mixed form runs 16 on
+# the matrix cores and the rest in the vector kernel.
+@pytest.mark.parametrize("nrhs", [16, 17, 18, 20, 24, 26, 40])
 def test_matrix_core_p2p_single_leaf_is_direct(orc, nrhs):
     w = W.uniform_cube(3000, 1.0, 0.02, nrhs=nrhs, seed=52)
     log(f"single leaf n=3000 nrhs={nrhs} (matrix-core P2P)")
