@@ -394,7 +394,7 @@ static hipError_t matvec_group(rpy_plan_t* P, const rpy::Launch& l, const Work& 
     he = step(RPY_PH_P2P, 1, s1, [&] { return rpy::run_p2p(ln, P->tiles, cn, w.sF, w.u, mixed); },
               cn >= rpy::NEAR_MC_RHS ? cn : 0);
   if (he == hipSuccess && haveO)
-    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, cn, w.sF, w.u); });
+    he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_overlap(ln, P->tiles, cn, w.sF, w.u, mixed); });
   if (he == hipSuccess && haveW)
     he = step(RPY_PH_OVERLAP, 1, s1, [&] { return rpy::run_wdirect(ln, P->tiles, cn, w.sF, w.u, mixed); });
   if (he == hipSuccess && fork) he = hipEventRecord(P->ev_join, s1);

@@ -123,7 +123,7 @@ constexpr int NEAR_VEC_RHS = 8;
 constexpr int NEAR_MC_RHS = 16;
 constexpr int NEAR_MAX_RHS = NEAR_MC_RHS + NEAR_VEC_RHS;
 hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u);  // FP64
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed);
 // W-list boxes of at most Launch::wd beads are summed directly (far
 // formula) by run_wdirect; the target evaluation uses the multipoles of the
 // others only.  Per target and right-hand side the multipole route costs

@@ -111,6 +111,7 @@ struct PairK {
   R ock9;     // (c0/c1) 9/(32a)
   R ob;       // (c0/c1) 3/(32a)
   R r2min;    // floor added to r^2 before the reciprocal square root (coincident beads)
+  R i2a;      // 1/(2a)
 };
 
 // Power of two S with 2aS in [1, 2).
@@ -121,7 +122,7 @@ template <class R>
 static PairK<R> pair_const(double as) {
   const double oc = 4.0 / (3.0 * as);
   return PairK<R>{(R)(2.0 * as * as / 3.0), (R)(2.0 * as * as), (R)(4.0 * as * as), (R)oc,
-                  (R)(oc * 9.0 / (32.0 * as)), (R)(oc * 3.0 / (32.0 * as)), (R)1e-30};
+                  (R)(oc * 9.0 / (32.0 * as)), (R)(oc * 3.0 / (32.0 * as)), (R)1e-30, (R)(0.5 / as)};
 }
 
 __device__ inline float rinv_of(float r2) { return __builtin_amdgcn_rsqf(r2); }
@@ -517,8 +518,16 @@ __global__ void __launch_bounds__(P2P_T) k_wdirect(const int4* tiles, Tree t, Li
 // them with the r >= 2a formula, so (M_overlap - M_far) F is added.  Same
 // tiling as the P2P (padded, unrolled by 4); leaves of the O list are
 // separated, so r > 0 and the far values are finite.  Pairs at r >= 2a get a
-// zero coefficient (masked, no branch).  With the prefactor taken out:
-//   A' = oc (1 - 9r/(32a)) - 1/r - (2a^2/3)/r^3,  B' = ob/r - (1 - 2a^2/r^2)/r^3.
+// zero coefficient (masked, no branch).  With the prefactor taken out and
+// rho = r/(2a), the two branches' differences are
+//   A' = oc (1 - 9r/(32a)) - 1/r - (2a^2/3)/r^3
+//      = -(2a^2/3) (1 - rho)^2 (9 rho^2 + 2 rho + 1) / r^3,
+//   B' = ob/r - (1 - 2a^2/r^2)/r^3 = 2a^2 (1 - rho)^2 (1 + rho)^2 / r^5,
+// both with a double zero at r = 2a, where the branches meet.  In this
+// factored form nothing cancels, so the mixed form evaluates it in FP32
+// (rounding errors relative to the difference itself) and, as the P2P, adds
+// each staged chunk's FP32 sums into FP64.  The FP64 form subtracts the two
+// branches (fewer operations; the cancellation costs digits FP64 can spare).
 // Most pairs of two such leaves are farther apart than 2a, so the staged
 // sources are cut into groups of OV_G with bounding boxes, and a wave skips a
 // group whose box is 2a or more from every one of the wave's targets.
@@ -615,10 +624,19 @@ __global__ void __launch_bounds__(P2P_T) k_overlap(const int4* tiles, const doub
           const R r2 = fma(dx, dx, fma(dy, dy, fma(dz, dz, k.r2min)));
           const R rinv = rinv_of(r2);
           const R ri2 = rinv * rinv, ri3 = ri2 * rinv;
-          const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
-          const R Ao = fma(-k.ock9, (r2 - k.r2min) * rinv, k.oc), Bo = k.ob * rinv;
           const bool ov = r2 < k.four_a2;
-          const R A = ov ? Ao - Af : (R)0, B = ov ? Bo - Bf : (R)0;
+          R A, B;
+          if constexpr (MIXED) {  // factored
+            const R rho = (r2 - k.r2min) * rinv * k.i2a;
+            const R om = (R)1 - rho, op = (R)1 + rho, w = om * om * ri3;
+            A = ov ? -k.a3 * w * fma(fma((R)9, rho, (R)2), rho, (R)1) : (R)0;
+            B = ov ? k.a2 * w * (op * op) * ri2 : (R)0;
+          } else {  // the two branches and their difference (fewer operations)
+            const R Af = fma(k.a3, ri3, rinv), Bf = ri3 * fma(-k.a2, ri2, (R)1);
+            const R Ao = fma(-k.ock9, (r2 - k.r2min) * rinv, k.oc), Bo = k.ob * rinv;
+            A = ov ? Ao - Af : (R)0;
+            B = ov ? Bo - Bf : (R)0;
+          }
 #pragma unroll
           for (int r = 0; r < NRC; ++r) {
             const R fx = fs[3 * r][s], fy = fs[3 * r + 1][s], fz = fs[3 * r + 2][s];
@@ -700,24 +718,26 @@ hipError_t run_p2p(const Launch& l, const Tiles& tiles, int nrc, const double* s
   return hipGetLastError();
 }
 
-// The overlap correction is a near/far correction sum: it runs in FP64 in
-// both precision forms (the mixed form keeps such sums in FP64).  Its
-// difference M_overlap - M_far cancels as r approaches 2a, where the two
-// branches meet.
-hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u) {
+// The overlap correction: FP32 pair arithmetic (the factored differences)
+// with FP64 sums per staged chunk in the mixed form, FP64 otherwise.
+hipError_t run_overlap(const Launch& l, const Tiles& tiles, int nrc, const double* sF, double* u, int mixed) {
   const Built* B = l.B;
   if (tiles.n == 0 || B->lists[LO].len == 0) return hipSuccess;
   if (nrc > NEAR_VEC_RHS) {  // launches of 8 right-hand sides, then the rest
-    const hipError_t he = run_overlap(l, tiles, NEAR_VEC_RHS, sF, u);
+    const hipError_t he = run_overlap(l, tiles, NEAR_VEC_RHS, sF, u, mixed);
     const int64_t off = (int64_t)NEAR_VEC_RHS * 3 * B->n;
-    return he != hipSuccess ? he : run_overlap(l, tiles, nrc - NEAR_VEC_RHS, sF + off, u + off);
+    return he != hipSuccess ? he : run_overlap(l, tiles, nrc - NEAR_VEC_RHS, sF + off, u + off, mixed);
   }
   const PairLaunch q = pair_launch(l.a, l.eta);
   const double four_a2 = 4.0 * l.a * l.a;
 #define OV_CASE(NR)                                                                                                 \
   case NR:                                                                                                          \
-    k_overlap<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], four_a2, B->sx,     \
-                                                     B->sy, B->sz, sF, B->n, q.kd, q.S, q.c1S, u);                  \
+    if (mixed)                                                                                                      \
+      k_overlap<NR, true><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], four_a2, B->sx,    \
+                                                      B->sy, B->sz, sF, B->n, q.kf, q.S, q.c1S, u);                 \
+    else                                                                                                            \
+      k_overlap<NR, false><<<tiles.n, P2P_T, 0, l.s>>>(tiles.t, tiles.box, B->tree, B->lists[LO], four_a2, B->sx,   \
+                                                       B->sy, B->sz, sF, B->n, q.kd, q.S, q.c1S, u);                \
     break;
   switch (nrc) {
     OV_CASE(1)
