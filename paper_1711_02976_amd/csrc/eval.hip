@@ -134,17 +134,20 @@ __global__ void __launch_bounds__(SETS_T) k_eval_sets(int p, bool mult, const in
   }
 }
 
-// Adds the 12 sets at D (m-major, nmax) evaluated at this lane's target,
-// offset (vx, vy, vz) from the expansion centre, box side h.  Harmonics:
+// Adds the 12 sets of ER right-hand sides (at D + q stride, m-major, nmax)
+// evaluated at this lane's target, offset (vx, vy, vz) from the expansion
+// centre, box side h, to vel[q].  The harmonics are formed once for the ER
+// right-hand sides:
 // S_n^m = (n-m)!(n+m)! R_n^m (local; the factor is folded into the sets) or
 // I_n^m (multipole), both by
 //   h_m^m = -(2m-1) (x' + i y') h_{m-1}^{m-1},  h_0^0 = s',
 //   h_n   = (2n-1) z' h_{n-1} - ((n-1)^2 - m^2) r' h_{n-2},
 // (x', y', z', r', s') = (x, y, z, r^2, 1) or (x/r^2, y/r^2, z/r^2, 1/r^2, 1/r)
-// in box units.
-template <bool MULT>
-__device__ inline void eval_sets(const double2* __restrict__ D, int nmax, double vx, double vy, double vz, double h,
-                                 double C1, double* vel) {
+// in box units.  Each right-hand side's sums run in the same order whatever
+// ER is.
+template <bool MULT, int ER>
+__device__ inline void eval_sets(const double2* __restrict__ D, int64_t stride, int nmax, double vx, double vy,
+                                 double vz, double h, double C1, double (*vel)[3]) {
   const double ih = 1.0 / h, x = vx * ih, y = vy * ih, z = vz * ih;
   const double r2 = x * x + y * y + z * z;
   double zz, rr, ux, uy, sc;
@@ -161,12 +164,16 @@ __device__ inline void eval_sets(const double2* __restrict__ D, int nmax, double
     uy = y;
     sc = 1.0;
   }
-  double s[12];
+  double s[ER][12];
 #pragma unroll
-  for (int e = 0; e < 12; ++e) s[e] = 0.0;
+  for (int q = 0; q < ER; ++q)
+#pragma unroll
+    for (int e = 0; e < 12; ++e) s[q][e] = 0.0;
   auto acc = [&](double2 hv, const double2* d) {
 #pragma unroll
-    for (int e = 0; e < 12; ++e) s[e] = fma(d[e].x, hv.x, fma(-d[e].y, hv.y, s[e]));
+    for (int q = 0; q < ER; ++q)
+#pragma unroll
+      for (int e = 0; e < 12; ++e) s[q][e] = fma(d[q * stride + e].x, hv.x, fma(-d[q * stride + e].y, hv.y, s[q][e]));
   };
   double2 dg = make_double2(sc, 0.0);
   const double2* Dp = D;
@@ -202,12 +209,19 @@ __device__ inline void eval_sets(const double2* __restrict__ D, int nmax, double
     }
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) vel[i] += s[i] - C1 * (vx * s[3 + 3 * i] + vy * s[4 + 3 * i] + vz * s[5 + 3 * i]);
+  for (int q = 0; q < ER; ++q)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      vel[q][i] += s[q][i] - C1 * (vx * s[q][3 + 3 * i] + vy * s[q][4 + 3 * i] + vz * s[q][5 + 3 * i]);
 }
 
 // One wave per tile (leaf box, first bead, count <= 64, leaf ordinal),
-// EV_WAVES consecutive tiles per block.
+// EV_WAVES consecutive tiles per block.  The evaluation shares the harmonics
+// of each expansion between EV_RHS right-hand sides (two: on cube-15M the
+// evaluation took 102 ms against 111 ms with one and 135 ms with four, where
+// the sums' registers cut the occupancy).
 constexpr int EV_WAVES = 4;
+constexpr int EV_RHS = 2;
 // Writes (assigns) the far-field velocity of every bead of the tile.
 template <int NRC>
 __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4* tiles, int ntiles, Tree t, List W,
@@ -229,15 +243,18 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_apply(int p, const int4*
   // all loads before the first store, so that the set arrays can be read
   // through the scalar cache
   double vel[NRC][3];
-  for (int r = 0; r < NRC; ++r) {
-    vel[r][0] = vel[r][1] = vel[r][2] = 0.0;
-    eval_sets<false>(DL + ((int64_t)tl.w * NRC + r) * T * 12, p, px - cx, py - cy, pz - cz, h, C1, vel[r]);
+  constexpr int ER = NRC < EV_RHS ? NRC : EV_RHS;
+  static_assert(NRC % ER == 0, "right-hand sides in whole groups of ER");
+  for (int r = 0; r < NRC; ++r) vel[r][0] = vel[r][1] = vel[r][2] = 0.0;
+  for (int r = 0; r < NRC; r += ER) {
+    eval_sets<false, ER>(DL + ((int64_t)tl.w * NRC + r) * T * 12, (int64_t)T * 12, p, px - cx, py - cy, pz - cz, h,
+                         C1, vel + r);
     for (int e = w0; e < w1; ++e) {
       const int C = W.ent[e];
       const int wi = widx[C];
       if (wi < 0) continue;  // few beads: summed directly with the near field
-      eval_sets<true>(DW + ((int64_t)wi * NRC + r) * To * 12, p + 2, px - t.cx[C], py - t.cy[C], pz - t.cz[C],
-                      t.h[C], C1, vel[r]);
+      eval_sets<true, ER>(DW + ((int64_t)wi * NRC + r) * To * 12, (int64_t)To * 12, p + 2, px - t.cx[C],
+                          py - t.cy[C], pz - t.cz[C], t.h[C], C1, vel + r);
     }
   }
   if (lane < tl.z)
@@ -421,8 +438,8 @@ __global__ void __launch_bounds__(64 * EV_WAVES) k_eval_poly_apply(int p, const 
       const int C = W.ent[e];
       const int wi = widx[C];
       if (wi < 0) continue;  // few beads: summed directly with the near field
-      eval_sets<true>(DW + ((int64_t)wi * NRC + r) * To * 12, p + 2, px - t.cx[C], py - t.cy[C], pz - t.cz[C],
-                      t.h[C], C1, vel[r]);
+      eval_sets<true, 1>(DW + ((int64_t)wi * NRC + r) * To * 12, 0, p + 2, px - t.cx[C], py - t.cy[C],
+                         pz - t.cz[C], t.h[C], C1, vel + r);
     }
   if (lane < tl.z)
 #pragma unroll
