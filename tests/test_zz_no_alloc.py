@@ -67,15 +67,17 @@ def test_noalloc_matches_matvec(orc):
         PB.free()
 
 
-def test_noalloc_matrix_core_group(orc):
-    # 20 right-hand sides in the mixed form: a near-field group of 16 on the
-    # matrix cores and one of 4 on the vector units, from the scratch; the
-    # workspace fits, so the grouping and the results equal rpy_matvec's
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_noalloc_matrix_core_group(orc, precision):
+    # 20 right-hand sides: in the mixed form a near-field group of 16 on the
+    # matrix cores and one of 4 on the vector units, in the FP64 form one
+    # launch of 16 + 4, from the scratch; the workspace fits, so the grouping
+    # and the results equal rpy_matvec's
     import paper_1711_02976_amd as R
     torch = torch_cuda()
     w = W.uniform_cube(6_000, 1.0, 0.01, nrhs=20, seed=134)
-    log(f"noalloc: n={w.n} nrhs={w.nrhs} mixed")
-    P = _plan(R, w, leaf_size=200, order=16, precision="mixed")
+    log(f"noalloc: n={w.n} nrhs={w.nrhs} {precision}")
+    P = _plan(R, w, leaf_size=200, order=16, precision=precision)
     try:
         F = to_dev(w.forces)
         ref = P.matvec(F).cpu().numpy()
