@@ -46,9 +46,10 @@ typedef enum {
 
 typedef enum {
   RPY_PREC_FP64 = 0,   /* every kernel in FP64 */
-  RPY_PREC_MIXED = 1   /* P2P, the direct W sums and M2L in FP32 (pair
-                          differences, expansion storage, the overlap
-                          correction and every sum across kernels in FP64) */
+  RPY_PREC_MIXED = 1   /* P2P, the direct W sums, the overlap correction's
+                          pair terms and M2L in FP32 (pair differences,
+                          expansion storage and every sum across kernels in
+                          FP64) */
 } rpy_precision;
 
 typedef struct {
