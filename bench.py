@@ -273,7 +273,9 @@ def run(args):
         precision) and for those on the vector units alone (against the
         vector peak, also by the vector kernel's own count);
         M2L flop/s of the rotation operator (20 S flops per V pair and
-        density) against the vector peak (no MFMA instruction is issued)."""
+        density) against the vector peak (no MFMA instruction is issued), in
+        the timed region (where it shares the GPU with the near field) and
+        alone (the isolated-phase matvec)."""
         tm = q["timings"]
         steps = max(args.steps, 1)
         L_p2p = tm["launches"]["p2p"] / steps
@@ -292,6 +294,7 @@ def run(args):
         f_p2p_kernel = pairs * (20 * L_vec + 18 * rhs_vec)
         peak_mc = PEAK_MFMA_FP32_TFLOPS if is_mixed else PEAK_MFMA_FP64_TFLOPS
         t_m2l = tm["ms"]["m2l"] / steps * 1e-3
+        t_m2l_alone = q["serial"]["ms"]["m2l"] * 1e-3 if q.get("serial") else 0.0
         f_m2l = npv * 4 * w.nrhs * 20 * S
         out = {"p2p": {"launches_per_matvec": L_p2p, "ms_per_matvec": round(t_p2p * 1e3, 4),
                        "avg_launch_ms": round(t_p2p * 1e3 / max(L_p2p, 1), 4),
@@ -316,6 +319,8 @@ def run(args):
                "m2l": {"ms_per_matvec": round(t_m2l * 1e3, 4), "v_pairs": npv, "flops_per_matvec": f_m2l,
                        "achieved_tflops": round(f_m2l / t_m2l / 1e12, 3) if t_m2l > 0 else None,
                        "frac": round(f_m2l / t_m2l / 1e12 / peak, 4) if t_m2l > 0 else None,
+                       "ms_alone": round(t_m2l_alone * 1e3, 4),
+                       "frac_alone": round(f_m2l / t_m2l_alone / 1e12 / peak, 4) if t_m2l_alone > 0 else None,
                        "peak_tflops": peak, "mfma_instructions": 0}}
         st = q["stats"]
         if st.get("bead_pass_ms", 0) > 0:
@@ -460,6 +465,36 @@ def copy_probe(mib):
     return 0
 
 
+def gemm_probe(cols, p=16):
+    """The dense alternative to the rotation M->L as a library GEMM: one
+    offset's real-split operator [2T x 2T] (T = (p+1)(p+2)/2) applied to
+    `cols` gathered (source, density) columns, through torch.matmul
+    (hipBLASLt), in FP32 and in BF16.  Prints the rates (HIP events, median
+    of 10 after 3 warm-ups)."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    k = (p + 1) * (p + 2)
+    out = {"gemm_probe": f"[{k}x{k}] x [{k}x{cols}]", "order": p}
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.randn(k, k, device="cuda:0").to(dt)
+        b = torch.randn(k, cols, device="cuda:0").to(dt)
+        for _ in range(3):
+            c = a @ b
+        ts = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            c = a @ b
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        out[name] = {"ms": round(ms, 4), "tflops": round(2.0 * k * k * cols / (ms * 1e-3) / 1e12, 2)}
+        del a, b, c
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,6 +519,9 @@ def main():
                     help="also time the oracle's FMM (same order and leaf size) on the first SYSTEMS systems")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device three times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--gemm-probe", type=int, default=0, metavar="COLS",
+                    help="only time the dense M->L operator of one offset (p = 16) as a library GEMM on COLS "
+                         "columns, FP32 and BF16, then exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="turn four rocprofv3 --pmc output folders (FETCH_SIZE and WRITE_SIZE of a benchmark run "
                          "and of a --copy-probe run of the size given by --copy-probe) into "
@@ -496,6 +534,8 @@ def main():
         return pmc_summary(args)
     if args.copy_probe > 0:
         return copy_probe(args.copy_probe)
+    if args.gemm_probe > 0:
+        return gemm_probe(args.gemm_probe)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
