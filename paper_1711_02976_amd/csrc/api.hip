@@ -210,7 +210,6 @@ struct rpy_plan_s {
   int wd = 0;         // W-list boxes of at most wd beads are summed directly (< 0: none)
   int eval_mode = 0;  // rpy::EVAL_SETS or rpy::EVAL_POLY
   int inject = -1;    // phase at which the next pass reports a HIP error (tests)
-  int near_max = rpy::NEAR_MAX_RHS;  // right-hand sides per near-field launch (at most)
   int tuned = 0, tune_hit = 0;       // autotuned; choice taken from the cache
   double tune_err = 0.0;             // measured error of the tuned choice
   int device = 0;     // device current when the plan was built
@@ -970,7 +969,7 @@ rpy_status rpy_matvec(rpy_plan_t* P, int32_t nrhs, const double* forces, double*
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;  // the high-order kernels take one right-hand side
   while (nrc > 1 && 2.0 * P->B.tree.nbox * 4.0 * nrc * T * 16.0 > 64e9) nrc /= 2;
   // near-field groups: 16 (matrix cores) or up to 8 right-hand sides share each pair's geometry
-  const int nrn = std::max(nrc, std::min(near_group_max(nrhs, P->precision == RPY_PREC_MIXED), P->near_max));
+  const int nrn = std::max(nrc, near_group_max(nrhs, P->precision == RPY_PREC_MIXED));
   if (alloc_ws(P, nrc, nrn) != 0) return fail(RPY_ENOMEM, "cannot allocate the matvec workspace");
   rpy::Launch l{&P->B, &P->tb, P->p, P->a, P->eta, P->stream, P->wd};
   const int mixed = P->precision == RPY_PREC_MIXED;
@@ -1000,7 +999,7 @@ rpy_status rpy_matvec_noalloc(rpy_plan_t* P, int32_t nrhs, const double* forces,
   // rpy_matvec, halved until the workspace fits the fixed scratch
   int nrc = nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1);
   if (P->p > rpy::MAX_ORDER_MULTI) nrc = 1;
-  int nrn = std::max(nrc, std::min(near_group_max(nrhs, P->precision == RPY_PREC_MIXED), P->near_max));
+  int nrn = std::max(nrc, near_group_max(nrhs, P->precision == RPY_PREC_MIXED));
   size_t sz[WS_N], tot = 0;
   for (;;) {
     ws_sizes(P, nrc, nrn, sz);
