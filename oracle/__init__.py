@@ -39,9 +39,13 @@ _up = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+        # RPY_ORACLE_LIB: another build of rpy_oracle.c (the sanitizer test's)
+        path = os.environ.get("RPY_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = C.CDLL(path)
         L.orc_rpy_block.argtypes = [_dp, C.c_double, C.c_double, _dp]
         L.orc_rpy_direct.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, C.c_double,
                                      C.c_int64, C.c_void_p, _dp, C.c_int]
