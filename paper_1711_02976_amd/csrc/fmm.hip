@@ -443,107 +443,112 @@ hipError_t unpermute_velocities(const Launch& l, const double* u, const double* 
 // M_n^m(P) = sum_{k<=n,l} 2^-k M_k^l(C) conj(R_{n-k}^{m-l}(d/h_P)).
 constexpr int TR_T = 256;
 
-// One block per (parent box, density): thread t = output (n,m), summing the
-// children's translated multipoles in turn (Rt and the child's density
-// staged in LDS; the fourth density re-centred on the child first).
+// One block per (parent box, right-hand side): thread t = output (n,m) of
+// the four densities of that right-hand side, summing the children's
+// translated multipoles in turn (Rt and the child's four densities staged in
+// LDS, the fourth re-centred on the child first); each Rt entry read serves
+// the four densities.
 template <int ND>
 __global__ void __launch_bounds__(TR_T) k_m2m(int p, int ls, Tree t, const double2* oct, double2* M) {
-  const int b = ls + blockIdx.x, d = blockIdx.y;
+  const int b = ls + blockIdx.x, d0 = 4 * blockIdx.y;
   const int nc = t.nchild[b];
   if (nc == 0) return;
   const int T = ncoef(p), F1 = (p + 1) * (p + 1);
   extern __shared__ double2 sm[];
-  double2* Rt = sm;        // F1
-  double2* Mc = sm + F1;   // F1
+  double2* Rt = sm;       // F1
+  double2* Mc = sm + F1;  // [4][F1]
   // outputs threadIdx.x and threadIdx.x + TR_T (T exceeds TR_T above order 21)
-  double2 acc[2] = {make_double2(0, 0), make_double2(0, 0)};
+  double2 acc[2][4];
   int nq[2] = {0, 0}, mq[2] = {0, 0};
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[q][g] = make_double2(0, 0);
     const int c = threadIdx.x + q * TR_T;
     if (c < T) {
       while (tri(nq[q] + 1) <= c) ++nq[q];
       mq[q] = c - tri(nq[q]);
     }
   }
-  const int dd = d & 3, base = d - dd;
   for (int C = t.child[b]; C < t.child[b] + nc; ++C) {
     const int o = (t.ax[C] & 1) | ((t.ay[C] & 1) << 1) | ((t.az[C] & 1) << 2);
     const double w[3] = {t.cx[C] - t.cx[b], t.cy[C] - t.cy[b], t.cz[C] - t.cz[b]};
     __syncthreads();
     for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
-    const double2* src = M + (int64_t)C * ND * T;
+    const double2* src = M + ((int64_t)C * ND + d0) * T;
     for (int f = threadIdx.x; f < F1; f += TR_T) {
       int k = (int)sqrt((double)f);
       while (k * k > f) --k;
       while ((k + 1) * (k + 1) <= f) ++k;
       const int l = f - k * k - k;
-      double2 v = getc(src + d * T, k, l, p);
-      if (dd == 3)
-        for (int c = 0; c < 3; ++c) {
-          const double2 u = getc(src + (base + c) * T, k, l, p);
-          v.x += w[c] * u.x;
-          v.y += w[c] * u.y;
-        }
       const double sc = ldexp(1.0, -k);
-      Mc[f] = make_double2(v.x * sc, v.y * sc);
+      double2 v[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) v[g] = getc(src + g * T, k, l, p);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v[3].x += w[c] * v[c].x;
+        v[3].y += w[c] * v[c].y;
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) Mc[g * F1 + f] = make_double2(v[g].x * sc, v[g].y * sc);
     }
     __syncthreads();
     for (int q = 0; q < 2; ++q) {
       if (threadIdx.x + q * TR_T >= T) break;
       const int n = nq[q], m = mq[q];
-      // four independent partial sums keep several LDS reads in flight
-      double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
       for (int k = 0; k <= n; ++k) {
         const int j = n - k;
         const int lmin = max(-k, m - j), lmax = min(k, m + j);
         const int mk = fidx(k, 0), rj = fidx(j, m);  // rj - l >= j*j for l <= lmax
-        int l = lmin;
-        for (; l + 3 <= lmax; l += 4) {
+        for (int l = lmin; l <= lmax; ++l) {
+          const double2 r = Rt[rj - l];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) cfmac(a4[u], Mc[mk + l + u], Rt[rj - (l + u)]);
+          for (int g = 0; g < 4; ++g) cfmac(acc[q][g], Mc[g * F1 + mk + l], r);
         }
-        for (; l <= lmax; ++l) cfmac(a4[0], Mc[mk + l], Rt[rj - l]);
       }
-      acc[q].x += (a4[0].x + a4[1].x) + (a4[2].x + a4[3].x);
-      acc[q].y += (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y);
     }
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q)
-    if (threadIdx.x + q * TR_T < T) M[(int64_t)b * ND * T + d * T + threadIdx.x + q * TR_T] = acc[q];
+    if (threadIdx.x + q * TR_T < T)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) M[((int64_t)b * ND + d0 + g) * T + threadIdx.x + q * TR_T] = acc[q][g];
 }
 
 // ------------------------------------------------------------------ L->L --
-// One block per child box of one level; thread t = output (k,l):
-// L_k^l(C) += 2^-(k+1) sum_{n>=k,m} L_n^m(P) R_{n-k}^{m-l}(d/h_P).
+// One block per (child box of one level, right-hand side); thread t =
+// output (k,l) of the four densities:
+// L_k^l(C) += 2^-(k+1) sum_{n>=k,m} L_n^m(P) R_{n-k}^{m-l}(d/h_P),
+// each Rt entry read serving the four densities.
 template <int ND>
 __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const double2* oct, double2* L) {
-  const int b = ls + blockIdx.x, d = blockIdx.y;
+  const int b = ls + blockIdx.x, d0 = 4 * blockIdx.y;
   const int P = t.parent[b];
   if (P < 0) return;
   const int T = ncoef(p), F1 = (p + 1) * (p + 1);
   extern __shared__ double2 sm[];
-  double2* Rt = sm;        // F1
-  double2* Lp = sm + F1;   // F1
+  double2* Rt = sm;       // F1
+  double2* Lp = sm + F1;  // [4][F1]
   const int o = (t.ax[b] & 1) | ((t.ay[b] & 1) << 1) | ((t.az[b] & 1) << 2);
   const double w[3] = {t.cx[P] - t.cx[b], t.cy[P] - t.cy[b], t.cz[P] - t.cz[b]};
   for (int i = threadIdx.x; i < F1; i += TR_T) Rt[i] = oct[(int64_t)o * F1 + i];
-  const double2* src = L + (int64_t)P * ND * T;
-  const int dd = d & 3, base = d - dd;
+  const double2* src = L + ((int64_t)P * ND + d0) * T;
   for (int f = threadIdx.x; f < F1; f += TR_T) {
     int k = (int)sqrt((double)f);
     while (k * k > f) --k;
     while ((k + 1) * (k + 1) <= f) ++k;
     const int l = f - k * k - k;
-    double2 v = getc(src + d * T, k, l, p);
-    if (dd == 3)
-      for (int c = 0; c < 3; ++c) {
-        const double2 u = getc(src + (base + c) * T, k, l, p);
-        v.x += w[c] * u.x;
-        v.y += w[c] * u.y;
-      }
-    Lp[f] = v;
+    double2 v[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) v[g] = getc(src + g * T, k, l, p);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[3].x += w[c] * v[c].x;
+      v[3].y += w[c] * v[c].y;
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) Lp[g * F1 + f] = v[g];
   }
   __syncthreads();
   // outputs threadIdx.x and threadIdx.x + TR_T (T exceeds TR_T above order 21)
@@ -551,25 +556,26 @@ __global__ void __launch_bounds__(TR_T) k_l2l(int p, int ls, Tree t, const doubl
     int k = 0;
     while (tri(k + 1) <= c) ++k;
     const int l = c - tri(k);
-    // four independent partial sums keep several LDS reads in flight
-    double2 a4[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    double2 acc[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[g] = make_double2(0, 0);
     for (int n = k; n <= p; ++n) {
       const int j = n - k;
       const int mmin = max(-n, l - j), mmax = min(n, l + j);
       const int ln = fidx(n, 0), rj = fidx(j, -l);  // rj + m >= j*j for m >= mmin
-      int m = mmin;
-      for (; m + 3 <= mmax; m += 4) {
+      for (int m = mmin; m <= mmax; ++m) {
+        const double2 r = Rt[rj + m];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) cfma(a4[q], Lp[ln + m + q], Rt[rj + m + q]);
+        for (int g = 0; g < 4; ++g) cfma(acc[g], Lp[g * F1 + ln + m], r);
       }
-      for (; m <= mmax; ++m) cfma(a4[0], Lp[ln + m], Rt[rj + m]);
     }
-    const double2 acc =
-        make_double2((a4[0].x + a4[1].x) + (a4[2].x + a4[3].x), (a4[0].y + a4[1].y) + (a4[2].y + a4[3].y));
     const double sc = ldexp(1.0, -(k + 1));
-    double2* out = L + (int64_t)b * ND * T + d * T + c;
-    const double2 v = *out;
-    *out = make_double2(v.x + sc * acc.x, v.y + sc * acc.y);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      double2* out = L + ((int64_t)b * ND + d0 + g) * T + c;
+      const double2 v = *out;
+      *out = make_double2(v.x + sc * acc[g].x, v.y + sc * acc[g].y);
+    }
   }
 }
 
@@ -651,13 +657,13 @@ __global__ void __launch_bounds__(M2L_T) k_m2l_dense(int p, int c0, Tree t, List
 
 hipError_t run_m2m(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
-  const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
+  const size_t shm = sizeof(double2) * 5 * (l.p + 1) * (l.p + 1);
   // parents down to level 2 only: multipoles at levels 0 and 1 are never
   // read (V lists start at level 2, and W-list boxes are descendants of a
   // leaf's colleagues, so they sit at level 2 or deeper)
   for (int lev = B->depth - 1; lev >= 2; --lev) {
     const int ls = B->level_start[lev], le = B->level_start[lev + 1];
-    DISPATCH_ND(nrc, (k_m2m<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
+    DISPATCH_ND(nrc, (k_m2m<ND><<<dim3(le - ls, ND / 4), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.M)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -687,12 +693,12 @@ hipError_t run_m2l(const Launch& l, int nrc, Exp e) {
 
 hipError_t run_l2l(const Launch& l, int nrc, Exp e) {
   const Built* B = l.B;
-  const size_t shm = sizeof(double2) * 2 * (l.p + 1) * (l.p + 1);
+  const size_t shm = sizeof(double2) * 5 * (l.p + 1) * (l.p + 1);
   // children from level 3: local expansions at levels 0 and 1 are zero (no
   // V or X entries there), so level 2 keeps what M->L and S->L wrote
   for (int lev = 3; lev <= B->depth; ++lev) {
     const int ls = B->level_start[lev], le = B->level_start[lev + 1];
-    DISPATCH_ND(nrc, (k_l2l<ND><<<dim3(le - ls, ND), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
+    DISPATCH_ND(nrc, (k_l2l<ND><<<dim3(le - ls, ND / 4), TR_T, shm, l.s>>>(l.p, ls, B->tree, l.tb->oct, e.L)));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
