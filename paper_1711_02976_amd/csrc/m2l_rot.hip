@@ -57,17 +57,19 @@ struct RotSched {
   unsigned char nord[RW];
 };
 
-// Per-column data of a batch, in LDS (structure of arrays, one slot per lane).
+// Per-column data of a batch, in LDS (structure of arrays, one slot per lane),
+// in the kernel's precision.
+template <class R>
 struct ColData {
-  int* src;      // source box, -1 for an empty column
-  double* e1x;   // e^{-i(pi/2 - phi)}
-  double* e1y;
-  double* e2x;   // e^{i theta}
-  double* e2y;
-  double* rinv;  // 1/rho (box units)
-  double* wx;    // source centre - target centre (re-centres the fourth density)
-  double* wy;
-  double* wz;
+  int* src;  // source box, -1 for an empty column
+  R* e1x;    // e^{-i(pi/2 - phi)}
+  R* e1y;
+  R* e2x;    // e^{i theta}
+  R* e2y;
+  R* rinv;   // 1/rho (box units)
+  R* wx;     // source centre - target centre (re-centres the fourth density)
+  R* wy;
+  R* wz;
 };
 
 __host__ __device__ constexpr int rot_block(int n) { return n * (n + 1) * (2 * n + 1) / 6; }  // sum_{j<n} (j+1)^2
@@ -149,7 +151,7 @@ __device__ inline void load_col(const typename Cx<R>::T* col, int ld, R* xr, R* 
 // X, scaled to the paper's normalisation): Phi(pi/2 - phi), R, Phi(-theta),
 // S R S.
 template <int N, class R>
-__device__ void first_half(int c, int ld, const ColData& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
+__device__ void first_half(int c, int ld, const ColData<R>& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
   using C = typename Cx<R>::T;
   constexpr int K = N + 1, t0 = N * (N + 1) / 2;
   constexpr int SG = (N & 1) ? -1 : 1;
@@ -175,7 +177,7 @@ __device__ void first_half(int c, int ld, const ColData& cd, const R* __restrict
 
 // Phase 2: z translation of order l (KK = p - l + 1 degrees) of column c.
 template <int KK, class R>
-__device__ void ztrans(int l, int c, int ld, const ColData& cd, const R* __restrict__ H, typename Cx<R>::T* X) {
+__device__ void ztrans(int l, int c, int ld, const ColData<R>& cd, const R* __restrict__ H, typename Cx<R>::T* X) {
   using C = typename Cx<R>::T;
   const R ri = (R)cd.rinv[c];
   R s = 1;
@@ -211,7 +213,7 @@ __device__ void ztrans(int l, int c, int ld, const ColData& cd, const R* __restr
 
 // Phase 3 for degree N of column c: R, Phi(theta), S R S, Phi(phi - pi/2).
 template <int N, class R>
-__device__ void second_half(int c, int ld, const ColData& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
+__device__ void second_half(int c, int ld, const ColData<R>& cd, const R* __restrict__ A, typename Cx<R>::T* X) {
   using C = typename Cx<R>::T;
   constexpr int K = N + 1, t0 = N * (N + 1) / 2;
   constexpr int SG = (N & 1) ? -1 : 1;
@@ -253,9 +255,9 @@ __global__ void __launch_bounds__(RT, MINW) k_m2l_rot(int p, int nc, int nd_all,
   if (b < 0) return;  // whole block, before any barrier
   const int d0 = ND * blockIdx.y;
   C* X = reinterpret_cast<C*>(smem);
-  ColData cd;
+  ColData<R> cd;
   {
-    double* dq = reinterpret_cast<double*>(X + (size_t)T * ld);
+    R* dq = reinterpret_cast<R*>(X + (size_t)T * ld);
     cd.e1x = dq; dq += nc;
     cd.e1y = dq; dq += nc;
     cd.e2x = dq; dq += nc;
@@ -458,7 +460,7 @@ static RotSched make_sched(int p) {
 }
 
 static size_t rot_smem_bytes(int p, int nc, size_t real) {
-  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * sizeof(double) + sizeof(int));
+  return (size_t)ncoef(p) * (nc + 1) * 2 * real + (size_t)nc * (8 * real + sizeof(int));
 }
 
 // ND densities per block, nsplit blocks per target box (nsplit ND densities
@@ -513,12 +515,12 @@ static hipError_t launch_rot(const Launch& l, int nrc, Exp e, const R* rot, cons
     const hipError_t he = hipGetLastError();
     if (he != hipSuccess) return he;
   }
-  // 64 columns per batch, halved while the LDS (160 KB per CU) cannot hold
-  // them.  Up to degree 16 in FP32, 60 columns let two blocks share a CU
-  // (registers are then capped for four waves per SIMD); each block then
-  // takes the four densities of one right-hand side.
+  // 64 columns per batch (one per lane), halved while the LDS (160 KB per CU)
+  // cannot hold them.  Up to degree 16 in FP32 two blocks share a CU (80 KB
+  // each; registers are then capped for four waves per SIMD); each block
+  // then takes the four densities of one right-hand side.
   const bool lo = p <= 16, two = lo && sizeof(R) == 4;
-  int nc = two ? 60 : 64;
+  int nc = 64;
   while (nc > 8 && rot_smem_bytes(p, nc, sizeof(R)) > 160 * 1024) nc /= 2;
   const size_t shm = rot_smem_bytes(p, nc, sizeof(R));
   if (shm > 160 * 1024) return hipErrorInvalidValue;

@@ -126,7 +126,7 @@ def test_fmm_fp64_matches_oracle_fmm(orc, case):
 # Leaves of several hundred beads, as the library's own leaf-size choice
 # makes them on the benchmark workloads: P2P tiles of 128 beads and
 # evaluation tiles of 64 beads span several tiles per leaf, the M->L runs in
-# batches of 60-64 columns with the deepest level on its own stream, and on
+# batches of 64 columns with the deepest level on its own stream, and on
 # clustered beads the W, X and O lists are non-empty and some boxes' S->L
 # work is split over several work items.
 def _large_leaf_cases():
