@@ -293,8 +293,14 @@ rpy_status rpy_plan_timings(rpy_plan_t* plan, rpy_timings_t* out);
  * error at `phase` (an rpy_phase) instead of issuing that phase, exactly as
  * a failed launch would: rpy_matvec returns RPY_EDEVICE, nothing after the
  * failed phase is issued, and the plan is in the sticky error state.
- * phase = -1 clears a pending injection.  Returns RPY_EINVAL for other
- * values.  No kernel is made to fail on the device. */
+ * phase = RPY_INJECT_ALLOC instead makes the plan's next matvec-workspace
+ * allocation fail part-way, as a failed hipMalloc would: rpy_matvec frees
+ * what it had allocated and returns RPY_ENOMEM before issuing any work, the
+ * velocities are not written, and the plan stays usable (the next call
+ * allocates again).  A call that needs no new workspace leaves the injection
+ * pending.  phase = -1 clears a pending injection.  Returns RPY_EINVAL for
+ * other values.  No kernel is made to fail on the device. */
+#define RPY_INJECT_ALLOC 100
 rpy_status rpy_plan_inject_error(rpy_plan_t* plan, int32_t phase);
 
 /* Release a plan and its device memory; NULL is a no-op.  Waits for the

@@ -27,6 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librpyfmm.so")
 
 RPY_OK, RPY_EINVAL, RPY_ENONFINITE, RPY_ENOMEM, RPY_EDEVICE, RPY_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+RPY_INJECT_ALLOC = 100  # rpy_plan_inject_error: fail the next matvec-workspace allocation
 PREC_FP64, PREC_MIXED = 0, 1
 LIST_NAMES = ("U", "V", "W", "X", "O")
 
@@ -315,11 +316,14 @@ class Plan:
 
     def inject_error(self, phase):
         """Failure-path testing: the next matvec pass reports a HIP error at
-        `phase` (a name from PHASES or its index; -1 clears)."""
-        if isinstance(phase, str):
+        `phase` (a name from PHASES or its index; -1 clears), or with
+        phase "alloc" the next matvec-workspace allocation fails."""
+        if phase == "alloc":
+            phase = RPY_INJECT_ALLOC
+        elif isinstance(phase, str):
             phase = PHASES.index(phase)
-        if not -1 <= int(phase) < len(PHASES):
-            raise ValueError(f"phase must be -1 or one of {PHASES}")
+        if not (-1 <= int(phase) < len(PHASES) or phase == RPY_INJECT_ALLOC):
+            raise ValueError(f"phase must be -1, 'alloc' or one of {PHASES}")
         rpy_plan_inject_error(self.handle, phase)
 
     def free(self):

@@ -336,8 +336,12 @@ static int alloc_ws(rpy_plan_t* P, int nrc, int nrn) {
                       (void**)&w.Q, (void**)&w.DL, (void**)&w.DW, (void**)&w.XP, (void**)&w.PV,
                       (void**)&w.M32};
   int64_t tot = 0;
+  // an injected allocation failure (rpy_plan_inject_error) hits half-way,
+  // after some arrays are allocated, like a device that runs out of memory
+  const int fail_at = P->inject == RPY_INJECT_ALLOC ? WS_N / 2 : WS_N;
+  if (fail_at < WS_N) P->inject = -1;
   for (int k = 0; k < WS_N; ++k) {
-    if (hipMalloc(dst[k], sz[k]) != hipSuccess) {
+    if (k == fail_at || hipMalloc(dst[k], sz[k]) != hipSuccess) {
       (void)hipGetLastError();
       *dst[k] = nullptr;
       free_ws(P);
@@ -1247,7 +1251,8 @@ rpy_status rpy_plan_stats(const rpy_plan_t* P, rpy_plan_stats_t* out) {
 
 rpy_status rpy_plan_inject_error(rpy_plan_t* P, int32_t phase) {
   if (!P) return fail(RPY_EINVAL, "plan is NULL");
-  if (phase < -1 || phase >= RPY_NPHASE) return fail(RPY_EINVAL, "phase must be -1 or a rpy_phase");
+  if ((phase < -1 || phase >= RPY_NPHASE) && phase != RPY_INJECT_ALLOC)
+    return fail(RPY_EINVAL, "phase must be -1, a rpy_phase or RPY_INJECT_ALLOC");
   P->inject = phase;
   return RPY_OK;
 }

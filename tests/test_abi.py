@@ -72,6 +72,7 @@ def test_host_validation_without_gpu():
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
     assert b"w_direct" in L.rpy_last_error()
     assert L.rpy_plan_inject_error(None, 0) == R.RPY_EINVAL
+    assert L.rpy_plan_inject_error(None, R.RPY_INJECT_ALLOC) == R.RPY_EINVAL
     o = R.make_options(tune=2)
     assert L.rpy_plan(C.byref(h), 10, C.c_void_p(8), 0.5, 1.0, 1e-6, C.byref(o)) == R.RPY_EINVAL
     assert b"tune" in L.rpy_last_error()

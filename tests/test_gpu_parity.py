@@ -487,6 +487,44 @@ def test_failed_phase_makes_the_plan_sticky(orc, phase):
         Q.free()
 
 
+def test_failed_workspace_allocation_leaves_the_plan_usable(orc):
+    """An allocation failure of the matvec workspace (forced from the host,
+    half-way through its arrays) returns RPY_ENOMEM before any work is
+    issued and leaves the velocities unwritten; the plan stays usable and
+    its next call gives what a plan that never failed gives.  A call that
+    needs no new workspace leaves the injection pending."""
+    import ctypes as C
+    import paper_1711_02976_amd as R
+    torch = torch_cuda()
+    w = W.uniform_cube(3000, 1.0, 0.01, nrhs=4, seed=122)
+    log("injected workspace allocation failure")
+    P = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6, leaf_size=40)
+    Q = R.Plan(to_dev(w.pos), w.a, w.eta, 1e-6, leaf_size=40)
+    try:
+        F = to_dev(w.forces)
+
+        def raw(nrhs, U):
+            return R.lib().rpy_matvec(P.handle, nrhs, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()))
+
+        U1 = torch.empty_like(F[:1])
+        assert raw(1, U1) == R.RPY_OK  # workspace for one right-hand side
+        P.inject_error("alloc")
+        assert raw(1, U1) == R.RPY_OK  # no new workspace needed: still pending
+        U4 = torch.full_like(F, float("nan"))
+        assert raw(4, U4) == R.RPY_ENOMEM
+        assert b"workspace" in R.lib().rpy_last_error()
+        torch.cuda.synchronize()
+        assert torch.isnan(U4).all()
+        assert raw(4, U4) == R.RPY_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(U4.cpu().numpy(), Q.matvec(F).cpu().numpy())
+        # one right-hand side alone runs other kernels than a pass of four
+        assert orc.rel_l2(U1.cpu().numpy(), U4[:1].cpu().numpy()) <= 1e-13
+    finally:
+        P.free()
+        Q.free()
+
+
 def test_fullsize_cube_1M_sampled(orc):
     """1,000,000 beads, cube side 100, a = 0.5: FP64 FMM at eps = 1e-6 against
     the direct sum on 2,000 sampled targets."""
