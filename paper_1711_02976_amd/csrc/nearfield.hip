@@ -147,8 +147,11 @@ __device__ inline double rinv_of(double r2) {
 // Positions enter the pair arithmetic relative to the target leaf's centre
 // (differences taken in FP64, scaled by S and rounded once); in the mixed
 // form the pair arithmetic and per-source-leaf sums run in FP32.
+// The FP32 launch of 4 right-hand sides (the rest of 20 after the
+// matrix-core group) is held to 96 registers, five waves per SIMD instead of
+// four (two registers spill; 192 instead of 196 ms on cube-15M).
 template <int NRC, bool MIXED>
-__global__ void __launch_bounds__(P2P_T) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
+__global__ void __launch_bounds__(P2P_T, (NRC == 4 && MIXED) ? 5 : 1) k_p2p(const int4* tiles, Tree t, List U, const double* sx,
                                                const double* sy, const double* sz, const double* sF, int64_t n,
                                                PairK<typename std::conditional<MIXED, float, double>::type> k,
                                                double S, double c1, double* u) {
