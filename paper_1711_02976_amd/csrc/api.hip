@@ -157,7 +157,11 @@ static int model_tree(const rpy::Built& B, int order, double eps, bool mixed, in
   const double c_pair = mixed ? 0.53e-3 : 0.98e-3;  // per padded pair, one right-hand side
   // the FP32 rotation M2L up to p = 16 fits two blocks per CU; the FP64 one
   // above p = 16 takes 32 columns per batch
-  double c_v = p > 16 ? 2.55 * S / S21 : 0.94 * S / S16;
+  // up to p = 16 the M->L per (V pair, density) is affine in S: a part
+  // that does not shrink with the order (gathers, phases, column sums,
+  // barriers) equal to 655 units of S (cube-15M, FP32: 0.70 ns at p = 16,
+  // 0.25 ns at p = 7)
+  double c_v = p > 16 ? 2.55 * S / S21 : 0.94 * (655.0 + S) / (655.0 + S16);
   if (!mixed) c_v *= p > 16 ? 2.15 : 1.65;
   const double c_box = 30.0 * (T / T21) * (T / T21);
   const double c_leaf = 27.0 * T / T21;
